@@ -1,0 +1,184 @@
+/*
+ * fnls.h -- C ABI of libfnls: tau-preconditioned GMRES for the linear systems
+ * of the Riesz fractional nonlinear Schroedinger time stepper, on one AMD
+ * MI355X (gfx950).
+ *
+ * Problem (Sec. 2 of arXiv 2410.03643, "the discrete linear systems"):
+ * at every time level solve
+ *
+ *     (D - T_d + i I) u = b,
+ *
+ * where T_d = sum over the d axes of T_1 = mu T_0 applied along that axis
+ * (Kronecker sum, Sec. 2.2), T_0 the symmetric Toeplitz matrix of the
+ * fractional centred-difference coefficients c_k (Sec. 2.1),
+ * mu = dt / h^alpha, and D = rho dt |u^n|^2 (+ dt V) the real diagonal.
+ *
+ * Method: GMRES, right-preconditioned by the sine-transform TBAN
+ * preconditioner of Sec. 4 (its parameter omega, 1 by default) written in
+ * complex form,
+ *
+ *     z = -2 i omega ((omega+1) - i D)^{-1} . S_d (omega + i Lambda_d)^{-1} . S_d r,
+ *
+ * where S_d is the d-fold orthonormal sine transform (DST-I) and Lambda_d the
+ * Kronecker sum of the eigenvalues of the tau matrix tau(T_1) (Sec. 4).
+ * Zero initial guess, relative-residual stopping test (Sec. 5 protocol).
+ *
+ * Conventions (all entry points)
+ * ------------------------------
+ * - Grid: n interior points per axis, n + 1 a power of two, 1 <= n <= 1023,
+ *   d in {1, 2, 3}; h = (b - a)/(n + 1) is the spacing (Sec. 2.1).
+ * - Vectors: device pointers to N = n^d complex values, C order over
+ *   (n,)*d with the LAST axis the fastest (x_1), i.e. the column-stacking
+ *   vec() of Sec. 2.2.  fnls_c128 is layout-compatible with torch.complex128
+ *   and with double[2].  All vectors are owned by the caller and must stay
+ *   valid until the context's stream has executed the call.  Input vectors
+ *   must not alias output vectors unless stated otherwise.
+ * - Workspace: one caller-owned device block of at least
+ *   fnls_workspace_bytes(d, n, restart) bytes, passed to fnls_assemble; the
+ *   library keeps its tables, the diagonal, the Krylov basis and all
+ *   temporaries there.  The library allocates no device memory; it owns the
+ *   context struct and a small pinned host buffer for status words.
+ * - Streams: every call enqueues its kernels on the context's HIP stream.
+ *   fnls_solve / fnls_step / fnls_first_step return when the result is
+ *   complete (they wait on that stream to make convergence decisions);
+ *   fnls_rhs / fnls_apply_A / fnls_apply_precond / fnls_precond_setup return
+ *   immediately (stream-ordered).
+ * - Errors: functions return an fnls_status.  Argument errors are detected on
+ *   the host before any GPU work and leave the context unchanged.  No C++
+ *   exception crosses the ABI.  fnls_last_error() gives a message.
+ * - Threading: a context is not thread-safe; use one context per stream.
+ */
+#ifndef FNLS_H
+#define FNLS_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fnls_ctx fnls_ctx;
+
+/* One complex double: re, im (torch.complex128 element). */
+typedef struct { double re, im; } fnls_c128;
+
+typedef enum {
+    FNLS_OK = 0,
+    FNLS_NOT_CONVERGED = 1,     /* result written; info says how far it got    */
+    FNLS_ERR_INVALID_ARG = -1,  /* bad size / parameter / NULL pointer          */
+    FNLS_ERR_STATE = -2,        /* call order (e.g. solve before precond_setup) */
+    FNLS_ERR_WORKSPACE = -3,    /* workspace missing or too small               */
+    FNLS_ERR_NONFINITE = -4,    /* NaN / Inf in b (detected by the first norm)  */
+    FNLS_ERR_HIP = -5,          /* a HIP runtime call failed                    */
+    FNLS_ERR_NO_DEVICE = -6     /* no usable GPU                                */
+} fnls_status;
+
+typedef enum {
+    FNLS_FP64 = 0,     /* everything in FP64 / complex128                                */
+    FNLS_FP32_IR = 1   /* GMRES-IR: FP32 (complex64) transforms, matvec and basis inside
+                          an FP64 refinement loop; dots, Hessenberg, x, b and the outer
+                          residual in FP64                                               */
+} fnls_precision;
+
+/* Solver options.  Fill with fnls_default_opts() and override fields. */
+typedef struct {
+    double tol;        /* relative residual ||b - A x|| / ||b|| to reach (default 1e-10) */
+    int restart;       /* GMRES restart length m (default 30; <= workspace capacity)     */
+    int maxit;         /* total GMRES iterations allowed (default 2000, Sec. 5)          */
+    int precision;     /* fnls_precision (default FNLS_FP64)                             */
+    double inner_tol;  /* FNLS_FP32_IR: inner relative tolerance (default 1e-5)          */
+    int max_outer;     /* FNLS_FP32_IR: maximum refinement steps (default 20)            */
+    int fixed_iters;   /* > 0: run exactly this many iterations, no tolerance test (FP64) */
+    int lookahead;     /* iterations enqueued ahead of the host's convergence check
+                          (0 = synchronise every iteration; default 1)                   */
+    int reserved[4];
+} fnls_opts;
+
+/* Result of a solve.  relres_hist[k] is the GMRES estimate |g_{k+1}|/||b||
+ * after total iteration k (FP64 path; inner estimates for FP32_IR), for
+ * k < min(iters, 64). */
+typedef struct {
+    int iters;          /* total (inner) GMRES iterations                       */
+    int outer_iters;    /* refinement steps (FP32_IR) or GMRES cycles (FP64)    */
+    int status;         /* fnls_status of the solve                             */
+    int breakdown;      /* 1 if an Arnoldi happy breakdown ended a cycle        */
+    double relres_true; /* ||b - A x|| / ||b|| recomputed in FP64 at the end    */
+    double relres_hist[64];
+} fnls_info;
+
+/* Default options (see field comments). */
+void fnls_default_opts(fnls_opts *opts);
+
+/* Create a context on HIP device `device`, enqueuing on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  Returns FNLS_ERR_NO_DEVICE if the
+ * device does not exist.  *out is NULL on failure. */
+int fnls_create(fnls_ctx **out, int device, void *hip_stream);
+
+/* Release the context (not the caller's workspace).  Waits for its stream. */
+void fnls_destroy(fnls_ctx *ctx);
+
+/* Bytes of device workspace needed for d, n and a Krylov restart length
+ * `restart` (both precisions fit the same block).  0 for invalid sizes. */
+size_t fnls_workspace_bytes(int d, int n, int restart);
+
+/* a1 -- Assemble the operator for one parameter set (Sec. 2.1, 2.2, 4):
+ * fractional centred-difference coefficients c_k of order alpha in (1, 2],
+ * mu = tau / h^alpha, the circulant-embedding symbol of T_1 and the
+ * eigenvalues lambda_k of tau(T_1) (both on the host in extended precision,
+ * then copied into the workspace).  rho >= 0 scales |u|^2 in D, tau > 0 is
+ * the time step, h > 0 the grid spacing.  `workspace` is a device pointer
+ * owned by the caller, 256-byte aligned, of `workspace_bytes` bytes; its
+ * size fixes the largest usable restart length.  Invalidates any previous
+ * precond_setup. */
+int fnls_assemble(fnls_ctx *ctx, double alpha, double rho, int d, int n, double h, double tau,
+                  void *workspace, size_t workspace_bytes);
+
+/* a2 -- Preconditioner setup for the current time level (Sec. 2.1, 2.2):
+ * D_j = rho tau |u_cur_j|^2 (+ tau V_j if V != NULL, V real, N doubles on
+ * the device), and the preconditioner parameter omega > 0 (Sec. 3-4; 1 is
+ * the paper's choice). */
+int fnls_precond_setup(fnls_ctx *ctx, const fnls_c128 *u_cur, const double *V, double omega);
+
+/* a3 -- y = A x = (D - T_d + i I) x.  x and y must not alias. */
+int fnls_apply_A(fnls_ctx *ctx, const fnls_c128 *x, fnls_c128 *y);
+
+/* a4 -- z = Ptilde^{-1} r, the complex form of the sine-transform TBAN
+ * preconditioner (formula in the header comment).  r and z must not alias. */
+int fnls_apply_precond(fnls_ctx *ctx, const fnls_c128 *r, fnls_c128 *z);
+
+/* Right-hand side of the three-level scheme (Sec. 2.1, 2.2 multiplied by
+ * 2 dt): b = (i I + T_d - D) u_prev, with D from the last precond_setup. */
+int fnls_rhs(fnls_ctx *ctx, const fnls_c128 *u_prev, fnls_c128 *b);
+
+/* a5-a8 -- Solve A x = b (x0 = 0) by right-preconditioned GMRES(m) with
+ * classical Gram-Schmidt applied twice and complex Givens rotations, FP64 or
+ * FP32 GMRES-IR per opts->precision.  Stops when the recomputed relative
+ * residual is below opts->tol (FNLS_OK) or after opts->maxit iterations
+ * (FNLS_NOT_CONVERGED, best x written).  b == 0 gives x = 0.  `opts` may be
+ * NULL (defaults); `info` may be NULL.  b and x must not alias. */
+int fnls_solve(fnls_ctx *ctx, const fnls_c128 *b, fnls_c128 *x, const fnls_opts *opts,
+               fnls_info *info);
+
+/* a9 -- One three-level time step (Sec. 2.1 LICD / Sec. 2.2 TLID scheme):
+ * precond_setup(u_cur), b = (i I + T_d - D) u_prev, solve, u_next = x.
+ * u_next must not alias u_prev or u_cur. */
+int fnls_step(fnls_ctx *ctx, const fnls_c128 *u_prev, const fnls_c128 *u_cur, fnls_c128 *u_next,
+              const fnls_opts *opts, fnls_info *info);
+
+/* Starter u^0 -> u^1: one Crank-Nicolson step with the nonlinearity frozen
+ * at u^0, i.e. the same system with tau replaced by tau/2 (the paper cites a
+ * second-order starter without defining it).  u1 must not alias u0. */
+int fnls_first_step(fnls_ctx *ctx, const fnls_c128 *u0, fnls_c128 *u1, const fnls_opts *opts,
+                    fnls_info *info);
+
+/* Last error message of this context ("" if none); valid until the next call. */
+const char *fnls_last_error(const fnls_ctx *ctx);
+
+/* Static description of a status code. */
+const char *fnls_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FNLS_H */

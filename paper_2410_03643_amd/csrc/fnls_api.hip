@@ -1,0 +1,909 @@
+// C ABI of libfnls (declared in include/fnls.h): context, workspace layout,
+// host assembly of the tables, and the GMRES / GMRES-IR drivers that
+// sequence the kernels of fnls_kernels.hip on the context's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/fnls.h"
+#include "fnls_common.h"
+#include "fnls_launch.h"
+
+using namespace fnls;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kEvents = 8;
+constexpr size_t kStaticLds = 12 * 1024;   // static LDS of k_pass (reduction scratch, line table)
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+bool valid_n(int n) {
+    if (n < 1 || n > 1023) return false;
+    const int m = n + 1;
+    return (m & (m - 1)) == 0;
+}
+
+long long ipow(int n, int d) {
+    long long r = 1;
+    for (int i = 0; i < d; ++i) r *= n;
+    return r;
+}
+
+struct Geo {
+    int G, L, blocks;
+    size_t lds;
+    long long stride, nlines;
+};
+
+Geo pass_geo(int d, int n, int axis, bool fp64, size_t max_dyn_lds) {
+    Geo g;
+    const int m = n + 1;
+    g.G = std::max(1, std::min(64, m / 16));
+    const size_t elem = fp64 ? 16 : 8;
+    const size_t perline = (size_t)(2 * m + 2) * elem;
+    int L = 256 / g.G;
+    while (L > 1 && (size_t)L * perline > max_dyn_lds) L /= 2;
+    while (g.G * L < 64) L *= 2;   // whole wavefronts
+    g.L = L;
+    g.lds = (size_t)L * perline;
+    g.stride = ipow(n, d - 1 - axis);
+    g.nlines = ipow(n, d - 1);
+    g.blocks = (int)((g.nlines + L - 1) / L);
+    return g;
+}
+
+int stream_blocks(long long N) {
+    return (int)std::max<long long>(1, (N + (long long)kStreamThreads * kEpt - 1) / ((long long)kStreamThreads * kEpt));
+}
+
+struct Layout {
+    size_t tw64, tw32, syme64, symo64, lam64, syme32, symo32, lam32;
+    size_t state, partials, D64, D32;
+    size_t t1, t2, zb, acc, r64, bbuf, V;
+    size_t total;
+    int pstride;
+};
+
+Layout make_layout(int d, int n, int restart, size_t max_dyn_lds) {
+    Layout l;
+    const int m = n + 1;
+    const long long N = ipow(n, d);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    l.tw64 = take((size_t)2 * m * 16);
+    l.tw32 = take((size_t)2 * m * 8);
+    l.syme64 = take((size_t)m * 8);
+    l.symo64 = take((size_t)m * 8);
+    l.lam64 = take((size_t)m * 8);
+    l.syme32 = take((size_t)m * 4);
+    l.symo32 = take((size_t)m * 4);
+    l.lam32 = take((size_t)m * 4);
+    l.state = take(sizeof(GmresState));
+    int pmax = stream_blocks(N);
+    for (int ax = 0; ax < d; ++ax) {
+        pmax = std::max(pmax, pass_geo(d, n, ax, true, max_dyn_lds).blocks);
+        pmax = std::max(pmax, pass_geo(d, n, ax, false, max_dyn_lds).blocks);
+    }
+    l.pstride = pmax;
+    l.partials = take((size_t)(kMaxRestart + 2) * pmax * 16);
+    l.D64 = take((size_t)N * 8);
+    l.D32 = take((size_t)N * 4);
+    l.t1 = take((size_t)N * 16);
+    l.t2 = take((size_t)N * 16);
+    l.zb = take((size_t)N * 16);
+    l.acc = take((size_t)N * 16);
+    l.r64 = take((size_t)N * 16);
+    l.bbuf = take((size_t)N * 16);
+    l.V = take((size_t)N * 16 * restart);
+    l.total = off;
+    return l;
+}
+
+}  // namespace
+
+struct fnls_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    size_t max_dyn_lds = 64 * 1024;
+    std::string err;
+    // parameters
+    int assembled = 0;
+    double alpha = 0, rho = 0, h = 0, tau = 0;
+    int d = 0, n = 0, m = 0;
+    long long N = 0;
+    int restart_cap = 0;
+    double tscale = 1.0;
+    double omega = 1.0;
+    int have_D = 0;
+    // workspace
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    Layout lay{};
+    HostStatus* hs = nullptr;       // pinned, device-written
+    HostStatus* hs_dev = nullptr;
+    hipEvent_t ev[kEvents] = {};
+
+    template <typename T> T* at(size_t off) { return reinterpret_cast<T*>(ws + off); }
+    GmresState* st() { return at<GmresState>(lay.state); }
+};
+
+static int set_err(fnls_ctx* c, int code, const char* fmt, ...) {
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                         \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            return set_err(ctx, FNLS_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));   \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// pass sequencing
+// ---------------------------------------------------------------------------
+namespace {
+
+PassArgs base_args(fnls_ctx* c, bool fp64, int axis, const Geo& g) {
+    PassArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.n = c->n;
+    a.m = c->m;
+    a.d = c->d;
+    a.axis = axis;
+    a.G = g.G;
+    a.L = g.L;
+    a.lgG = 0;
+    while ((1 << a.lgG) < g.G) ++a.lgG;
+    a.lgL = 0;
+    while ((1 << a.lgL) < g.L) ++a.lgL;
+    // ceil(2^32 / n) for n >= 2 (n = 1 is handled in the kernel without it)
+    a.magic_n = c->n >= 2 ? (unsigned)((((unsigned long long)1 << 32) + (unsigned)c->n - 1) / (unsigned)c->n) : 0u;
+    a.stride = g.stride;
+    a.nlines = g.nlines;
+    a.N = c->N;
+    a.tw = fp64 ? (const void*)c->at<double2>(c->lay.tw64) : (const void*)c->at<float2>(c->lay.tw32);
+    a.sym_e = fp64 ? (const void*)c->at<double>(c->lay.syme64) : (const void*)c->at<float>(c->lay.syme32);
+    a.sym_o = fp64 ? (const void*)c->at<double>(c->lay.symo64) : (const void*)c->at<float>(c->lay.symo32);
+    a.lam = fp64 ? (const void*)c->at<double>(c->lay.lam64) : (const void*)c->at<float>(c->lay.lam32);
+    a.D = fp64 ? (const void*)c->at<double>(c->lay.D64) : (const void*)c->at<float>(c->lay.D32);
+    a.tscale = c->tscale;
+    a.omega = c->omega;
+    a.partials = c->at<double2>(c->lay.partials);
+    a.pstride = c->lay.pstride;
+    a.st = c->st();
+    a.hs = c->hs_dev;
+    return a;
+}
+
+int run_pass(fnls_ctx* c, bool fp64, int axis, PassVariant v, PassArgs& a, const Geo& g) {
+    hipError_t e = launch_pass(fp64 ? 1 : 0, v, a, g.blocks, g.lds, c->stream);
+    if (e != hipSuccess)
+        return set_err(c, FNLS_ERR_HIP, "pass launch (axis %d, ops %d) failed: %s", axis, v.ops, hipGetErrorString(e));
+    return FNLS_OK;
+}
+
+// Working vectors typed for the precision of the transform kernels.
+struct Bufs {
+    void* t1;
+    void* t2;
+    void* zb;
+    void* acc;
+    void* v0;     // basis vector 0
+    void* vbase;  // basis vectors 1..
+};
+
+Bufs bufs(fnls_ctx* c, bool fp64, const void* v0_fp64) {
+    Bufs b;
+    b.t1 = c->at<char>(c->lay.t1);
+    b.t2 = c->at<char>(c->lay.t2);
+    b.zb = c->at<char>(c->lay.zb);
+    b.acc = c->at<char>(c->lay.acc);
+    if (fp64) {
+        b.v0 = const_cast<void*>(v0_fp64);
+        b.vbase = c->at<char>(c->lay.V);
+    } else {
+        float2* V32 = c->at<float2>(c->lay.V);
+        b.v0 = V32;
+        b.vbase = V32 + c->N;
+    }
+    return b;
+}
+
+// Sine-transform passes that precede the last one: axes d-1 .. 1 forward,
+// axis 0 transform-divide-transform, axes 1 .. d-2 back.  The first pass reads
+// `src` with input mode `inm`; returns the buffer holding the result.
+int precond_front(fnls_ctx* c, bool fp64, int inm, const void* src, int basis_j, Bufs& b, void** result,
+                  int check_active) {
+    const int d = c->d;
+    void* cur_in = const_cast<void*>(src);
+    int cur_mode = inm;
+    void* pingpong[2] = {b.t1, b.t2};
+    int pp = 0;
+    auto step = [&](int axis, int ops) -> int {
+        Geo g = pass_geo(d, c->n, axis, fp64, c->max_dyn_lds);
+        PassArgs a = base_args(c, fp64, axis, g);
+        a.in = cur_in;
+        a.v0 = b.v0;
+        a.vbase = b.vbase;
+        a.basis_j = basis_j;
+        a.out = pingpong[pp];
+        a.check_active = check_active;
+        PassVariant v{cur_mode, ops, Z_NONE, OUT_LINE, FIN_WRITE};
+        int rc = run_pass(c, fp64, axis, v, a, g);
+        cur_in = pingpong[pp];
+        pp ^= 1;
+        cur_mode = IN_PLAIN;
+        return rc;
+    };
+    int rc;
+    for (int ax = d - 1; ax >= 1; --ax)
+        if ((rc = step(ax, P_DST1)) != FNLS_OK) return rc;
+    if ((rc = step(0, P_DST1 | P_DIV | P_DST2)) != FNLS_OK) return rc;
+    for (int ax = 1; ax <= d - 2; ++ax)
+        if ((rc = step(ax, P_DST1)) != FNLS_OK) return rc;
+    *result = cur_in;
+    return FNLS_OK;
+}
+
+// Toeplitz passes for axes d-2 .. 0 after the first one (which produced acc):
+// out = acc + cT T_axis x, the last one with final mode `fin`.
+int toeplitz_tail(fnls_ctx* c, bool fp64, const void* x, void* acc, int fin, void* final_out, PassArgs tmpl,
+                  int check_active) {
+    const int d = c->d;
+    for (int ax = d - 2; ax >= 0; --ax) {
+        Geo g = pass_geo(d, c->n, ax, fp64, c->max_dyn_lds);
+        PassArgs a = base_args(c, fp64, ax, g);
+        a.in = x;
+        a.acc_in = acc;
+        a.cT = -1.0;
+        a.check_active = check_active;
+        const bool last = (ax == 0);
+        a.out = last ? final_out : acc;
+        int f = last ? fin : FIN_WRITE;
+        a.v0 = tmpl.v0;
+        a.vbase = tmpl.vbase;
+        a.basis_j = tmpl.basis_j;
+        a.b64 = tmpl.b64;
+        a.r64 = tmpl.r64;
+        a.r32 = tmpl.r32;
+        a.ir = tmpl.ir;
+        PassVariant v{IN_PLAIN, P_TOEP, Z_NONE, OUT_ACC_NEXT, f};
+        int rc = run_pass(c, fp64, ax, v, a, g);
+        if (rc != FNLS_OK) return rc;
+    }
+    return FNLS_OK;
+}
+
+// y = (cD D + i ci I + cT T_d) x, all FP64 (used by apply_A and rhs).
+int matvec64(fnls_ctx* c, const void* x, void* y, double cD, double ci, double cT) {
+    const int d = c->d;
+    Geo g = pass_geo(d, c->n, d - 1, true, c->max_dyn_lds);
+    PassArgs a = base_args(c, true, d - 1, g);
+    a.in = x;
+    a.cD = cD;
+    a.ci = ci;
+    a.cT = cT;
+    a.out = (d == 1) ? y : c->at<char>(c->lay.acc);
+    PassVariant v{IN_PLAIN, P_TOEP, Z_NONE, OUT_ACC_FIRST, FIN_WRITE};
+    int rc = run_pass(c, true, d - 1, v, a, g);
+    if (rc != FNLS_OK || d == 1) return rc;
+    void* acc = c->at<char>(c->lay.acc);
+    for (int ax = d - 2; ax >= 0; --ax) {
+        Geo g2 = pass_geo(d, c->n, ax, true, c->max_dyn_lds);
+        PassArgs a2 = base_args(c, true, ax, g2);
+        a2.in = x;
+        a2.acc_in = acc;
+        a2.cT = cT;
+        a2.out = (ax == 0) ? y : acc;
+        PassVariant v2{IN_PLAIN, P_TOEP, Z_NONE, OUT_ACC_NEXT, FIN_WRITE};
+        rc = run_pass(c, true, ax, v2, a2, g2);
+        if (rc != FNLS_OK) return rc;
+    }
+    return FNLS_OK;
+}
+
+// One Arnoldi step j: w = A Ptilde^{-1} v_j into basis slot j+1, first-round
+// dot products, then the two Gram-Schmidt update kernels.
+int arnoldi_step(fnls_ctx* c, bool fp64, Bufs& b, int j) {
+    const int d = c->d;
+    const size_t esz = fp64 ? 16 : 8;
+    void* vj = (j == 0) ? b.v0 : (void*)((char*)b.vbase + (size_t)(j - 1) * c->N * esz);
+    void* w = (char*)b.vbase + (size_t)j * c->N * esz;
+    int rc;
+    if (d == 1) {
+        Geo g = pass_geo(d, c->n, 0, fp64, c->max_dyn_lds);
+        PassArgs a = base_args(c, fp64, 0, g);
+        a.in = vj;
+        a.v0 = b.v0;
+        a.vbase = b.vbase;
+        a.basis_j = j;
+        a.out = w;
+        a.cD = 1.0;
+        a.ci = 1.0;
+        a.cT = -1.0;
+        a.check_active = 1;
+        PassVariant v{IN_BASIS, P_DST1 | P_DIV | P_DST2 | P_SCALE | P_TOEP, Z_NONE, OUT_ACC_FIRST, FIN_WDOTS};
+        if ((rc = run_pass(c, fp64, 0, v, a, g)) != FNLS_OK) return rc;
+    } else {
+        void* t;
+        if ((rc = precond_front(c, fp64, IN_BASIS, vj, j, b, &t, 1)) != FNLS_OK) return rc;
+        Geo g = pass_geo(d, c->n, d - 1, fp64, c->max_dyn_lds);
+        PassArgs a = base_args(c, fp64, d - 1, g);
+        a.in = t;
+        a.zout = b.zb;
+        a.out = b.acc;
+        a.cD = 1.0;
+        a.ci = 1.0;
+        a.cT = -1.0;
+        a.check_active = 1;
+        PassVariant v{IN_PLAIN, P_DST1 | P_SCALE | P_TOEP, Z_WRITE, OUT_ACC_FIRST, FIN_WRITE};
+        if ((rc = run_pass(c, fp64, d - 1, v, a, g)) != FNLS_OK) return rc;
+        PassArgs tmpl;
+        std::memset(&tmpl, 0, sizeof tmpl);
+        tmpl.v0 = b.v0;
+        tmpl.vbase = b.vbase;
+        tmpl.basis_j = j;
+        if ((rc = toeplitz_tail(c, fp64, b.zb, b.acc, FIN_WDOTS, w, tmpl, 1)) != FNLS_OK) return rc;
+    }
+    StreamArgs s;
+    std::memset(&s, 0, sizeof s);
+    s.N = c->N;
+    s.w = w;
+    s.v0 = b.v0;
+    s.vbase = b.vbase;
+    s.nv = j + 1;
+    s.partials = c->at<double2>(c->lay.partials);
+    s.pstride = c->lay.pstride;
+    s.st = c->st();
+    s.hs = c->hs_dev;
+    s.check_active = 1;
+    const int blocks = stream_blocks(c->N);
+    hipError_t e = launch_cgs(fp64 ? 1 : 0, 0, s, blocks, c->stream);
+    if (e == hipSuccess) e = launch_cgs(fp64 ? 1 : 0, 1, s, blocks, c->stream);
+    if (e != hipSuccess) return set_err(c, FNLS_ERR_HIP, "cgs launch failed: %s", hipGetErrorString(e));
+    return FNLS_OK;
+}
+
+// End of a cycle: x (+)= Ptilde^{-1} (sum_i y_i v_i).  FP64: the recomputed
+// residual r = b - A x follows in the same passes.  FP32 (IR): x is updated
+// in FP64 from the FP32 correction, then the FP64 residual chain runs.
+int cycle_final(fnls_ctx* c, bool fp64, Bufs& b, const void* b64, void* x, int first) {
+    const int d = c->d;
+    double2* r64 = c->at<double2>(c->lay.r64);
+    float2* r32 = fp64 ? nullptr : c->at<float2>(c->lay.V);
+    int rc;
+    if (fp64) {
+        if (d == 1) {
+            Geo g = pass_geo(d, c->n, 0, true, c->max_dyn_lds);
+            PassArgs a = base_args(c, true, 0, g);
+            a.v0 = b.v0;
+            a.vbase = b.vbase;
+            a.x64 = (double2*)x;
+            a.first_cycle = first;
+            a.cD = 1.0;
+            a.ci = 1.0;
+            a.cT = -1.0;
+            a.b64 = (const double2*)b64;
+            a.r64 = r64;
+            PassVariant v{IN_COMBO, P_DST1 | P_DIV | P_DST2 | P_SCALE | P_TOEP, Z_XADD, OUT_ACC_FIRST, FIN_RESID};
+            return run_pass(c, true, 0, v, a, g);
+        }
+        void* t;
+        if ((rc = precond_front(c, true, IN_COMBO, nullptr, 0, b, &t, 0)) != FNLS_OK) return rc;
+        Geo g = pass_geo(d, c->n, d - 1, true, c->max_dyn_lds);
+        PassArgs a = base_args(c, true, d - 1, g);
+        a.in = t;
+        a.x64 = (double2*)x;
+        a.first_cycle = first;
+        a.out = b.acc;
+        a.cD = 1.0;
+        a.ci = 1.0;
+        a.cT = -1.0;
+        PassVariant v{IN_PLAIN, P_DST1 | P_SCALE | P_TOEP, Z_XADD, OUT_ACC_FIRST, FIN_WRITE};
+        if ((rc = run_pass(c, true, d - 1, v, a, g)) != FNLS_OK) return rc;
+        PassArgs tmpl;
+        std::memset(&tmpl, 0, sizeof tmpl);
+        tmpl.b64 = (const double2*)b64;
+        tmpl.r64 = r64;
+        return toeplitz_tail(c, true, x, b.acc, FIN_RESID, nullptr, tmpl, 0);
+    }
+    // FP32 correction
+    if (d == 1) {
+        Geo g = pass_geo(d, c->n, 0, false, c->max_dyn_lds);
+        PassArgs a = base_args(c, false, 0, g);
+        a.v0 = b.v0;
+        a.vbase = b.vbase;
+        a.x64 = (double2*)x;
+        a.first_cycle = first;
+        PassVariant v{IN_COMBO, P_DST1 | P_DIV | P_DST2 | P_SCALE, Z_XADD, OUT_LINE, FIN_WRITE};
+        if ((rc = run_pass(c, false, 0, v, a, g)) != FNLS_OK) return rc;
+    } else {
+        void* t;
+        if ((rc = precond_front(c, false, IN_COMBO, nullptr, 0, b, &t, 0)) != FNLS_OK) return rc;
+        Geo g = pass_geo(d, c->n, d - 1, false, c->max_dyn_lds);
+        PassArgs a = base_args(c, false, d - 1, g);
+        a.in = t;
+        a.x64 = (double2*)x;
+        a.first_cycle = first;
+        PassVariant v{IN_PLAIN, P_DST1 | P_SCALE, Z_XADD, OUT_LINE, FIN_WRITE};
+        if ((rc = run_pass(c, false, d - 1, v, a, g)) != FNLS_OK) return rc;
+    }
+    // FP64 residual r = b - A x, with its complex64 copy as the next basis vector 0
+    Geo g = pass_geo(d, c->n, d - 1, true, c->max_dyn_lds);
+    PassArgs a = base_args(c, true, d - 1, g);
+    a.in = x;
+    a.cD = 1.0;
+    a.ci = 1.0;
+    a.cT = -1.0;
+    if (d == 1) {
+        a.b64 = (const double2*)b64;
+        a.r64 = r64;
+        a.r32 = r32;
+        a.ir = 1;
+        PassVariant v{IN_PLAIN, P_TOEP, Z_NONE, OUT_ACC_FIRST, FIN_RESID};
+        return run_pass(c, true, 0, v, a, g);
+    }
+    void* acc64 = c->at<char>(c->lay.acc);
+    a.out = acc64;
+    PassVariant v{IN_PLAIN, P_TOEP, Z_NONE, OUT_ACC_FIRST, FIN_WRITE};
+    if ((rc = run_pass(c, true, d - 1, v, a, g)) != FNLS_OK) return rc;
+    PassArgs tmpl;
+    std::memset(&tmpl, 0, sizeof tmpl);
+    tmpl.b64 = (const double2*)b64;
+    tmpl.r64 = r64;
+    tmpl.r32 = r32;
+    tmpl.ir = 1;
+    return toeplitz_tail(c, true, x, acc64, FIN_RESID, nullptr, tmpl, 0);
+}
+
+int check_ready(fnls_ctx* c) {
+    if (!c) return FNLS_ERR_INVALID_ARG;
+    if (!c->assembled) return set_err(c, FNLS_ERR_STATE, "fnls_assemble has not been called");
+    return FNLS_OK;
+}
+
+int check_solve_ready(fnls_ctx* c) {
+    int rc = check_ready(c);
+    if (rc != FNLS_OK) return rc;
+    if (!c->have_D) return set_err(c, FNLS_ERR_STATE, "fnls_precond_setup has not been called");
+    return FNLS_OK;
+}
+
+// Wait for event k and return a snapshot of the host status.
+int wait_status(fnls_ctx* c, hipEvent_t ev, HostStatus* out) {
+    hipError_t e = hipEventSynchronize(ev);
+    if (e != hipSuccess) return set_err(c, FNLS_ERR_HIP, "hipEventSynchronize: %s", hipGetErrorString(e));
+    std::memcpy(out, (const void*)c->hs, sizeof(HostStatus));
+    return FNLS_OK;
+}
+
+// One GMRES cycle (iterations until the device reports a stop), with up to
+// `lookahead` iterations enqueued beyond the one whose status is awaited.
+// Returns FNLS_OK and sets *done when the solve ended before the cycle
+// started (b == 0 or non-finite b).
+int run_cycle(fnls_ctx* c, bool fp64, Bufs& b, int restart, int lookahead, int* done) {
+    int issued = 0, waited = 0;
+    *done = 0;
+    HostStatus hs;
+    while (true) {
+        while (issued < restart && issued <= waited + lookahead) {
+            int rc = arnoldi_step(c, fp64, b, issued);
+            if (rc != FNLS_OK) return rc;
+            HIPCHK(c, hipEventRecord(c->ev[issued % kEvents], c->stream));
+            ++issued;
+        }
+        int rc = wait_status(c, c->ev[waited % kEvents], &hs);
+        if (rc != FNLS_OK) return rc;
+        ++waited;
+        if (hs.done) {
+            *done = 1;
+            return FNLS_OK;
+        }
+        if (hs.stopped || waited >= restart) break;
+    }
+    // let any speculative (inactive) iterations drain before the final passes
+    return FNLS_OK;
+}
+
+void fill_info(fnls_ctx* c, fnls_info* info, int status) {
+    if (!info) return;
+    const HostStatus& hs = *c->hs;
+    std::memset(info, 0, sizeof *info);
+    info->iters = hs.total;
+    info->outer_iters = hs.outer;
+    info->status = status;
+    info->breakdown = hs.breakdown;
+    info->relres_true = hs.relres;
+    const int nh = std::min(64, hs.total);
+    for (int i = 0; i < nh; ++i) info->relres_hist[i] = hs.hist[i];
+}
+
+int solve_impl(fnls_ctx* c, const fnls_c128* b, fnls_c128* x, const fnls_opts* o, fnls_info* info) {
+    const bool fp64 = (o->precision == FNLS_FP64);
+    const int restart = o->restart;
+    HIPCHK(c, launch_config(c->st(), fp64 ? o->tol : o->inner_tol, o->tol, restart, o->maxit,
+                            fp64 ? o->fixed_iters : 0, fp64 ? (1 << 30) : o->max_outer, c->stream));
+    StreamArgs s;
+    std::memset(&s, 0, sizeof s);
+    s.N = c->N;
+    s.b64 = reinterpret_cast<const double2*>(b);
+    s.r32 = fp64 ? nullptr : c->at<float2>(c->lay.V);
+    s.partials = c->at<double2>(c->lay.partials);
+    s.pstride = c->lay.pstride;
+    s.st = c->st();
+    s.hs = c->hs_dev;
+    HIPCHK(c, launch_prepare(s, std::min(1024, stream_blocks(c->N)), c->stream));
+    int first = 1;
+    int status = FNLS_OK;
+    while (true) {
+        Bufs bf = bufs(c, fp64, first ? (const void*)b : (const void*)c->at<double2>(c->lay.r64));
+        int done = 0;
+        int rc = run_cycle(c, fp64, bf, restart, std::max(0, o->lookahead), &done);
+        if (rc != FNLS_OK) return rc;
+        if (done) {
+            // b == 0 (x = 0) or non-finite b
+            if (c->hs->nonfinite) return set_err(c, FNLS_ERR_NONFINITE, "non-finite value in b");
+            HIPCHK(c, hipMemsetAsync(x, 0, (size_t)c->N * 16, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            fill_info(c, info, FNLS_OK);
+            if (info) info->relres_true = 0.0;
+            return FNLS_OK;
+        }
+        rc = cycle_final(c, fp64, bf, b, x, first);
+        if (rc != FNLS_OK) return rc;
+        first = 0;
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        const HostStatus& hs = *c->hs;
+        if (hs.nonfinite) {
+            fill_info(c, info, FNLS_ERR_NONFINITE);
+            return set_err(c, FNLS_ERR_NONFINITE, "non-finite value during the solve");
+        }
+        if (hs.done) {
+            if (o->fixed_iters > 0 && fp64)
+                status = FNLS_OK;
+            else
+                status = (hs.relres < o->tol) ? FNLS_OK : FNLS_NOT_CONVERGED;
+            break;
+        }
+    }
+    fill_info(c, info, status);
+    return status;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+void fnls_default_opts(fnls_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->tol = 1e-10;
+    o->restart = 30;
+    o->maxit = 2000;
+    o->precision = FNLS_FP64;
+    o->inner_tol = 1e-5;
+    o->max_outer = 20;
+    o->fixed_iters = 0;
+    o->lookahead = 1;
+}
+
+const char* fnls_status_string(int s) {
+    switch (s) {
+        case FNLS_OK: return "ok";
+        case FNLS_NOT_CONVERGED: return "not converged";
+        case FNLS_ERR_INVALID_ARG: return "invalid argument";
+        case FNLS_ERR_STATE: return "invalid call order";
+        case FNLS_ERR_WORKSPACE: return "workspace missing or too small";
+        case FNLS_ERR_NONFINITE: return "non-finite input";
+        case FNLS_ERR_HIP: return "HIP runtime error";
+        case FNLS_ERR_NO_DEVICE: return "no usable GPU";
+        default: return "unknown status";
+    }
+}
+
+size_t fnls_workspace_bytes(int d, int n, int restart) {
+    if (d < 1 || d > 3 || !valid_n(n) || restart < 1 || restart > kMaxRestart) return 0;
+    // the LDS budget only changes the partial-sum stride; size for the smallest budget
+    return make_layout(d, n, restart, 48 * 1024).total;
+}
+
+int fnls_create(fnls_ctx** out, int device, void* hip_stream) {
+    if (!out) return FNLS_ERR_INVALID_ARG;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return FNLS_ERR_NO_DEVICE;
+    if (device < 0 || device >= count) return FNLS_ERR_NO_DEVICE;
+    fnls_ctx* c = new (std::nothrow) fnls_ctx();
+    if (!c) return FNLS_ERR_HIP;
+    c->device = device;
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    if (hipSetDevice(device) != hipSuccess) {
+        delete c;
+        return FNLS_ERR_NO_DEVICE;
+    }
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
+        c->max_dyn_lds = (size_t)lds > kStaticLds ? (size_t)lds - kStaticLds : 0;
+    if (hipHostMalloc((void**)&c->hs, sizeof(HostStatus), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+        delete c;
+        return FNLS_ERR_HIP;
+    }
+    std::memset((void*)c->hs, 0, sizeof(HostStatus));
+    if (hipHostGetDevicePointer((void**)&c->hs_dev, c->hs, 0) != hipSuccess) {
+        (void)hipHostFree(c->hs);
+        delete c;
+        return FNLS_ERR_HIP;
+    }
+    for (int i = 0; i < kEvents; ++i) {
+        if (hipEventCreateWithFlags(&c->ev[i], hipEventDisableTiming) != hipSuccess) {
+            for (int k = 0; k < i; ++k) (void)hipEventDestroy(c->ev[k]);
+            (void)hipHostFree(c->hs);
+            delete c;
+            return FNLS_ERR_HIP;
+        }
+    }
+    *out = c;
+    return FNLS_OK;
+}
+
+void fnls_destroy(fnls_ctx* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    for (int i = 0; i < kEvents; ++i)
+        if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+    if (c->hs) (void)hipHostFree(c->hs);
+    delete c;
+}
+
+const char* fnls_last_error(const fnls_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int fnls_assemble(fnls_ctx* c, double alpha, double rho, int d, int n, double h, double tau, void* workspace,
+                  size_t workspace_bytes) {
+    if (!c) return FNLS_ERR_INVALID_ARG;
+    if (!(alpha > 1.0 && alpha <= 2.0)) return set_err(c, FNLS_ERR_INVALID_ARG, "alpha must lie in (1, 2]");
+    if (!(rho >= 0.0) || !std::isfinite(rho)) return set_err(c, FNLS_ERR_INVALID_ARG, "rho must be finite and >= 0");
+    if (d < 1 || d > 3) return set_err(c, FNLS_ERR_INVALID_ARG, "d must be 1, 2 or 3");
+    if (!valid_n(n)) return set_err(c, FNLS_ERR_INVALID_ARG, "n + 1 must be a power of two and n <= 1023");
+    if (!(h > 0.0) || !std::isfinite(h)) return set_err(c, FNLS_ERR_INVALID_ARG, "h must be finite and > 0");
+    if (!(tau > 0.0) || !std::isfinite(tau)) return set_err(c, FNLS_ERR_INVALID_ARG, "tau must be finite and > 0");
+    if (!workspace) return set_err(c, FNLS_ERR_WORKSPACE, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
+        return set_err(c, FNLS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    // largest restart length that fits
+    int cap = 0;
+    for (int r = kMaxRestart; r >= 1; --r) {
+        if (make_layout(d, n, r, c->max_dyn_lds).total <= workspace_bytes) {
+            cap = r;
+            break;
+        }
+    }
+    if (cap < 1) return set_err(c, FNLS_ERR_WORKSPACE, "workspace too small (need %zu bytes for restart 1)",
+                                make_layout(d, n, 1, c->max_dyn_lds).total);
+    HIPCHK(c, hipSetDevice(c->device));
+    c->alpha = alpha;
+    c->rho = rho;
+    c->d = d;
+    c->n = n;
+    c->m = n + 1;
+    c->h = h;
+    c->tau = tau;
+    c->N = ipow(n, d);
+    c->ws = reinterpret_cast<char*>(workspace);
+    c->ws_bytes = workspace_bytes;
+    c->restart_cap = cap;
+    c->lay = make_layout(d, n, cap, c->max_dyn_lds);
+    c->tscale = 1.0;
+    c->have_D = 0;
+
+    // host tables in extended precision
+    const int m = n + 1;
+    const long double a = alpha;
+    std::vector<long double> ck(n);
+    ck[0] = std::tgamma(a + 1) / (std::tgamma(a / 2 + 1) * std::tgamma(a / 2 + 1));
+    for (int k = 0; k + 1 < n; ++k) ck[k + 1] = ck[k] * ((long double)k - a / 2) / ((long double)k + 1 + a / 2);
+    const long double mu = (long double)tau / std::pow((long double)h, a);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    std::vector<long double> cs(2 * m), sn(2 * m);
+    for (int t = 0; t < 2 * m; ++t) {
+        cs[t] = std::cos(pi * t / m);
+        sn[t] = std::sin(pi * t / m);
+    }
+    std::vector<long double> sym(2 * m);
+    for (int q = 0; q < 2 * m; ++q) {
+        long double acc = 0;
+        for (int j = n - 1; j >= 1; --j) acc += ck[j] * cs[(int)(((long long)j * q) % (2 * m))];
+        sym[q] = mu * (ck[0] + 2 * acc);
+    }
+    std::vector<double2> tw64(2 * m);
+    std::vector<float2> tw32(2 * m);
+    for (int t = 0; t < 2 * m; ++t) {
+        tw64[t] = make_double2((double)cs[t], (double)-sn[t]);
+        tw32[t] = make_float2((float)cs[t], (float)-sn[t]);
+    }
+    std::vector<double> se(m), so(m), lam(m);
+    std::vector<float> se32(m), so32(m), lam32(m);
+    for (int p = 0; p < m; ++p) {
+        se[p] = (double)(sym[2 * p] / (2 * m));
+        so[p] = (double)(sym[2 * p + 1] / (2 * m));
+        lam[p] = p == 0 ? 0.0 : (double)sym[p];
+        se32[p] = (float)se[p];
+        so32[p] = (float)so[p];
+        lam32[p] = (float)lam[p];
+    }
+    HIPCHK(c, hipMemcpyAsync(c->at<void>(c->lay.tw64), tw64.data(), 2 * m * sizeof(double2), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->at<void>(c->lay.tw32), tw32.data(), 2 * m * sizeof(float2), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->at<void>(c->lay.syme64), se.data(), m * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->at<void>(c->lay.symo64), so.data(), m * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->at<void>(c->lay.lam64), lam.data(), m * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->at<void>(c->lay.syme32), se32.data(), m * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->at<void>(c->lay.symo32), so32.data(), m * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->at<void>(c->lay.lam32), lam32.data(), m * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->at<void>(c->lay.state), 0, sizeof(GmresState), c->stream));
+    // the host vectors above go out of scope: finish the copies first
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->assembled = 1;
+    return FNLS_OK;
+}
+
+static int precond_setup_scaled(fnls_ctx* c, const fnls_c128* u, const double* V, double omega, double tau) {
+    StreamArgs s;
+    std::memset(&s, 0, sizeof s);
+    s.N = c->N;
+    s.u = u;
+    s.V = V;
+    s.D64 = c->at<double>(c->lay.D64);
+    s.D32 = c->at<float>(c->lay.D32);
+    s.rho = c->rho;
+    s.tau = tau;
+    const int blocks = (int)std::min<long long>(4096, (c->N + 255) / 256);
+    HIPCHK(c, launch_precond_setup(s, blocks, c->stream));
+    c->omega = omega;
+    c->have_D = 1;
+    return FNLS_OK;
+}
+
+int fnls_precond_setup(fnls_ctx* c, const fnls_c128* u_cur, const double* V, double omega) {
+    int rc = check_ready(c);
+    if (rc != FNLS_OK) return rc;
+    if (!u_cur) return set_err(c, FNLS_ERR_INVALID_ARG, "u_cur is NULL");
+    if (!(omega > 0.0) || !std::isfinite(omega)) return set_err(c, FNLS_ERR_INVALID_ARG, "omega must be > 0");
+    HIPCHK(c, hipSetDevice(c->device));
+    c->tscale = 1.0;
+    return precond_setup_scaled(c, u_cur, V, omega, c->tau);
+}
+
+int fnls_apply_A(fnls_ctx* c, const fnls_c128* x, fnls_c128* y) {
+    int rc = check_solve_ready(c);
+    if (rc != FNLS_OK) return rc;
+    if (!x || !y) return set_err(c, FNLS_ERR_INVALID_ARG, "NULL vector");
+    if ((const void*)x == (const void*)y) return set_err(c, FNLS_ERR_INVALID_ARG, "x and y must not alias");
+    HIPCHK(c, hipSetDevice(c->device));
+    return matvec64(c, x, y, 1.0, 1.0, -1.0);
+}
+
+int fnls_rhs(fnls_ctx* c, const fnls_c128* u_prev, fnls_c128* b) {
+    int rc = check_solve_ready(c);
+    if (rc != FNLS_OK) return rc;
+    if (!u_prev || !b) return set_err(c, FNLS_ERR_INVALID_ARG, "NULL vector");
+    if ((const void*)u_prev == (const void*)b) return set_err(c, FNLS_ERR_INVALID_ARG, "u_prev and b must not alias");
+    HIPCHK(c, hipSetDevice(c->device));
+    return matvec64(c, u_prev, b, -1.0, 1.0, 1.0);
+}
+
+int fnls_apply_precond(fnls_ctx* c, const fnls_c128* r, fnls_c128* z) {
+    int rc = check_solve_ready(c);
+    if (rc != FNLS_OK) return rc;
+    if (!r || !z) return set_err(c, FNLS_ERR_INVALID_ARG, "NULL vector");
+    if ((const void*)r == (const void*)z) return set_err(c, FNLS_ERR_INVALID_ARG, "r and z must not alias");
+    HIPCHK(c, hipSetDevice(c->device));
+    Bufs b = bufs(c, true, nullptr);
+    if (c->d == 1) {
+        Geo g = pass_geo(1, c->n, 0, true, c->max_dyn_lds);
+        PassArgs a = base_args(c, true, 0, g);
+        a.in = r;
+        a.out = z;
+        PassVariant v{IN_PLAIN, P_DST1 | P_DIV | P_DST2 | P_SCALE, Z_NONE, OUT_LINE, FIN_WRITE};
+        return run_pass(c, true, 0, v, a, g);
+    }
+    void* t;
+    if ((rc = precond_front(c, true, IN_PLAIN, r, 0, b, &t, 0)) != FNLS_OK) return rc;
+    Geo g = pass_geo(c->d, c->n, c->d - 1, true, c->max_dyn_lds);
+    PassArgs a = base_args(c, true, c->d - 1, g);
+    a.in = t;
+    a.out = z;
+    PassVariant v{IN_PLAIN, P_DST1 | P_SCALE, Z_NONE, OUT_LINE, FIN_WRITE};
+    return run_pass(c, true, c->d - 1, v, a, g);
+}
+
+static int resolve_opts(fnls_ctx* c, const fnls_opts* in, fnls_opts* o) {
+    if (in) *o = *in;
+    else fnls_default_opts(o);
+    if (!(o->tol > 0.0)) return set_err(c, FNLS_ERR_INVALID_ARG, "tol must be > 0");
+    if (o->restart < 1 || o->restart > c->restart_cap)
+        return set_err(c, FNLS_ERR_WORKSPACE, "restart %d exceeds the workspace capacity %d (or < 1)", o->restart,
+                       c->restart_cap);
+    if (o->maxit < 1) return set_err(c, FNLS_ERR_INVALID_ARG, "maxit must be >= 1");
+    if (o->precision != FNLS_FP64 && o->precision != FNLS_FP32_IR)
+        return set_err(c, FNLS_ERR_INVALID_ARG, "unknown precision");
+    if (o->precision == FNLS_FP32_IR) {
+        if (!(o->inner_tol > 0.0 && o->inner_tol < 1.0)) return set_err(c, FNLS_ERR_INVALID_ARG, "inner_tol must lie in (0, 1)");
+        if (o->max_outer < 1) return set_err(c, FNLS_ERR_INVALID_ARG, "max_outer must be >= 1");
+        if (o->fixed_iters) return set_err(c, FNLS_ERR_INVALID_ARG, "fixed_iters is FP64-only");
+    }
+    if (o->fixed_iters < 0) return set_err(c, FNLS_ERR_INVALID_ARG, "fixed_iters must be >= 0");
+    if (o->lookahead < 0 || o->lookahead > kEvents - 2) return set_err(c, FNLS_ERR_INVALID_ARG, "lookahead out of range");
+    return FNLS_OK;
+}
+
+int fnls_solve(fnls_ctx* c, const fnls_c128* b, fnls_c128* x, const fnls_opts* opts, fnls_info* info) {
+    int rc = check_solve_ready(c);
+    if (rc != FNLS_OK) return rc;
+    if (!b || !x) return set_err(c, FNLS_ERR_INVALID_ARG, "NULL vector");
+    if ((const void*)b == (const void*)x) return set_err(c, FNLS_ERR_INVALID_ARG, "b and x must not alias");
+    fnls_opts o;
+    if ((rc = resolve_opts(c, opts, &o)) != FNLS_OK) return rc;
+    HIPCHK(c, hipSetDevice(c->device));
+    return solve_impl(c, b, x, &o, info);
+}
+
+int fnls_step(fnls_ctx* c, const fnls_c128* u_prev, const fnls_c128* u_cur, fnls_c128* u_next,
+              const fnls_opts* opts, fnls_info* info) {
+    int rc = check_ready(c);
+    if (rc != FNLS_OK) return rc;
+    if (!u_prev || !u_cur || !u_next) return set_err(c, FNLS_ERR_INVALID_ARG, "NULL vector");
+    if ((const void*)u_next == (const void*)u_prev || (const void*)u_next == (const void*)u_cur)
+        return set_err(c, FNLS_ERR_INVALID_ARG, "u_next must not alias the inputs");
+    fnls_opts o;
+    if ((rc = resolve_opts(c, opts, &o)) != FNLS_OK) return rc;
+    HIPCHK(c, hipSetDevice(c->device));
+    c->tscale = 1.0;
+    if ((rc = precond_setup_scaled(c, u_cur, nullptr, c->omega > 0 ? c->omega : 1.0, c->tau)) != FNLS_OK) return rc;
+    fnls_c128* bb = c->at<fnls_c128>(c->lay.bbuf);
+    if ((rc = matvec64(c, u_prev, bb, -1.0, 1.0, 1.0)) != FNLS_OK) return rc;
+    return solve_impl(c, bb, u_next, &o, info);
+}
+
+int fnls_first_step(fnls_ctx* c, const fnls_c128* u0, fnls_c128* u1, const fnls_opts* opts, fnls_info* info) {
+    int rc = check_ready(c);
+    if (rc != FNLS_OK) return rc;
+    if (!u0 || !u1) return set_err(c, FNLS_ERR_INVALID_ARG, "NULL vector");
+    if ((const void*)u0 == (const void*)u1) return set_err(c, FNLS_ERR_INVALID_ARG, "u1 must not alias u0");
+    fnls_opts o;
+    if ((rc = resolve_opts(c, opts, &o)) != FNLS_OK) return rc;
+    HIPCHK(c, hipSetDevice(c->device));
+    const double omega = c->omega > 0 ? c->omega : 1.0;
+    c->tscale = 0.5;
+    rc = precond_setup_scaled(c, u0, nullptr, omega, 0.5 * c->tau);
+    fnls_c128* bb = c->at<fnls_c128>(c->lay.bbuf);
+    if (rc == FNLS_OK) rc = matvec64(c, u0, bb, -1.0, 1.0, 1.0);
+    if (rc == FNLS_OK || rc == FNLS_NOT_CONVERGED) rc = solve_impl(c, bb, u1, &o, info);
+    c->tscale = 1.0;
+    c->have_D = 0;   // D belongs to the starter system; the next step recomputes it
+    return rc;
+}
+
+}  // extern "C"

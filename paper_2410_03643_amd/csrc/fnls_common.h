@@ -1,0 +1,141 @@
+// Shared host/device definitions of libfnls: workspace-resident solver state,
+// the host-visible status word, and the argument blocks of the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fnls {
+
+// Largest restart length supported by the fixed-size Hessenberg state.
+constexpr int kMaxRestart = 64;
+// Elements per thread in the streaming (CGS update / setup) kernels.
+constexpr int kEpt = 8;
+constexpr int kStreamThreads = 256;
+
+// GMRES state kept in device memory (inside the caller's workspace).  Only
+// the last workgroup of a reduction kernel (and single-workgroup kernels)
+// write it; everything else reads it.
+struct GmresState {
+    // rotated Hessenberg R (column j holds rows 0..j), Givens, rhs g
+    double2 R[kMaxRestart][kMaxRestart];
+    double cs[kMaxRestart];
+    double2 sn[kMaxRestart];
+    double2 g[kMaxRestart + 1];
+    double2 hcol[kMaxRestart + 1];   // current column (h1 + h2)
+    double2 coef[kMaxRestart + 1];   // coefficients for update / combination kernels
+    double sigma[kMaxRestart + 1];   // raw basis vector i is stored as v_i / sigma_i
+    double2 y[kMaxRestart];
+    double hist[64];
+    double refnorm;     // ||b|| (FP64) or ||r|| (IR inner): GMRES relative reference
+    double bnorm;       // ||b||
+    double wnorm0;      // ||A P^{-1} v_j|| before orthogonalisation
+    double est;         // |g_{j+1}| / refnorm
+    double relres;      // last recomputed ||b - A x|| / ||b||
+    double tol;         // GMRES tolerance for the estimate
+    double outer_tol;   // tolerance on the recomputed residual
+    int j;              // current iteration within the cycle
+    int k;              // basis size of the stopped cycle
+    int total;          // total iterations
+    int active;         // 1 while the current cycle is running
+    int done;           // 1 when the whole solve has finished
+    int breakdown;
+    int restart, maxit, fixed_iters;
+    int outer;          // completed cycles / refinement steps
+    int max_outer;
+    int nonfinite;
+    unsigned counter;   // arrival counter for last-workgroup reductions
+    unsigned seq;       // status sequence number
+};
+
+// Status mirrored into pinned host memory after every decision point.
+struct HostStatus {
+    unsigned seq;
+    int total;
+    int stopped;     // 1: cycle stopped at this iteration
+    int done;        // 1: whole solve finished
+    int breakdown;
+    int nonfinite;
+    int outer;
+    int pad;
+    double est;
+    double relres;
+    double bnorm;
+    double hist[64];
+};
+
+enum InMode { IN_PLAIN = 0, IN_BASIS = 1, IN_COMBO = 2 };
+enum OutMode { OUT_LINE = 0, OUT_ACC_FIRST = 1, OUT_ACC_NEXT = 2 };
+enum FinalMode { FIN_WRITE = 0, FIN_WDOTS = 1, FIN_RESID = 2 };
+enum ZMode { Z_NONE = 0, Z_WRITE = 1, Z_XSET = 2, Z_XADD = 3 };
+
+// Arguments of the fused axis-pass kernel.  Element type of all "typed"
+// vectors is complex<R> (R = float or double, the kernel's template type);
+// x64 / b64 / r64 are always complex<double>.
+struct PassArgs {
+    // geometry
+    int n, m, d, axis;
+    int G;            // threads per line in the transform phases (power of two)
+    int L;            // lines per workgroup (power of two)
+    int lgG, lgL;     // log2 of G and L
+    unsigned magic_n; // ceil(2^32 / n) (n >= 2): e / n == umulhi(e, magic_n) for e < 2^16
+    long long stride; // element stride along the axis
+    long long nlines; // n^(d-1)
+    long long N;      // n^d
+    // input
+    const void* in;       // IN_PLAIN / IN_BASIS source (typed)
+    const void* v0;       // basis vector 0 (typed)
+    void* vbase;          // basis vector i >= 1 at vbase + (i-1) * N (typed)
+    int basis_j;          // IN_BASIS: index j; FIN_WDOTS: dots with 0..basis_j
+    // tables
+    const void* tw;       // W_{2m}^s, s < 2m (typed complex)
+    const void* sym_e;    // circulant symbol, even frequencies, pre-scaled (typed real)
+    const void* sym_o;    // odd frequencies
+    const void* lam;      // lambda_k at index k (typed real)
+    const void* D;        // diagonal (typed real)
+    double tscale;        // multiplies symbol and lambda (0.5 for the starter)
+    double omega;
+    // outputs
+    void* out;            // typed output (line data / acc / w / residual when typed)
+    void* zout;           // Z_WRITE target (typed)
+    double2* x64;         // Z_XSET / Z_XADD target
+    const void* acc_in;   // OUT_ACC_NEXT accumulator (typed)
+    const void* tin;      // Toeplitz input when it is not the line data (typed)
+    const double2* b64;   // FIN_RESID: right-hand side
+    double2* r64;         // FIN_RESID: residual (FP64)
+    void* r32;            // FIN_RESID: optional complex64 copy of the residual
+    double cD, ci, cT;    // OUT_ACC_FIRST coefficients
+    // reductions
+    double2* partials;    // [nv][pstride]
+    int pstride;
+    GmresState* st;
+    HostStatus* hs;
+    int check_active;     // return at once if st->active == 0
+    int first_cycle;      // Z_XADD: 1 = set x (first correction), 0 = accumulate
+    int ir;               // FIN_RESID: 1 = refinement step of FP32-IR
+};
+
+struct StreamArgs {
+    long long N;
+    const void* u;        // precond_setup input (complex128)
+    const double* V;      // optional potential
+    double* D64;
+    float* D32;
+    double rho, tau;
+    // CGS update
+    void* w;              // typed vector being orthogonalised
+    const void* v0;
+    const void* vbase;
+    int nv;               // number of basis vectors involved (j + 1)
+    // norm / prepare
+    const double2* b64;
+    void* r32;            // optional complex64 copy
+    double2* partials;
+    int pstride;
+    GmresState* st;
+    HostStatus* hs;
+    int check_active;
+    int mode;
+};
+
+}  // namespace fnls

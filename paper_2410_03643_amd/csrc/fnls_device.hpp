@@ -1,0 +1,353 @@
+// Device building blocks of libfnls (gfx950): complex arithmetic, in-register
+// DFTs, a Stockham radix-16/8/4/2 line FFT in LDS, and the two line operators
+// of the method -- the orthonormal DST-I (sine transform S of Sec. 4) and the
+// symmetric Toeplitz product T_1 x (Sec. 2.1) -- both on length m = n + 1
+// complex FFTs.
+//
+// DST-I of length n = m - 1 (y_k = sqrt(2/m) sum_j x_j sin(pi j k / m)):
+// with x_0 = x_m = 0, a_j = x_j - x_{m-j}, b_j = (x_j + x_{m-j}) W_{2m}^j
+// (W_L = exp(-2 pi i / L)), the odd extension's length-2m DFT Z satisfies
+// Z_{2p} = FFT_m(a)_p and Z_{2p+1} = FFT_m(b)_p, and y_k = (i / sqrt(2m)) Z_k.
+//
+// Toeplitz product: T_1 is the leading n x n block of the symmetric circulant
+// of length 2m whose first column is mu c_|k| (zero at k = n, n+1, n+2); its
+// eigenvalues are s_q, q < 2m (s_q = lambda_q, the tau eigenvalues, for
+// 1 <= q <= n).  Splitting the length-2m transform of the zero-padded line into
+// even and odd frequencies gives
+//   T_1 x = 1/2 [ IFFT_m(s_even . FFT_m(x)) + W_{2m}^{-j} IFFT_m(s_odd . FFT_m(W_{2m}^j x)) ],
+// two length-m convolutions (the 1/(2m) is folded into s_even, s_odd).
+//
+// Line layout in LDS: slot s in [0, m) holds unknown s (1-based), slot 0 is
+// the Dirichlet zero.  Each line owns two buffers A and B of m (+1 pad)
+// complex values; G threads of the workgroup work on one line.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <type_traits>
+
+namespace fnls {
+
+template <typename R> struct CT;
+template <> struct CT<double> { using C = double2; };
+template <> struct CT<float> { using C = float2; };
+template <typename R> using cplx = typename CT<R>::C;
+
+template <typename R> __device__ __forceinline__ cplx<R> cm(R a, R b) {
+    cplx<R> r;
+    r.x = a;
+    r.y = b;
+    return r;
+}
+template <typename C> __device__ __forceinline__ C cadd(C a, C b) { C r; r.x = a.x + b.x; r.y = a.y + b.y; return r; }
+template <typename C> __device__ __forceinline__ C csub(C a, C b) { C r; r.x = a.x - b.x; r.y = a.y - b.y; return r; }
+template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
+    C r;
+    r.x = a.x * b.x - a.y * b.y;
+    r.y = a.x * b.y + a.y * b.x;
+    return r;
+}
+// a * conj(b)
+template <typename C> __device__ __forceinline__ C cmulc(C a, C b) {
+    C r;
+    r.x = a.x * b.x + a.y * b.y;
+    r.y = a.y * b.x - a.x * b.y;
+    return r;
+}
+template <typename C, typename S> __device__ __forceinline__ C cscale(C a, S s) { C r; r.x = a.x * s; r.y = a.y * s; return r; }
+template <typename C> __device__ __forceinline__ C cneg(C a) { C r; r.x = -a.x; r.y = -a.y; return r; }
+template <typename C> __device__ __forceinline__ C czero() { C r; r.x = 0; r.y = 0; return r; }
+
+template <typename To, typename From> __device__ __forceinline__ cplx<To> ccast(From a) {
+    return cm<To>(static_cast<To>(a.x), static_cast<To>(a.y));
+}
+
+// multiply by -i (forward transform) or +i (inverse)
+template <bool INV, typename C> __device__ __forceinline__ C rot90(C a) {
+    C r;
+    if (INV) { r.x = -a.y; r.y = a.x; }
+    else     { r.x = a.y;  r.y = -a.x; }
+    return r;
+}
+
+// cos / sin of 2 pi j / 16
+__host__ __device__ constexpr double kc16(int j) {
+    switch (j & 15) {
+        case 0: return 1.0;
+        case 1: return 0.92387953251128675613;
+        case 2: return 0.70710678118654752440;
+        case 3: return 0.38268343236508977173;
+        case 4: return 0.0;
+        case 5: return -0.38268343236508977173;
+        case 6: return -0.70710678118654752440;
+        case 7: return -0.92387953251128675613;
+        case 8: return -1.0;
+        case 9: return -0.92387953251128675613;
+        case 10: return -0.70710678118654752440;
+        case 11: return -0.38268343236508977173;
+        case 12: return 0.0;
+        case 13: return 0.38268343236508977173;
+        case 14: return 0.70710678118654752440;
+        default: return 0.92387953251128675613;
+    }
+}
+__host__ __device__ constexpr double ks16(int j) { return kc16(j - 4); }
+
+// a * W_16^J (forward W = exp(-2 pi i / 16); inverse uses the conjugate)
+template <int J, bool INV, typename C> __device__ __forceinline__ C tw16(C a) {
+    constexpr int j = J & 15;
+    if constexpr (j == 0) {
+        return a;
+    } else if constexpr (j == 4) {
+        return rot90<INV>(a);
+    } else if constexpr (j == 8) {
+        return cneg(a);
+    } else if constexpr (j == 12) {
+        return rot90<!INV>(a);
+    } else {
+        using R = decltype(a.x);
+        const R c = static_cast<R>(kc16(j));
+        const R s = INV ? static_cast<R>(ks16(j)) : static_cast<R>(-ks16(j));
+        C r;
+        r.x = a.x * c - a.y * s;
+        r.y = a.x * s + a.y * c;
+        return r;
+    }
+}
+
+template <bool INV, typename C> __device__ __forceinline__ void dft2(C& a, C& b) {
+    C t = a;
+    a = cadd(t, b);
+    b = csub(t, b);
+}
+
+template <bool INV, typename C> __device__ __forceinline__ void dft4(C& v0, C& v1, C& v2, C& v3) {
+    C t0 = cadd(v0, v2), t1 = csub(v0, v2), t2 = cadd(v1, v3), t3 = rot90<INV>(csub(v1, v3));
+    v0 = cadd(t0, t2);
+    v2 = csub(t0, t2);
+    v1 = cadd(t1, t3);
+    v3 = csub(t1, t3);
+}
+
+// In-register DFT of length RAD in natural order.
+template <int RAD, bool INV, typename C> __device__ __forceinline__ void dft(C* v) {
+    if constexpr (RAD == 2) {
+        dft2<INV>(v[0], v[1]);
+    } else if constexpr (RAD == 4) {
+        dft4<INV>(v[0], v[1], v[2], v[3]);
+    } else if constexpr (RAD == 8) {
+        // n = 4 n1 + n2, k = k1 + 2 k2
+#pragma unroll
+        for (int n2 = 0; n2 < 4; ++n2) dft2<INV>(v[n2], v[4 + n2]);
+        v[5] = tw16<2, INV>(v[5]);
+        v[6] = tw16<4, INV>(v[6]);
+        v[7] = tw16<6, INV>(v[7]);
+        dft4<INV>(v[0], v[1], v[2], v[3]);
+        dft4<INV>(v[4], v[5], v[6], v[7]);
+        C t[8];
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) {
+            t[2 * k2] = v[k2];
+            t[2 * k2 + 1] = v[4 + k2];
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = t[i];
+    } else {
+        static_assert(RAD == 16, "radix");
+        // n = 4 n1 + n2, k = k1 + 4 k2; Y[n2][k1] kept at v[4 k1 + n2]
+#pragma unroll
+        for (int n2 = 0; n2 < 4; ++n2) dft4<INV>(v[n2], v[4 + n2], v[8 + n2], v[12 + n2]);
+        v[5] = tw16<1, INV>(v[5]);
+        v[6] = tw16<2, INV>(v[6]);
+        v[7] = tw16<3, INV>(v[7]);
+        v[9] = tw16<2, INV>(v[9]);
+        v[10] = tw16<4, INV>(v[10]);
+        v[11] = tw16<6, INV>(v[11]);
+        v[13] = tw16<3, INV>(v[13]);
+        v[14] = tw16<6, INV>(v[14]);
+        v[15] = tw16<9, INV>(v[15]);
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) dft4<INV>(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
+        C t[16];
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2) t[k1 + 4 * k2] = v[4 * k1 + k2];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = t[i];
+    }
+}
+
+// One Stockham (self-sorting, decimation in time) stage of radix RAD on one
+// line buffer X, computed in registers.  The caller places a barrier between
+// stage_load and stage_store (in-place update).  Ns is the product of the
+// radices of the earlier stages; tw[s] = W_{2m}^s.
+template <typename R, int RAD>
+struct StageRegs {
+    cplx<R> v[16 / RAD][RAD];
+};
+
+template <typename R, int RAD, bool INV>
+__device__ __forceinline__ void stage_load(StageRegs<R, RAD>& g, const cplx<R>* X, int m, int Ns, int lt, int G,
+                                           const cplx<R>* __restrict__ tw) {
+    using C = cplx<R>;
+    constexpr int PER = 16 / RAD;
+    const int nb = m / RAD;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int b = lt + q * G;
+        if (b < nb) {
+#pragma unroll
+            for (int r = 0; r < RAD; ++r) g.v[q][r] = X[b + r * nb];
+            const int k = b & (Ns - 1);
+            const int step = k * ((2 * m) / (Ns * RAD));
+#pragma unroll
+            for (int r = 1; r < RAD; ++r) {
+                C w = tw[r * step];
+                if (INV) w.y = -w.y;
+                g.v[q][r] = cmul(g.v[q][r], w);
+            }
+            dft<RAD, INV>(g.v[q]);
+        }
+    }
+}
+
+template <typename R, int RAD>
+__device__ __forceinline__ void stage_store(const StageRegs<R, RAD>& g, cplx<R>* X, int m, int Ns, int lt, int G) {
+    constexpr int PER = 16 / RAD;
+    const int nb = m / RAD;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int b = lt + q * G;
+        if (b < nb) {
+            const int k = b & (Ns - 1);
+            const int base = (b - k) * RAD + k;
+#pragma unroll
+            for (int r = 0; r < RAD; ++r) X[base + r * Ns] = g.v[q][r];
+        }
+    }
+}
+
+// Stage on A and (optionally) B with one buffer's registers live at a time:
+// load+compute A | barrier | store A, load+compute B | barrier | store B.
+// The barrier of the next stage (or the caller's) orders "store B" before
+// any later read of B.
+template <typename R, int RAD, bool INV>
+__device__ __forceinline__ void stockham_stage(cplx<R>* A, cplx<R>* B, bool both, int m, int Ns, int lt, int G,
+                                               const cplx<R>* __restrict__ tw) {
+    StageRegs<R, RAD> g;
+    stage_load<R, RAD, INV>(g, A, m, Ns, lt, G, tw);
+    __syncthreads();
+    stage_store<R, RAD>(g, A, m, Ns, lt, G);
+    if (both) {
+        stage_load<R, RAD, INV>(g, B, m, Ns, lt, G, tw);
+        __syncthreads();
+        stage_store<R, RAD>(g, B, m, Ns, lt, G);
+    } else {
+        __syncthreads();
+    }
+}
+
+// Length-m FFT (unnormalised) of line buffer A (and B), natural order in and
+// out.  Ends with a barrier.
+template <typename R, bool INV>
+__device__ __forceinline__ void line_fft(cplx<R>* A, cplx<R>* B, bool both, int m, int lt, int G, const cplx<R>* __restrict__ tw) {
+    int Ns = 1;
+    while (Ns < m) {
+        const int rem = m / Ns;
+        if (rem >= 16) {
+            stockham_stage<R, 16, INV>(A, B, both, m, Ns, lt, G, tw);
+            Ns *= 16;
+        } else if (rem == 8) {
+            stockham_stage<R, 8, INV>(A, B, both, m, Ns, lt, G, tw);
+            Ns *= 8;
+        } else if (rem == 4) {
+            stockham_stage<R, 4, INV>(A, B, both, m, Ns, lt, G, tw);
+            Ns *= 4;
+        } else {
+            stockham_stage<R, 2, INV>(A, B, both, m, Ns, lt, G, tw);
+            Ns *= 2;
+        }
+        // the next stage's first barrier orders this stage's stores to B; the
+        // caller is synchronised below after the last stage
+    }
+    __syncthreads();
+}
+
+// Orthonormal DST-I of the line in A (slots 1..m-1), result in A; B is scratch.
+// Caller has synchronised after writing A.
+template <typename R>
+__device__ __forceinline__ void line_dst(cplx<R>* A, cplx<R>* B, int m, int lt, int G, const cplx<R>* __restrict__ tw) {
+    using C = cplx<R>;
+    const int half = m >> 1;
+    for (int j = lt; j <= half; j += G) {
+        if (j == 0) {
+            A[0] = czero<C>();
+            B[0] = czero<C>();
+        } else {
+            const C xj = A[j];
+            const C xmj = A[m - j];
+            const C a = csub(xj, xmj);
+            const C s = cadd(xj, xmj);
+            if (j == half) {
+                A[j] = czero<C>();
+                B[j] = cmul(s, tw[j]);
+            } else {
+                A[j] = a;
+                A[m - j] = cneg(a);
+                B[j] = cmul(s, tw[j]);
+                B[m - j] = cmul(s, tw[m - j]);
+            }
+        }
+    }
+    __syncthreads();
+    line_fft<R, false>(A, B, true, m, lt, G, tw);
+    // y_{2p} = (i/sqrt(2m)) A_p, y_{2p+1} = (i/sqrt(2m)) B_p
+    constexpr int PER = 8;
+    C ra[PER], rb[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int p = lt + q * G;
+        if (p < half) {
+            ra[q] = A[p];
+            rb[q] = B[p];
+        }
+    }
+    __syncthreads();
+    const R sc = static_cast<R>(1.0 / sqrt(2.0 * m));
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int p = lt + q * G;
+        if (p < half) {
+            A[2 * p] = (p == 0) ? czero<C>() : cm<R>(-sc * ra[q].y, sc * ra[q].x);
+            A[2 * p + 1] = cm<R>(-sc * rb[q].y, sc * rb[q].x);
+        }
+    }
+    __syncthreads();
+}
+
+// Toeplitz convolution core: on exit A holds IFFT_m(s_e FFT_m(x)) and B holds
+// IFFT_m(s_o FFT_m(W^j x)); the product at slot j is A[j] + conj(W_{2m}^j) B[j].
+template <typename R>
+__device__ __forceinline__ void line_toeplitz(cplx<R>* A, cplx<R>* B, int m, int lt, int G, const cplx<R>* __restrict__ tw,
+                              const R* __restrict__ sym_e, const R* __restrict__ sym_o, R tscale) {
+    for (int s = lt; s < m; s += G) B[s] = cmul(A[s], tw[s]);
+    __syncthreads();
+    line_fft<R, false>(A, B, true, m, lt, G, tw);
+    for (int p = lt; p < m; p += G) {
+        A[p] = cscale(A[p], sym_e[p] * tscale);
+        B[p] = cscale(B[p], sym_o[p] * tscale);
+    }
+    __syncthreads();
+    line_fft<R, true>(A, B, true, m, lt, G, tw);
+}
+
+// ---------------------------------------------------------------------------
+// wavefront / workgroup reductions (fixed order: deterministic)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+}  // namespace fnls

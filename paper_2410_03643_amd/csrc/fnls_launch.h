@@ -1,0 +1,23 @@
+// Host-side launch entry points of the kernels in fnls_kernels.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fnls_common.h"
+
+namespace fnls {
+
+struct PassVariant {
+    int inm, ops, zm, outm, fin;
+};
+
+enum PassOps { P_DST1 = 1, P_DIV = 2, P_DST2 = 4, P_SCALE = 8, P_TOEP = 16 };
+
+hipError_t launch_pass(int fp64, const PassVariant& v, const PassArgs& a, int blocks, size_t lds, hipStream_t s);
+hipError_t launch_precond_setup(const StreamArgs& a, int blocks, hipStream_t s);
+hipError_t launch_prepare(const StreamArgs& a, int blocks, hipStream_t s);
+hipError_t launch_cgs(int fp64, int mode, const StreamArgs& a, int blocks, hipStream_t s);
+hipError_t launch_config(GmresState* st, double tol, double outer_tol, int restart, int maxit, int fixed_iters,
+                         int max_outer, hipStream_t s);
+
+}  // namespace fnls

@@ -1,0 +1,250 @@
+"""Python binding of libfnls (the C ABI in include/fnls.h), via ctypes.
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+PyTorch supplies device memory (the workspace is a torch uint8 tensor) and the
+stream (the current torch stream of the device at construction time).  The
+library must have been built (``python -m paper_2410_03643_amd.build``);
+nothing here falls back to another implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from dataclasses import dataclass, field
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfnls.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "fnls.h")
+
+OK = 0
+NOT_CONVERGED = 1
+ERR_INVALID_ARG = -1
+ERR_STATE = -2
+ERR_WORKSPACE = -3
+ERR_NONFINITE = -4
+ERR_HIP = -5
+ERR_NO_DEVICE = -6
+FP64 = 0
+FP32_IR = 1
+
+
+class FnlsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("fnls error %d: %s" % (code, msg))
+        self.code = code
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("maxit", ctypes.c_int),
+                ("precision", ctypes.c_int), ("inner_tol", ctypes.c_double),
+                ("max_outer", ctypes.c_int), ("fixed_iters", ctypes.c_int),
+                ("lookahead", ctypes.c_int), ("reserved", ctypes.c_int * 4)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("outer_iters", ctypes.c_int), ("status", ctypes.c_int),
+                ("breakdown", ctypes.c_int), ("relres_true", ctypes.c_double),
+                ("relres_hist", ctypes.c_double * 64)]
+
+
+@dataclass
+class SolveInfo:
+    iters: int
+    outer_iters: int
+    status: int
+    breakdown: int
+    relres_true: float
+    relres_hist: list = field(default_factory=list)
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libfnls.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libfnls.so is not built: run python -m paper_2410_03643_amd.build")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, ci, cd, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    L.fnls_default_opts.argtypes = [ctypes.POINTER(Opts)]
+    L.fnls_default_opts.restype = None
+    L.fnls_create.argtypes = [ctypes.POINTER(vp), ci, vp]
+    L.fnls_create.restype = ci
+    L.fnls_destroy.argtypes = [vp]
+    L.fnls_destroy.restype = None
+    L.fnls_workspace_bytes.argtypes = [ci, ci, ci]
+    L.fnls_workspace_bytes.restype = sz
+    L.fnls_assemble.argtypes = [vp, cd, cd, ci, ci, cd, cd, vp, sz]
+    L.fnls_assemble.restype = ci
+    L.fnls_precond_setup.argtypes = [vp, vp, vp, cd]
+    L.fnls_precond_setup.restype = ci
+    for name in ("fnls_apply_A", "fnls_apply_precond", "fnls_rhs"):
+        getattr(L, name).argtypes = [vp, vp, vp]
+        getattr(L, name).restype = ci
+    L.fnls_solve.argtypes = [vp, vp, vp, ctypes.POINTER(Opts), ctypes.POINTER(Info)]
+    L.fnls_solve.restype = ci
+    L.fnls_step.argtypes = [vp, vp, vp, vp, ctypes.POINTER(Opts), ctypes.POINTER(Info)]
+    L.fnls_step.restype = ci
+    L.fnls_first_step.argtypes = [vp, vp, vp, ctypes.POINTER(Opts), ctypes.POINTER(Info)]
+    L.fnls_first_step.restype = ci
+    L.fnls_last_error.argtypes = [vp]
+    L.fnls_last_error.restype = ctypes.c_char_p
+    L.fnls_status_string.argtypes = [ci]
+    L.fnls_status_string.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def declared_symbols() -> list[str]:
+    """Function names declared in include/fnls.h."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", " ", txt, flags=re.S)   # drop comments
+    return sorted(set(re.findall(r"\b(fnls_[a-zA-Z0-9_]+)\s*\(", txt)))
+
+
+def workspace_bytes(d: int, n: int, restart: int = 30) -> int:
+    return int(lib().fnls_workspace_bytes(d, n, restart))
+
+
+def default_opts() -> Opts:
+    o = Opts()
+    lib().fnls_default_opts(ctypes.byref(o))
+    return o
+
+
+class Solver:
+    """One assembled operator (alpha, rho, d, n, h, tau) on one GPU.
+
+    Vectors are torch.complex128 tensors of shape (n,)*d on the solver's
+    device (C order, last axis = x_1)."""
+
+    def __init__(self, alpha: float, rho: float, d: int, n: int, h: float, tau: float,
+                 device=None, restart: int = 30):
+        import torch
+        self.torch = torch
+        if device is None:
+            device = torch.device("cuda", torch.cuda.current_device())
+        self.device = torch.device(device)
+        self.stream = torch.cuda.current_stream(self.device)
+        self.alpha, self.rho, self.d, self.n, self.h, self.tau = alpha, rho, d, n, h, tau
+        self.shape = (n,) * d
+        L = lib()
+        self._ctx = ctypes.c_void_p()
+        rc = L.fnls_create(ctypes.byref(self._ctx), self.device.index or 0,
+                           ctypes.c_void_p(self.stream.cuda_stream))
+        if rc != OK:
+            raise FnlsError(rc, L.fnls_status_string(rc).decode())
+        nbytes = L.fnls_workspace_bytes(d, n, restart)
+        if nbytes == 0:
+            L.fnls_destroy(self._ctx)
+            self._ctx = None
+            raise FnlsError(ERR_INVALID_ARG, "unsupported size d=%d n=%d restart=%d" % (d, n, restart))
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self._ws.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        self._check(L.fnls_assemble(self._ctx, alpha, rho, d, n, h, tau,
+                                    ctypes.c_void_p(self._ws_ptr), nbytes))
+
+    # -- helpers -----------------------------------------------------------
+    def _check(self, rc: int) -> int:
+        if rc < 0:
+            raise FnlsError(rc, lib().fnls_last_error(self._ctx).decode())
+        return rc
+
+    def _vec(self, t, name):
+        torch = self.torch
+        if not isinstance(t, torch.Tensor):
+            raise TypeError("%s must be a torch tensor" % name)
+        if t.dtype != torch.complex128 or tuple(t.shape) != self.shape or not t.is_contiguous() \
+                or t.device != self.device:
+            raise ValueError("%s must be a contiguous complex128 tensor of shape %s on %s"
+                             % (name, self.shape, self.device))
+        return ctypes.c_void_p(t.data_ptr())
+
+    def _out(self):
+        return self.torch.empty(self.shape, dtype=self.torch.complex128, device=self.device)
+
+    @staticmethod
+    def _opts(tol, restart, maxit, precision, inner_tol, max_outer, fixed_iters, lookahead):
+        o = default_opts()
+        o.tol = tol
+        o.restart = restart
+        o.maxit = maxit
+        o.precision = {"fp64": FP64, "fp32_ir": FP32_IR}[precision] if isinstance(precision, str) \
+            else int(precision)
+        o.inner_tol = inner_tol
+        o.max_outer = max_outer
+        o.fixed_iters = fixed_iters
+        o.lookahead = lookahead
+        return o
+
+    @staticmethod
+    def _info(i: Info) -> SolveInfo:
+        return SolveInfo(i.iters, i.outer_iters, i.status, i.breakdown, i.relres_true,
+                         [i.relres_hist[k] for k in range(min(64, i.iters))])
+
+    # -- C ABI calls -------------------------------------------------------
+    def precond_setup(self, u_cur, V=None, omega: float = 1.0):
+        vp = None
+        if V is not None:
+            if V.dtype != self.torch.float64 or tuple(V.shape) != self.shape or not V.is_contiguous():
+                raise ValueError("V must be a contiguous float64 tensor of shape %s" % (self.shape,))
+            vp = ctypes.c_void_p(V.data_ptr())
+        self._check(lib().fnls_precond_setup(self._ctx, self._vec(u_cur, "u_cur"), vp, omega))
+
+    def apply_A(self, x, out=None):
+        y = self._out() if out is None else out
+        self._check(lib().fnls_apply_A(self._ctx, self._vec(x, "x"), self._vec(y, "y")))
+        return y
+
+    def apply_precond(self, r, out=None):
+        z = self._out() if out is None else out
+        self._check(lib().fnls_apply_precond(self._ctx, self._vec(r, "r"), self._vec(z, "z")))
+        return z
+
+    def rhs(self, u_prev, out=None):
+        b = self._out() if out is None else out
+        self._check(lib().fnls_rhs(self._ctx, self._vec(u_prev, "u_prev"), self._vec(b, "b")))
+        return b
+
+    def solve(self, b, out=None, *, tol=1e-10, restart=30, maxit=2000, precision="fp64",
+              inner_tol=1e-5, max_outer=20, fixed_iters=0, lookahead=1):
+        x = self._out() if out is None else out
+        o = self._opts(tol, restart, maxit, precision, inner_tol, max_outer, fixed_iters, lookahead)
+        info = Info()
+        self._check(lib().fnls_solve(self._ctx, self._vec(b, "b"), self._vec(x, "x"),
+                                     ctypes.byref(o), ctypes.byref(info)))
+        return x, self._info(info)
+
+    def step(self, u_prev, u_cur, out=None, *, tol=1e-10, restart=30, maxit=2000,
+             precision="fp64", inner_tol=1e-5, max_outer=20, lookahead=1):
+        un = self._out() if out is None else out
+        o = self._opts(tol, restart, maxit, precision, inner_tol, max_outer, 0, lookahead)
+        info = Info()
+        self._check(lib().fnls_step(self._ctx, self._vec(u_prev, "u_prev"), self._vec(u_cur, "u_cur"),
+                                    self._vec(un, "u_next"), ctypes.byref(o), ctypes.byref(info)))
+        return un, self._info(info)
+
+    def first_step(self, u0, out=None, *, tol=1e-10, restart=30, maxit=2000,
+                   precision="fp64", inner_tol=1e-5, max_outer=20, lookahead=1):
+        u1 = self._out() if out is None else out
+        o = self._opts(tol, restart, maxit, precision, inner_tol, max_outer, 0, lookahead)
+        info = Info()
+        self._check(lib().fnls_first_step(self._ctx, self._vec(u0, "u0"), self._vec(u1, "u1"),
+                                          ctypes.byref(o), ctypes.byref(info)))
+        return u1, self._info(info)
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            lib().fnls_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,77 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+declared in include/fnls.h, sizes workspaces, and rejects bad calls on the
+host (no device is touched)."""
+import ctypes
+
+import pytest
+
+from paper_2410_03643_amd import fnls
+
+
+@pytest.fixture(scope="module")
+def L():
+    return fnls.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = fnls.declared_symbols()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_default_opts(L):
+    o = fnls.default_opts()
+    assert o.tol == 1e-10 and o.restart == 30 and o.maxit == 2000
+    assert o.precision == fnls.FP64 and o.fixed_iters == 0 and o.lookahead == 1
+    assert o.inner_tol == 1e-5 and o.max_outer == 20
+
+
+def test_struct_sizes_match_header():
+    # double + 3 int + pad + double + 3 int + int[4] -> 64 bytes; info 24 + 512
+    assert ctypes.sizeof(fnls.Opts) == 64
+    assert ctypes.sizeof(fnls.Info) == 24 + 64 * 8
+
+
+@pytest.mark.parametrize("d,n", [(1, 1), (1, 1023), (2, 7), (2, 1023), (3, 255)])
+def test_workspace_bytes_valid(L, d, n):
+    b30 = fnls.workspace_bytes(d, n, 30)
+    b1 = fnls.workspace_bytes(d, n, 1)
+    N = n ** d
+    assert b30 >= (30 + 6) * 16 * N
+    assert b30 - b1 >= 29 * 16 * N - 256   # one basis vector per extra restart slot
+
+
+@pytest.mark.parametrize("d,n,r", [(0, 7, 30), (4, 7, 30), (2, 0, 30), (2, 6, 30), (2, 1024, 30),
+                                   (2, 2047, 30), (2, 7, 0), (2, 7, 65)])
+def test_workspace_bytes_invalid(L, d, n, r):
+    assert fnls.workspace_bytes(d, n, r) == 0
+
+
+def test_status_strings(L):
+    for code, word in [(0, "ok"), (1, "not converged"), (-1, "invalid"), (-3, "workspace"),
+                       (-4, "non-finite"), (-6, "GPU")]:
+        assert word in L.fnls_status_string(code).decode()
+
+
+def test_null_context_is_rejected(L):
+    assert L.fnls_assemble(None, 1.5, 2.0, 2, 7, 0.1, 0.01, None, 0) == fnls.ERR_INVALID_ARG
+    assert L.fnls_precond_setup(None, None, None, 1.0) == fnls.ERR_INVALID_ARG
+    assert L.fnls_apply_A(None, None, None) == fnls.ERR_INVALID_ARG
+    assert L.fnls_apply_precond(None, None, None) == fnls.ERR_INVALID_ARG
+    assert L.fnls_rhs(None, None, None) == fnls.ERR_INVALID_ARG
+    assert L.fnls_solve(None, None, None, None, None) == fnls.ERR_INVALID_ARG
+    assert L.fnls_step(None, None, None, None, None, None) == fnls.ERR_INVALID_ARG
+    assert L.fnls_first_step(None, None, None, None, None) == fnls.ERR_INVALID_ARG
+    assert L.fnls_create(None, 0, None) == fnls.ERR_INVALID_ARG
+    L.fnls_destroy(None)
+    assert L.fnls_last_error(None) == b"null context"
+
+
+def test_create_without_device_reports_no_device(L):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    ctx = ctypes.c_void_p()
+    assert L.fnls_create(ctypes.byref(ctx), 0, None) == fnls.ERR_NO_DEVICE
+    assert not ctx.value

@@ -1,0 +1,227 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Element-wise comparison on the same seeded inputs.  Operators: relative
+max-norm error <= 1e-12 (FP64 FFT/DST rounding against the dense oracle).
+Solves (parity rule): IT within 1 of the oracle's at the same tolerance, and
+||x_gpu - x_oracle(fixed_iters = IT_gpu)|| / ||x_oracle|| <= 1e-10; the
+recomputed residual of the GPU solution (by the oracle's own operator) below
+the tolerance.  FP32-IR: oracle residual of x_IR below the tolerance and its
+error against the FP64 oracle solution reported and bounded by cond * tol.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import fcd
+from paper_2410_03643_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+OP_TOL = 1e-12
+X_TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch, torch.device("cuda", 0)
+
+
+def make(torch_dev, d, n, lo, hi, alpha, rho, tau, noise=1e-3, seed=0, restart=30):
+    from paper_2410_03643_amd.fnls import Solver
+    torch, dev = torch_dev
+    h = (hi - lo) / (n + 1)
+    u = inputs.soliton(d, n, lo, hi, noise=noise, seed=seed)
+    s = Solver(alpha, rho, d, n, h, tau, device=dev, restart=restart)
+    o = oracle.OracleSolver(alpha, rho, d, n, h, tau)
+    ut = torch.from_numpy(u).to(dev)
+    s.precond_setup(ut)
+    o.precond_setup(u)
+    return s, o, u, ut
+
+
+def relerr(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def to_np(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+OP_CASES = [(1, 1), (1, 3), (1, 7), (1, 15), (1, 63), (1, 1023),
+            (2, 1), (2, 3), (2, 7), (2, 31), (2, 127),
+            (3, 1), (3, 3), (3, 7), (3, 15), (3, 31)]
+
+
+@pytest.mark.parametrize("d,n", OP_CASES)
+def test_apply_A(torch_dev, d, n):
+    torch, dev = torch_dev
+    s, o, u, ut = make(torch_dev, d, n, -6.0, 6.0, 1.5, 2.0, 0.05)
+    x = inputs.random_field((n,) * d, seed=3)
+    y = to_np(s.apply_A(torch.from_numpy(x).to(dev)))
+    assert relerr(y, o.apply_A(x)) < OP_TOL
+
+
+@pytest.mark.parametrize("d,n", OP_CASES)
+def test_apply_precond(torch_dev, d, n):
+    torch, dev = torch_dev
+    s, o, u, ut = make(torch_dev, d, n, -6.0, 6.0, 1.7, 2.0, 0.05)
+    r = inputs.random_field((n,) * d, seed=4)
+    z = to_np(s.apply_precond(torch.from_numpy(r).to(dev)))
+    assert relerr(z, o.apply_Pinv(r)) < OP_TOL
+
+
+@pytest.mark.parametrize("d,n", [(1, 63), (2, 31), (3, 15)])
+def test_rhs(torch_dev, d, n):
+    torch, dev = torch_dev
+    s, o, u, ut = make(torch_dev, d, n, -6.0, 6.0, 1.3, 1.0, 0.02)
+    b = to_np(s.rhs(ut))
+    assert relerr(b, o.rhs(u)) < OP_TOL
+
+
+@pytest.mark.parametrize("alpha", [1.1, 1.5, 2.0])
+def test_apply_A_alpha_range(torch_dev, alpha):
+    torch, dev = torch_dev
+    s, o, u, ut = make(torch_dev, 2, 63, -10.0, 10.0, alpha, 2.0, 0.01)
+    x = inputs.random_field((63, 63), seed=5)
+    assert relerr(to_np(s.apply_A(torch.from_numpy(x).to(dev))), o.apply_A(x)) < OP_TOL
+    assert relerr(to_np(s.apply_precond(torch.from_numpy(x).to(dev))), o.apply_Pinv(x)) < OP_TOL
+
+
+def check_solve(torch_dev, s, o, u, ut, tol=1e-10, **kw):
+    torch, dev = torch_dev
+    b = o.rhs(u)
+    bt = torch.from_numpy(b).to(dev)
+    x_t, info = s.solve(bt, tol=tol, **kw)
+    x = to_np(x_t)
+    xo, io = o.solve(b, tol=tol)
+    xf, _ = o.solve(b, fixed_iters=info.iters)
+    res = np.linalg.norm(b - o.apply_A(x)) / np.linalg.norm(b)
+    print("IT gpu %d oracle %d | relres gpu %.3e oracle-recomputed %.3e | |x-x_fixed| %.3e"
+          % (info.iters, io.iters, info.relres_true, res,
+             np.linalg.norm(x - xf) / np.linalg.norm(xf)), flush=True)
+    assert info.status == 0
+    assert abs(info.iters - io.iters) <= 1
+    assert res < tol
+    assert np.linalg.norm(x - xf) / np.linalg.norm(xf) < X_TOL
+    return x, info
+
+
+@pytest.mark.parametrize("d,n,lo,hi", [(1, 63, -20, 20), (1, 1023, -20, 20), (2, 31, -10, 10),
+                                       (2, 127, -10, 10), (3, 15, -8, 8), (3, 31, -8, 8)])
+def test_solve_fp64(torch_dev, d, n, lo, hi):
+    s, o, u, ut = make(torch_dev, d, n, lo, hi, 1.5, 2.0, 0.01)
+    check_solve(torch_dev, s, o, u, ut)
+
+
+def test_solve_metric_case(torch_dev):
+    """d = 2, n = 1023 on [-10, 10]^2, alpha 1.5, rho 2, dt 0.01 (full size)."""
+    p = inputs.metric_case()
+    s, o, u, ut = make(torch_dev, p.d, p.n, p.lo, p.hi, p.alpha, p.rho, p.tau)
+    check_solve(torch_dev, s, o, u, ut)
+
+
+@pytest.mark.parametrize("d,n", [(1, 255), (2, 63), (3, 15)])
+def test_solve_fp32_ir(torch_dev, d, n):
+    torch, dev = torch_dev
+    s, o, u, ut = make(torch_dev, d, n, -10.0, 10.0, 1.6, 2.0, 0.01)
+    b = o.rhs(u)
+    x_t, info = s.solve(torch.from_numpy(b).to(dev), tol=1e-10, precision="fp32_ir")
+    x = to_np(x_t)
+    res = np.linalg.norm(b - o.apply_A(x)) / np.linalg.norm(b)
+    xo, _ = o.solve(b, tol=1e-13)
+    err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    print("IR: inner IT %d outer %d relres %.3e (oracle %.3e) err vs FP64 oracle %.3e"
+          % (info.iters, info.outer_iters, info.relres_true, res, err), flush=True)
+    assert info.status == 0
+    assert res < 1e-10
+    assert err < 1e-8
+
+
+def test_zero_rhs_gives_zero(torch_dev):
+    torch, dev = torch_dev
+    s, o, u, ut = make(torch_dev, 2, 31, -10, 10, 1.5, 2.0, 0.01)
+    x_t, info = s.solve(torch.zeros_like(ut))
+    assert info.iters == 0 and float(x_t.abs().max()) == 0.0
+
+
+def test_nonfinite_rhs_is_reported(torch_dev):
+    from paper_2410_03643_amd.fnls import FnlsError, ERR_NONFINITE
+    torch, dev = torch_dev
+    s, o, u, ut = make(torch_dev, 2, 31, -10, 10, 1.5, 2.0, 0.01)
+    b = ut.clone()
+    b[3, 5] = complex(float("nan"), 0.0)
+    with pytest.raises(FnlsError) as e:
+        s.solve(b)
+    assert e.value.code == ERR_NONFINITE
+
+
+def test_exact_preconditioner_one_iteration(torch_dev):
+    """alpha = 2, rho = 0: Ptilde = A, GMRES stops after one iteration."""
+    torch, dev = torch_dev
+    s, o, u, ut = make(torch_dev, 2, 31, -5, 5, 2.0, 0.0, 0.05)
+    b = inputs.random_field((31, 31), seed=9)
+    x_t, info = s.solve(torch.from_numpy(b).to(dev), tol=1e-13)
+    assert info.iters == 1
+    x = to_np(x_t)
+    assert np.linalg.norm(b - o.apply_A(x)) / np.linalg.norm(b) < 1e-13
+
+
+def test_restart_and_maxit(torch_dev):
+    torch, dev = torch_dev
+    s, o, u, ut = make(torch_dev, 1, 127, -20, 20, 1.9, 2.0, 0.5)
+    b = o.rhs(u)
+    bt = torch.from_numpy(b).to(dev)
+    x_t, info = s.solve(bt, tol=1e-10, restart=2)
+    assert info.status == 0 and info.outer_iters > 1
+    x = to_np(x_t)
+    assert np.linalg.norm(b - o.apply_A(x)) / np.linalg.norm(b) < 1e-10
+    x_t, info = s.solve(bt, tol=1e-30, maxit=3)
+    assert info.status == 1 and info.iters == 3
+
+
+@pytest.mark.parametrize("k", [1, 2, 4])
+def test_fixed_iters_matches_oracle(torch_dev, k):
+    torch, dev = torch_dev
+    s, o, u, ut = make(torch_dev, 2, 63, -10, 10, 1.4, 2.0, 0.05)
+    b = o.rhs(u)
+    x_t, info = s.solve(torch.from_numpy(b).to(dev), fixed_iters=k)
+    assert info.iters == k
+    xf, _ = o.solve(b, fixed_iters=k)
+    assert np.linalg.norm(to_np(x_t) - xf) / np.linalg.norm(xf) < 1e-12
+
+
+def test_solve_is_deterministic(torch_dev):
+    torch, dev = torch_dev
+    s, o, u, ut = make(torch_dev, 2, 127, -10, 10, 1.5, 2.0, 0.01)
+    b = s.rhs(ut)
+    x1, i1 = s.solve(b)
+    x2, i2 = s.solve(b)
+    assert i1.iters == i2.iters and torch.equal(x1, x2)
+
+
+def test_lookahead_settings_agree(torch_dev):
+    torch, dev = torch_dev
+    s, o, u, ut = make(torch_dev, 2, 63, -10, 10, 1.5, 2.0, 0.01)
+    b = s.rhs(ut)
+    xs = [s.solve(b, lookahead=la)[0] for la in (0, 1, 3)]
+    assert torch.equal(xs[0], xs[1]) and torch.equal(xs[0], xs[2])
+
+
+def test_step_and_first_step(torch_dev):
+    torch, dev = torch_dev
+    d, n, lo, hi, alpha, rho, tau = 2, 63, -10.0, 10.0, 1.5, 2.0, 0.005
+    s, o, u, ut = make(torch_dev, d, n, lo, hi, alpha, rho, tau, noise=0.0)
+    u1t, i1 = s.first_step(ut)
+    u1 = to_np(u1t)
+    u1o, _ = o.first_step(u, tol=1e-13)
+    assert np.linalg.norm(u1 - u1o) / np.linalg.norm(u1o) < 1e-9
+    u2t, i2 = s.step(ut, u1t)
+    u2o, _ = o.step(u, u1o, tol=1e-13)
+    u2 = to_np(u2t)
+    assert np.linalg.norm(u2 - u2o) / np.linalg.norm(u2o) < 1e-9
+    # unitarity of the three-level step (mass invariant)
+    assert abs(np.linalg.norm(u2) - np.linalg.norm(u)) / np.linalg.norm(u) < 1e-9
