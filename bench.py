@@ -1,0 +1,189 @@
+#!/usr/bin/env python3
+"""Benchmark: preconditioned GMRES solves per second on one MI355X.
+
+Workload: the d = 2, n = 1023 system (1,046,529 complex unknowns) on
+[-10, 10]^2 with alpha = 1.5, rho = 2, dt = 0.01, u = sech(|x|) exp(i x_1)
+plus 1e-3 complex noise (seed 0); right-preconditioned GMRES(30) with the
+sine-transform TBAN preconditioner (omega = 1), tolerance 1e-10.
+
+One step = one time-step solve of the whole hot path through the C ABI:
+preconditioner setup D = rho dt |u|^2, right-hand side b = (iI + T - D) u, and
+the GMRES solve (FP64, or FP32 GMRES-IR with --precision fp32_ir; both are
+timed and reported).  The operator tables are assembled once before timing
+(they depend only on alpha, h, dt).  Inputs are resident in HBM.
+
+Prints one JSON line (rank 0, N = 1).  The "roofline" object is for the
+dominant kernel class of the headline precision, from HIP events bracketing
+each launch in a separate instrumented run of the same steps; "cpu_baseline"
+times the CPU oracle on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+TOL = 1e-10
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def time_steps(torch, s, u, un, steps, precision):
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    info = None
+    for _ in range(steps):
+        _, info = s.step(u, u, out=un, tol=TOL, precision=precision)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, ev0.elapsed_time(ev1) / 1e3, info
+
+
+def kernel_profile(torch, s, u, un, steps, precision):
+    s.timing(True)
+    for _ in range(steps):
+        s.step(u, u, out=un, tol=TOL, precision=precision)
+    rep = s.timing_report()
+    s.timing(False)
+    for r in rep:
+        r["avg_us"] = 1e3 * r["total_ms"] / r["launches"]
+        r["bytes_per_launch"] = r["bytes"] / r["launches"]
+        r["gbs"] = r["bytes_per_launch"] / (r["avg_us"] * 1e-6) / 1e9
+        r["ms_per_step"] = r["total_ms"] / steps
+    rep.sort(key=lambda r: -r["total_ms"])
+    return rep
+
+
+def cpu_baseline(p, seconds):
+    import numpy as np  # noqa: F401
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    o = oracle.OracleSolver(p.alpha, p.rho, p.d, p.n, p.h, p.tau)
+    t0 = time.perf_counter()
+    count = 0
+    iters = None
+    while True:
+        _, info = o.step(p.u, p.u, tol=TOL)
+        count += 1
+        iters = info.iters
+        if time.perf_counter() - t0 >= seconds:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": count / dt, "unit": "solves/s", "cores": int(cores), "kind": "oracle",
+            "sample": "%d oracle time-step solves (D, b, FP64 GMRES(30) to 1e-10, %d iterations each) "
+                      "of the same d=2 n=1023 system, %.1f s" % (count, iters, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--precision", choices=["fp64", "fp32_ir"], default="fp64",
+                    help="precision of the headline value (both are measured)")
+    ap.add_argument("--profile-steps", type=int, default=20)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2410_03643_amd import inputs
+    from paper_2410_03643_amd.fnls import Solver
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda", 0)
+    p = inputs.metric_case()
+    log("workload %s: N=%d" % (p.name, p.N))
+    s = Solver(p.alpha, p.rho, p.d, p.n, p.h, p.tau, device=dev, restart=30)
+    u = torch.from_numpy(p.u).to(dev)
+    un = torch.empty_like(u)
+
+    results = {}
+    for prec in ("fp64", "fp32_ir"):
+        log("%s: warmup %d" % (prec, args.warmup))
+        for _ in range(args.warmup):
+            s.step(u, u, out=un, tol=TOL, precision=prec)
+        torch.cuda.synchronize()
+        log("%s: timing %d steps" % (prec, args.steps))
+        wall, gpu, info = time_steps(torch, s, u, un, args.steps, prec)
+        log("%s: %.3f ms/step wall, %.3f ms/step events, IT=%d outer=%d relres=%.2e"
+            % (prec, 1e3 * wall / args.steps, 1e3 * gpu / args.steps, info.iters,
+               info.outer_iters, info.relres_true))
+        assert info.status == 0 and info.relres_true < TOL, "solve did not reach the tolerance"
+        log("%s: kernel profile over %d steps" % (prec, args.profile_steps))
+        prof = kernel_profile(torch, s, u, un, args.profile_steps, prec)
+        results[prec] = dict(wall=wall, gpu=gpu, info=info, prof=prof)
+
+    head = results[args.precision]
+    other = "fp32_ir" if args.precision == "fp64" else "fp64"
+    steps = args.steps
+    dom = head["prof"][0]
+    roofline = {"bound": "hbm", "kernel": dom["name"], "achieved": round(dom["gbs"], 1),
+                "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(dom["gbs"] / PEAK_HBM_GBS, 4),
+                "traffic": None, "avg_us": round(dom["avg_us"], 2),
+                "bytes_per_launch": int(dom["bytes_per_launch"])}
+    total_bytes = sum(r["bytes"] for r in head["prof"]) / args.profile_steps
+    step_ms = 1e3 * head["wall"] / steps
+    out = {
+        "metric": "PGMRES solves/s at d=2 n=1023 (FP64 vs FP32-IR @1e-10); % HBM roofline",
+        "value": round(steps / head["wall"], 2),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(step_ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": p.name + ": d=2 n=1023 [-10,10]^2 rho=2 dt=0.01, sech soliton + 1e-3 "
+                   "noise (seed 0), one time-step solve (setup + rhs + GMRES(30), tol 1e-10)",
+                   "d": 2, "n": 1023, "unknowns": p.N, "restart": 30, "tol": TOL,
+                   "precision": args.precision},
+        "iters": head["info"].iters,
+        "outer_iters": head["info"].outer_iters,
+        "relres_true": head["info"].relres_true,
+        "gpu_ms_per_step": round(1e3 * head["gpu"] / steps, 4),
+        "alg_bytes_per_step": int(total_bytes),
+        "alg_gbs_whole_step": round(total_bytes / (step_ms * 1e-3) / 1e9, 1),
+        "roofline": roofline,
+        other: {"value": round(steps / results[other]["wall"], 2),
+                "ms_per_step": round(1e3 * results[other]["wall"] / steps, 4),
+                "iters": results[other]["info"].iters,
+                "outer_iters": results[other]["info"].outer_iters,
+                "relres_true": results[other]["info"].relres_true,
+                "dominant_kernel": results[other]["prof"][0]["name"],
+                "dominant_gbs": round(results[other]["prof"][0]["gbs"], 1)},
+        "kernels": [{k: (round(v, 3) if isinstance(v, float) else v)
+                     for k, v in r.items() if k in ("name", "launches", "avg_us", "gbs", "ms_per_step")}
+                    for r in head["prof"][:8]],
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle), ~%.0f s" % args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -171,6 +171,24 @@ int fnls_step(fnls_ctx *ctx, const fnls_c128 *u_prev, const fnls_c128 *u_cur, fn
 int fnls_first_step(fnls_ctx *ctx, const fnls_c128 *u0, fnls_c128 *u1, const fnls_opts *opts,
                     fnls_info *info);
 
+/* Per-kernel timing (optional instrumentation, used by the benchmark).
+ * fnls_timing(ctx, 1) clears earlier records and brackets every following
+ * kernel launch of this context with a pair of HIP events on its stream;
+ * fnls_timing(ctx, 0) stops recording.  fnls_timing_report waits for the
+ * stream and writes one entry per kernel class (at most max_entries): the
+ * number of launches, their summed event time in milliseconds, and their
+ * summed algorithmic bytes (every vector a launch must read once and write
+ * once).  Returns the number of entries written, or a negative status. */
+typedef struct {
+    char name[64];
+    int launches;
+    double total_ms;
+    double bytes;
+} fnls_kernel_stat;
+
+int fnls_timing(fnls_ctx *ctx, int enable);
+int fnls_timing_report(fnls_ctx *ctx, fnls_kernel_stat *out, int max_entries);
+
 /* Last error message of this context ("" if none); valid until the next call. */
 const char *fnls_last_error(const fnls_ctx *ctx);
 

@@ -134,6 +134,18 @@ struct fnls_ctx {
     HostStatus* hs = nullptr;       // pinned, device-written
     HostStatus* hs_dev = nullptr;
     hipEvent_t ev[kEvents] = {};
+    // optional per-launch timing (fnls_timing / fnls_timing_report)
+    struct TimingRec {
+        int cls;
+        hipEvent_t a, b;
+        double bytes;
+    };
+    int timing = 0;
+    std::vector<TimingRec> recs;
+    std::vector<hipEvent_t> evpool;
+    size_t evused = 0;
+    std::vector<std::string> class_names;
+    int cur_k = 0;   // basis size of the combination being formed (byte accounting)
 
     template <typename T> T* at(size_t off) { return reinterpret_cast<T*>(ws + off); }
     GmresState* st() { return at<GmresState>(lay.state); }
@@ -157,6 +169,47 @@ static int set_err(fnls_ctx* c, int code, const char* fmt, ...) {
         if (e_ != hipSuccess)                                                                     \
             return set_err(ctx, FNLS_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));   \
     } while (0)
+
+// ---------------------------------------------------------------------------
+// optional per-launch timing with HIP events
+// ---------------------------------------------------------------------------
+namespace {
+
+hipEvent_t pool_event(fnls_ctx* c) {
+    if (c->evused == c->evpool.size()) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        c->evpool.push_back(e);
+    }
+    return c->evpool[c->evused++];
+}
+
+int class_id(fnls_ctx* c, const std::string& name) {
+    for (size_t i = 0; i < c->class_names.size(); ++i)
+        if (c->class_names[i] == name) return (int)i;
+    c->class_names.push_back(name);
+    return (int)c->class_names.size() - 1;
+}
+
+// Begin a timed launch; returns the record index or -1 when timing is off.
+int timing_begin(fnls_ctx* c, const std::string& name, double bytes) {
+    if (!c->timing) return -1;
+    fnls_ctx::TimingRec r;
+    r.cls = class_id(c, name);
+    r.a = pool_event(c);
+    r.b = pool_event(c);
+    r.bytes = bytes;
+    if (!r.a || !r.b) return -1;
+    (void)hipEventRecord(r.a, c->stream);
+    c->recs.push_back(r);
+    return (int)c->recs.size() - 1;
+}
+
+void timing_end(fnls_ctx* c, int rec) {
+    if (rec >= 0) (void)hipEventRecord(c->recs[rec].b, c->stream);
+}
+
+}  // namespace
 
 // ---------------------------------------------------------------------------
 // pass sequencing
@@ -195,8 +248,45 @@ PassArgs base_args(fnls_ctx* c, bool fp64, int axis, const Geo& g) {
     return a;
 }
 
+std::string pass_name(bool fp64, const PassVariant& v, int axis) {
+    std::string s = fp64 ? "pass64." : "pass32.";
+    static const char* inm[] = {"", "basis.", "combo."};
+    s += inm[v.inm];
+    if (v.ops & P_DST1) s += "dst";
+    if (v.ops & P_DIV) s += "_div";
+    if (v.ops & P_DST2) s += "_dst";
+    if (v.ops & P_SCALE) s += "_scale";
+    static const char* zm[] = {"", "_z", "_xset", "_xadd"};
+    s += zm[v.zm];
+    if (v.ops & P_TOEP) s += (v.ops & ~P_TOEP) ? "_toep" : "toep";
+    static const char* om[] = {"", "_first", "_next"};
+    s += om[v.outm];
+    static const char* fm[] = {"", "_wdots", "_resid"};
+    s += fm[v.fin];
+    s += ".ax" + std::to_string(axis);
+    return s;
+}
+
+// Algorithmic bytes of one launch: every vector the pass must read once and
+// write once (line data, D, accumulators, basis vectors of the dot products).
+double pass_bytes(fnls_ctx* c, bool fp64, const PassVariant& v, const PassArgs& a) {
+    const double N = (double)c->N, e = fp64 ? 16.0 : 8.0, dsz = fp64 ? 8.0 : 4.0;
+    double b = (v.inm == IN_COMBO) ? c->cur_k * e * N : e * N;
+    if ((v.ops & P_SCALE) || v.outm == OUT_ACC_FIRST) b += dsz * N;
+    if (v.zm == Z_WRITE) b += e * N;
+    if (v.zm == Z_XSET) b += 16.0 * N;
+    if (v.zm == Z_XADD) b += (a.first_cycle ? 16.0 : 32.0) * N;
+    if (v.outm == OUT_ACC_NEXT) b += e * N;
+    if (v.fin == FIN_WRITE && a.out) b += e * N;
+    if (v.fin == FIN_WDOTS) b += e * N + (a.basis_j + 1) * e * N;
+    if (v.fin == FIN_RESID) b += 32.0 * N + (a.r32 ? 8.0 * N : 0.0);
+    return b;
+}
+
 int run_pass(fnls_ctx* c, bool fp64, int axis, PassVariant v, PassArgs& a, const Geo& g) {
+    const int rec = c->timing ? timing_begin(c, pass_name(fp64, v, axis), pass_bytes(c, fp64, v, a)) : -1;
     hipError_t e = launch_pass(fp64 ? 1 : 0, v, a, g.blocks, g.lds, c->stream);
+    timing_end(c, rec);
     if (e != hipSuccess)
         return set_err(c, FNLS_ERR_HIP, "pass launch (axis %d, ops %d) failed: %s", axis, v.ops, hipGetErrorString(e));
     return FNLS_OK;
@@ -378,8 +468,15 @@ int arnoldi_step(fnls_ctx* c, bool fp64, Bufs& b, int j) {
     s.hs = c->hs_dev;
     s.check_active = 1;
     const int blocks = stream_blocks(c->N);
+    const double cgs_bytes = (2.0 + (j + 1)) * (fp64 ? 16.0 : 8.0) * (double)c->N;
+    int rec = c->timing ? timing_begin(c, fp64 ? "cgs64.update_dots" : "cgs32.update_dots", cgs_bytes) : -1;
     hipError_t e = launch_cgs(fp64 ? 1 : 0, 0, s, blocks, c->stream);
-    if (e == hipSuccess) e = launch_cgs(fp64 ? 1 : 0, 1, s, blocks, c->stream);
+    timing_end(c, rec);
+    if (e == hipSuccess) {
+        rec = c->timing ? timing_begin(c, fp64 ? "cgs64.update_norm_givens" : "cgs32.update_norm_givens", cgs_bytes) : -1;
+        e = launch_cgs(fp64 ? 1 : 0, 1, s, blocks, c->stream);
+        timing_end(c, rec);
+    }
     if (e != hipSuccess) return set_err(c, FNLS_ERR_HIP, "cgs launch failed: %s", hipGetErrorString(e));
     return FNLS_OK;
 }
@@ -521,6 +618,7 @@ int run_cycle(fnls_ctx* c, bool fp64, Bufs& b, int restart, int lookahead, int* 
         }
         if (hs.stopped || waited >= restart) break;
     }
+    c->cur_k = hs.total - c->cur_k;   // iterations of this cycle (caller set cur_k = total before)
     // let any speculative (inactive) iterations drain before the final passes
     return FNLS_OK;
 }
@@ -558,6 +656,7 @@ int solve_impl(fnls_ctx* c, const fnls_c128* b, fnls_c128* x, const fnls_opts* o
     while (true) {
         Bufs bf = bufs(c, fp64, first ? (const void*)b : (const void*)c->at<double2>(c->lay.r64));
         int done = 0;
+        c->cur_k = c->hs->total;
         int rc = run_cycle(c, fp64, bf, restart, std::max(0, o->lookahead), &done);
         if (rc != FNLS_OK) return rc;
         if (done) {
@@ -676,6 +775,7 @@ void fnls_destroy(fnls_ctx* c) {
     for (int i = 0; i < kEvents; ++i)
         if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
     if (c->hs) (void)hipHostFree(c->hs);
+    for (auto e : c->evpool) (void)hipEventDestroy(e);
     delete c;
 }
 
@@ -904,6 +1004,37 @@ int fnls_first_step(fnls_ctx* c, const fnls_c128* u0, fnls_c128* u1, const fnls_
     c->tscale = 1.0;
     c->have_D = 0;   // D belongs to the starter system; the next step recomputes it
     return rc;
+}
+
+int fnls_timing(fnls_ctx* c, int enable) {
+    if (!c) return FNLS_ERR_INVALID_ARG;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->recs.clear();
+    c->evused = 0;
+    c->timing = enable ? 1 : 0;
+    return FNLS_OK;
+}
+
+int fnls_timing_report(fnls_ctx* c, fnls_kernel_stat* out, int max_entries) {
+    if (!c || (!out && max_entries > 0) || max_entries < 0) return FNLS_ERR_INVALID_ARG;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const int ncls = (int)c->class_names.size();
+    std::vector<fnls_kernel_stat> agg(ncls);
+    for (int i = 0; i < ncls; ++i) {
+        std::memset(&agg[i], 0, sizeof(fnls_kernel_stat));
+        std::snprintf(agg[i].name, sizeof agg[i].name, "%s", c->class_names[i].c_str());
+    }
+    for (const auto& r : c->recs) {
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, r.a, r.b));
+        agg[r.cls].launches += 1;
+        agg[r.cls].total_ms += ms;
+        agg[r.cls].bytes += r.bytes;
+    }
+    int k = 0;
+    for (int i = 0; i < ncls && k < max_entries; ++i)
+        if (agg[i].launches > 0) out[k++] = agg[i];
+    return k;
 }
 
 }  // extern "C"

@@ -48,6 +48,11 @@ class Info(ctypes.Structure):
                 ("relres_hist", ctypes.c_double * 64)]
 
 
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 64), ("launches", ctypes.c_int),
+                ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
 @dataclass
 class SolveInfo:
     iters: int
@@ -95,6 +100,10 @@ def lib() -> ctypes.CDLL:
     L.fnls_last_error.restype = ctypes.c_char_p
     L.fnls_status_string.argtypes = [ci]
     L.fnls_status_string.restype = ctypes.c_char_p
+    L.fnls_timing.argtypes = [vp, ci]
+    L.fnls_timing.restype = ci
+    L.fnls_timing_report.argtypes = [vp, ctypes.POINTER(KernelStat), ci]
+    L.fnls_timing_report.restype = ci
     _lib = L
     return L
 
@@ -237,6 +246,17 @@ class Solver:
         self._check(lib().fnls_first_step(self._ctx, self._vec(u0, "u0"), self._vec(u1, "u1"),
                                           ctypes.byref(o), ctypes.byref(info)))
         return u1, self._info(info)
+
+    def timing(self, enable: bool):
+        """Start (clearing earlier records) or stop per-launch event timing."""
+        self._check(lib().fnls_timing(self._ctx, 1 if enable else 0))
+
+    def timing_report(self):
+        """Per kernel class: launches, summed event milliseconds, algorithmic bytes."""
+        arr = (KernelStat * 256)()
+        k = self._check(lib().fnls_timing_report(self._ctx, arr, 256))
+        return [dict(name=arr[i].name.decode(), launches=arr[i].launches,
+                     total_ms=arr[i].total_ms, bytes=arr[i].bytes) for i in range(k)]
 
     def close(self):
         if getattr(self, "_ctx", None):
