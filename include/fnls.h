@@ -189,6 +189,15 @@ typedef struct {
 int fnls_timing(fnls_ctx *ctx, int enable);
 int fnls_timing_report(fnls_ctx *ctx, fnls_kernel_stat *out, int max_entries);
 
+/* Tuning of the transform passes (optional; the defaults suit m = n + 1 =
+ * 1024).  For the given precision (fnls_precision) and axis kind (strided = 0:
+ * the contiguous last axis, 1: the other axes): rmax in {4, 8, 16} is the
+ * largest FFT radix, so m / rmax threads work on one line; `lines` (a power
+ * of two) is the number of lines per workgroup at m = 1024.  Settings that
+ * would exceed the workgroup size or LDS limits are rejected or clamped.
+ * Waits for the context's stream. */
+int fnls_set_pass_config(fnls_ctx *ctx, int precision, int strided, int rmax, int lines);
+
 /* Last error message of this context ("" if none); valid until the next call. */
 const char *fnls_last_error(const fnls_ctx *ctx);
 

@@ -21,7 +21,12 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kEvents = 8;
-constexpr size_t kStaticLds = 12 * 1024;   // static LDS of k_pass (reduction scratch, line table)
+constexpr size_t kStaticLds = 8 * 1024;    // static LDS of k_pass (reduction scratch)
+// lines per workgroup of the transform passes at m = 1024 (more for smaller m)
+constexpr int kRowLines = 1;
+constexpr int kColLines = 4;
+// producers with more workgroups than this get an explicit reduction kernel
+constexpr int kRedundantMax = 1024;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -38,22 +43,56 @@ long long ipow(int n, int d) {
 }
 
 struct Geo {
-    int G, L, blocks;
+    int G, L, blocks, rmax;
     size_t lds;
     long long stride, nlines;
 };
 
-Geo pass_geo(int d, int n, int axis, bool fp64, size_t max_dyn_lds) {
+// Transform-pass configuration per (precision, axis kind): the largest FFT
+// radix (threads per line G = m / rmax) and the lines per workgroup at
+// m = 1024 (scaled up for shorter lines so a workgroup keeps its size).
+struct PassConfig {
+    int rmax[2][2];    // [fp64][strided axis]
+    int lines[2][2];
+};
+
+PassConfig default_pass_config() {
+    // measured best at d = 2, n = 1023 (FP32 index 0, FP64 index 1)
+    PassConfig p;
+    p.rmax[0][0] = 4;
+    p.lines[0][0] = 1;
+    p.rmax[0][1] = 8;
+    p.lines[0][1] = 4;
+    p.rmax[1][0] = 4;
+    p.lines[1][0] = 2;
+    p.rmax[1][1] = 8;
+    p.lines[1][1] = 4;
+    return p;
+}
+
+int pass_threads_max(int rmax) { return rmax == 16 ? 256 : 4096 / rmax; }
+
+Geo pass_geo(int d, int n, int axis, bool fp64, size_t max_dyn_lds, const PassConfig& cfg) {
     Geo g;
     const int m = n + 1;
-    g.G = std::max(1, std::min(64, m / 16));
+    const bool contiguous = (axis == d - 1);
+    const int col = contiguous ? 0 : 1;
+    g.rmax = cfg.rmax[fp64 ? 1 : 0][col];
+    g.G = std::max(1, m / g.rmax);
+    const int tmax = pass_threads_max(g.rmax);
     const size_t elem = fp64 ? 16 : 8;
-    const size_t perline = (size_t)(2 * m + 2) * elem;
-    int L = 256 / g.G;
-    while (L > 1 && (size_t)L * perline > max_dyn_lds) L /= 2;
+    // per line: buffers A and B of padded_len(m) slots; per workgroup: the W_m table
+    const size_t perline = (size_t)2 * (m + (m >> 3) + 1) * elem;
+    // quarter twiddle table (padded) + per-line base offset (8 B) and Lambda (elem/2 B)
+    const int q4 = m >= 4 ? m / 4 : 1;
+    const size_t table = (size_t)(m >= 4 ? (q4 - 1) + ((q4 - 1) >> 3) + 1 : 1) * elem;
+    const int gref = 1024 / g.rmax;
+    int L = cfg.lines[fp64 ? 1 : 0][col] * std::max(1, gref / g.G);
+    L = std::max(1, std::min(L, tmax / g.G));
+    while (L > 1 && (size_t)L * (perline + 8 + elem / 2) + table > max_dyn_lds) L /= 2;
     while (g.G * L < 64) L *= 2;   // whole wavefronts
     g.L = L;
-    g.lds = (size_t)L * perline;
+    g.lds = (size_t)L * perline + table + (size_t)L * (8 + elem / 2);
     g.stride = ipow(n, d - 1 - axis);
     g.nlines = ipow(n, d - 1);
     g.blocks = (int)((g.nlines + L - 1) / L);
@@ -66,13 +105,13 @@ int stream_blocks(long long N) {
 
 struct Layout {
     size_t tw64, tw32, syme64, symo64, lam64, syme32, symo32, lam32;
-    size_t state, partials, D64, D32;
+    size_t state, p1, p2, p3, pr, px, D64, D32;
     size_t t1, t2, zb, acc, r64, bbuf, V;
     size_t total;
     int pstride;
 };
 
-Layout make_layout(int d, int n, int restart, size_t max_dyn_lds) {
+Layout make_layout(int d, int n, int restart) {
     Layout l;
     const int m = n + 1;
     const long long N = ipow(n, d);
@@ -91,13 +130,16 @@ Layout make_layout(int d, int n, int restart, size_t max_dyn_lds) {
     l.symo32 = take((size_t)m * 4);
     l.lam32 = take((size_t)m * 4);
     l.state = take(sizeof(GmresState));
-    int pmax = stream_blocks(N);
-    for (int ax = 0; ax < d; ++ax) {
-        pmax = std::max(pmax, pass_geo(d, n, ax, true, max_dyn_lds).blocks);
-        pmax = std::max(pmax, pass_geo(d, n, ax, false, max_dyn_lds).blocks);
-    }
+    // partial sums: at most one workgroup per line (any pass configuration)
+    // or per streaming chunk
+    const int pmax = (int)std::max<long long>(stream_blocks(N), ipow(n, d - 1));
     l.pstride = pmax;
-    l.partials = take((size_t)(kMaxRestart + 2) * pmax * 16);
+    const size_t pwide = (size_t)(kMaxRestart + 2) * pmax * 16;
+    l.p1 = take(pwide);
+    l.p2 = take(pwide);
+    l.p3 = take((size_t)pmax * 16);
+    l.pr = take((size_t)pmax * 16);
+    l.px = take((size_t)(kMaxRestart + 2) * 16);
     l.D64 = take((size_t)N * 8);
     l.D32 = take((size_t)N * 4);
     l.t1 = take((size_t)N * 16);
@@ -146,6 +188,7 @@ struct fnls_ctx {
     size_t evused = 0;
     std::vector<std::string> class_names;
     int cur_k = 0;   // basis size of the combination being formed (byte accounting)
+    PassConfig pcfg = default_pass_config();
 
     template <typename T> T* at(size_t off) { return reinterpret_cast<T*>(ws + off); }
     GmresState* st() { return at<GmresState>(lay.state); }
@@ -227,6 +270,8 @@ PassArgs base_args(fnls_ctx* c, bool fp64, int axis, const Geo& g) {
     a.L = g.L;
     a.lgG = 0;
     while ((1 << a.lgG) < g.G) ++a.lgG;
+    a.lgm = 0;
+    while ((1 << a.lgm) < c->m) ++a.lgm;
     a.lgL = 0;
     while ((1 << a.lgL) < g.L) ++a.lgL;
     // ceil(2^32 / n) for n >= 2 (n = 1 is handled in the kernel without it)
@@ -241,7 +286,7 @@ PassArgs base_args(fnls_ctx* c, bool fp64, int axis, const Geo& g) {
     a.D = fp64 ? (const void*)c->at<double>(c->lay.D64) : (const void*)c->at<float>(c->lay.D32);
     a.tscale = c->tscale;
     a.omega = c->omega;
-    a.partials = c->at<double2>(c->lay.partials);
+    a.pout = c->at<double2>(c->lay.p1);
     a.pstride = c->lay.pstride;
     a.st = c->st();
     a.hs = c->hs_dev;
@@ -284,6 +329,7 @@ double pass_bytes(fnls_ctx* c, bool fp64, const PassVariant& v, const PassArgs& 
 }
 
 int run_pass(fnls_ctx* c, bool fp64, int axis, PassVariant v, PassArgs& a, const Geo& g) {
+    v.rmax = g.rmax;
     const int rec = c->timing ? timing_begin(c, pass_name(fp64, v, axis), pass_bytes(c, fp64, v, a)) : -1;
     hipError_t e = launch_pass(fp64 ? 1 : 0, v, a, g.blocks, g.lds, c->stream);
     timing_end(c, rec);
@@ -330,7 +376,7 @@ int precond_front(fnls_ctx* c, bool fp64, int inm, const void* src, int basis_j,
     void* pingpong[2] = {b.t1, b.t2};
     int pp = 0;
     auto step = [&](int axis, int ops) -> int {
-        Geo g = pass_geo(d, c->n, axis, fp64, c->max_dyn_lds);
+        Geo g = pass_geo(d, c->n, axis, fp64, c->max_dyn_lds, c->pcfg);
         PassArgs a = base_args(c, fp64, axis, g);
         a.in = cur_in;
         a.v0 = b.v0;
@@ -361,7 +407,7 @@ int toeplitz_tail(fnls_ctx* c, bool fp64, const void* x, void* acc, int fin, voi
                   int check_active) {
     const int d = c->d;
     for (int ax = d - 2; ax >= 0; --ax) {
-        Geo g = pass_geo(d, c->n, ax, fp64, c->max_dyn_lds);
+        Geo g = pass_geo(d, c->n, ax, fp64, c->max_dyn_lds, c->pcfg);
         PassArgs a = base_args(c, fp64, ax, g);
         a.in = x;
         a.acc_in = acc;
@@ -377,6 +423,7 @@ int toeplitz_tail(fnls_ctx* c, bool fp64, const void* x, void* acc, int fin, voi
         a.r64 = tmpl.r64;
         a.r32 = tmpl.r32;
         a.ir = tmpl.ir;
+        if (tmpl.pout) a.pout = tmpl.pout;
         PassVariant v{IN_PLAIN, P_TOEP, Z_NONE, OUT_ACC_NEXT, f};
         int rc = run_pass(c, fp64, ax, v, a, g);
         if (rc != FNLS_OK) return rc;
@@ -387,7 +434,7 @@ int toeplitz_tail(fnls_ctx* c, bool fp64, const void* x, void* acc, int fin, voi
 // y = (cD D + i ci I + cT T_d) x, all FP64 (used by apply_A and rhs).
 int matvec64(fnls_ctx* c, const void* x, void* y, double cD, double ci, double cT) {
     const int d = c->d;
-    Geo g = pass_geo(d, c->n, d - 1, true, c->max_dyn_lds);
+    Geo g = pass_geo(d, c->n, d - 1, true, c->max_dyn_lds, c->pcfg);
     PassArgs a = base_args(c, true, d - 1, g);
     a.in = x;
     a.cD = cD;
@@ -399,7 +446,7 @@ int matvec64(fnls_ctx* c, const void* x, void* y, double cD, double ci, double c
     if (rc != FNLS_OK || d == 1) return rc;
     void* acc = c->at<char>(c->lay.acc);
     for (int ax = d - 2; ax >= 0; --ax) {
-        Geo g2 = pass_geo(d, c->n, ax, true, c->max_dyn_lds);
+        Geo g2 = pass_geo(d, c->n, ax, true, c->max_dyn_lds, c->pcfg);
         PassArgs a2 = base_args(c, true, ax, g2);
         a2.in = x;
         a2.acc_in = acc;
@@ -412,6 +459,30 @@ int matvec64(fnls_ctx* c, const void* x, void* y, double cD, double ci, double c
     return FNLS_OK;
 }
 
+// One-workgroup decision / reduction kernel (k_finish).
+int run_finish(fnls_ctx* c, const StreamArgs& s, const char* name) {
+    const int rec = c->timing ? timing_begin(c, name, 16.0 * s.pin_nb) : -1;
+    hipError_t e = launch_finish(s, c->stream);
+    timing_end(c, rec);
+    if (e != hipSuccess) return set_err(c, FNLS_ERR_HIP, "finish launch failed: %s", hipGetErrorString(e));
+    return FNLS_OK;
+}
+
+// When the producer of s.pin had many workgroups, sum its nv partials first
+// (one workgroup) so that consumer workgroups read a single entry per value.
+int reduce_if_wide(fnls_ctx* c, StreamArgs& s, int nv) {
+    if (s.pin_nb <= kRedundantMax) return FNLS_OK;
+    StreamArgs r = s;
+    r.mode = 3;
+    r.nv = nv;
+    r.pout = c->at<double2>(c->lay.px);
+    int rc = run_finish(c, r, "finish.reduce");
+    if (rc != FNLS_OK) return rc;
+    s.pin = c->at<double2>(c->lay.px);
+    s.pin_nb = 1;
+    return FNLS_OK;
+}
+
 // One Arnoldi step j: w = A Ptilde^{-1} v_j into basis slot j+1, first-round
 // dot products, then the two Gram-Schmidt update kernels.
 int arnoldi_step(fnls_ctx* c, bool fp64, Bufs& b, int j) {
@@ -421,7 +492,7 @@ int arnoldi_step(fnls_ctx* c, bool fp64, Bufs& b, int j) {
     void* w = (char*)b.vbase + (size_t)j * c->N * esz;
     int rc;
     if (d == 1) {
-        Geo g = pass_geo(d, c->n, 0, fp64, c->max_dyn_lds);
+        Geo g = pass_geo(d, c->n, 0, fp64, c->max_dyn_lds, c->pcfg);
         PassArgs a = base_args(c, fp64, 0, g);
         a.in = vj;
         a.v0 = b.v0;
@@ -437,7 +508,7 @@ int arnoldi_step(fnls_ctx* c, bool fp64, Bufs& b, int j) {
     } else {
         void* t;
         if ((rc = precond_front(c, fp64, IN_BASIS, vj, j, b, &t, 1)) != FNLS_OK) return rc;
-        Geo g = pass_geo(d, c->n, d - 1, fp64, c->max_dyn_lds);
+        Geo g = pass_geo(d, c->n, d - 1, fp64, c->max_dyn_lds, c->pcfg);
         PassArgs a = base_args(c, fp64, d - 1, g);
         a.in = t;
         a.zout = b.zb;
@@ -462,36 +533,69 @@ int arnoldi_step(fnls_ctx* c, bool fp64, Bufs& b, int j) {
     s.v0 = b.v0;
     s.vbase = b.vbase;
     s.nv = j + 1;
-    s.partials = c->at<double2>(c->lay.partials);
     s.pstride = c->lay.pstride;
     s.st = c->st();
     s.hs = c->hs_dev;
     s.check_active = 1;
+    const int nb1 = pass_geo(d, c->n, 0, fp64, c->max_dyn_lds, c->pcfg).blocks;
     const int blocks = stream_blocks(c->N);
-    const double cgs_bytes = (2.0 + (j + 1)) * (fp64 ? 16.0 : 8.0) * (double)c->N;
+    const double esz_d = fp64 ? 16.0 : 8.0;
+    const double cgs_bytes = (2.0 + (j + 1)) * esz_d * (double)c->N;
+    // first Gram-Schmidt update (consumes the dots of the last pass)
+    s.pin = c->at<double2>(c->lay.p1);
+    s.pin_nb = nb1;
+    if ((rc = reduce_if_wide(c, s, j + 2)) != FNLS_OK) return rc;
+    s.pout = c->at<double2>(c->lay.p2);
     int rec = c->timing ? timing_begin(c, fp64 ? "cgs64.update_dots" : "cgs32.update_dots", cgs_bytes) : -1;
     hipError_t e = launch_cgs(fp64 ? 1 : 0, 0, s, blocks, c->stream);
     timing_end(c, rec);
-    if (e == hipSuccess) {
-        rec = c->timing ? timing_begin(c, fp64 ? "cgs64.update_norm_givens" : "cgs32.update_norm_givens", cgs_bytes) : -1;
-        e = launch_cgs(fp64 ? 1 : 0, 1, s, blocks, c->stream);
-        timing_end(c, rec);
-    }
     if (e != hipSuccess) return set_err(c, FNLS_ERR_HIP, "cgs launch failed: %s", hipGetErrorString(e));
-    return FNLS_OK;
+    // second update (reorthogonalisation)
+    s.pin = c->at<double2>(c->lay.p2);
+    s.pin_nb = blocks;
+    if ((rc = reduce_if_wide(c, s, j + 1)) != FNLS_OK) return rc;
+    s.pout = c->at<double2>(c->lay.p3);
+    rec = c->timing ? timing_begin(c, fp64 ? "cgs64.update_norm" : "cgs32.update_norm", cgs_bytes) : -1;
+    e = launch_cgs(fp64 ? 1 : 0, 1, s, blocks, c->stream);
+    timing_end(c, rec);
+    if (e != hipSuccess) return set_err(c, FNLS_ERR_HIP, "cgs launch failed: %s", hipGetErrorString(e));
+    // Givens step and stopping decision
+    s.pin = c->at<double2>(c->lay.p3);
+    s.pin_nb = blocks;
+    if ((rc = reduce_if_wide(c, s, 1)) != FNLS_OK) return rc;
+    s.mode = 1;
+    return run_finish(c, s, "finish.givens");
 }
 
 // End of a cycle: x (+)= Ptilde^{-1} (sum_i y_i v_i).  FP64: the recomputed
 // residual r = b - A x follows in the same passes.  FP32 (IR): x is updated
 // in FP64 from the FP32 correction, then the FP64 residual chain runs.
+int cycle_final_passes(fnls_ctx* c, bool fp64, Bufs& b, const void* b64, void* x, int first);
+
 int cycle_final(fnls_ctx* c, bool fp64, Bufs& b, const void* b64, void* x, int first) {
+    int rc = cycle_final_passes(c, fp64, b, b64, x, first);
+    if (rc != FNLS_OK) return rc;
+    StreamArgs s;
+    std::memset(&s, 0, sizeof s);
+    s.pin = c->at<double2>(c->lay.pr);
+    s.pin_nb = pass_geo(c->d, c->n, 0, true, c->max_dyn_lds, c->pcfg).blocks;
+    s.pstride = c->lay.pstride;
+    s.st = c->st();
+    s.hs = c->hs_dev;
+    s.mode = 2;
+    s.ir = fp64 ? 0 : 1;
+    if ((rc = reduce_if_wide(c, s, 1)) != FNLS_OK) return rc;
+    return run_finish(c, s, "finish.residual");
+}
+
+int cycle_final_passes(fnls_ctx* c, bool fp64, Bufs& b, const void* b64, void* x, int first) {
     const int d = c->d;
     double2* r64 = c->at<double2>(c->lay.r64);
     float2* r32 = fp64 ? nullptr : c->at<float2>(c->lay.V);
     int rc;
     if (fp64) {
         if (d == 1) {
-            Geo g = pass_geo(d, c->n, 0, true, c->max_dyn_lds);
+            Geo g = pass_geo(d, c->n, 0, true, c->max_dyn_lds, c->pcfg);
             PassArgs a = base_args(c, true, 0, g);
             a.v0 = b.v0;
             a.vbase = b.vbase;
@@ -502,12 +606,13 @@ int cycle_final(fnls_ctx* c, bool fp64, Bufs& b, const void* b64, void* x, int f
             a.cT = -1.0;
             a.b64 = (const double2*)b64;
             a.r64 = r64;
+            a.pout = c->at<double2>(c->lay.pr);
             PassVariant v{IN_COMBO, P_DST1 | P_DIV | P_DST2 | P_SCALE | P_TOEP, Z_XADD, OUT_ACC_FIRST, FIN_RESID};
             return run_pass(c, true, 0, v, a, g);
         }
         void* t;
         if ((rc = precond_front(c, true, IN_COMBO, nullptr, 0, b, &t, 0)) != FNLS_OK) return rc;
-        Geo g = pass_geo(d, c->n, d - 1, true, c->max_dyn_lds);
+        Geo g = pass_geo(d, c->n, d - 1, true, c->max_dyn_lds, c->pcfg);
         PassArgs a = base_args(c, true, d - 1, g);
         a.in = t;
         a.x64 = (double2*)x;
@@ -522,11 +627,12 @@ int cycle_final(fnls_ctx* c, bool fp64, Bufs& b, const void* b64, void* x, int f
         std::memset(&tmpl, 0, sizeof tmpl);
         tmpl.b64 = (const double2*)b64;
         tmpl.r64 = r64;
+        tmpl.pout = c->at<double2>(c->lay.pr);
         return toeplitz_tail(c, true, x, b.acc, FIN_RESID, nullptr, tmpl, 0);
     }
     // FP32 correction
     if (d == 1) {
-        Geo g = pass_geo(d, c->n, 0, false, c->max_dyn_lds);
+        Geo g = pass_geo(d, c->n, 0, false, c->max_dyn_lds, c->pcfg);
         PassArgs a = base_args(c, false, 0, g);
         a.v0 = b.v0;
         a.vbase = b.vbase;
@@ -537,7 +643,7 @@ int cycle_final(fnls_ctx* c, bool fp64, Bufs& b, const void* b64, void* x, int f
     } else {
         void* t;
         if ((rc = precond_front(c, false, IN_COMBO, nullptr, 0, b, &t, 0)) != FNLS_OK) return rc;
-        Geo g = pass_geo(d, c->n, d - 1, false, c->max_dyn_lds);
+        Geo g = pass_geo(d, c->n, d - 1, false, c->max_dyn_lds, c->pcfg);
         PassArgs a = base_args(c, false, d - 1, g);
         a.in = t;
         a.x64 = (double2*)x;
@@ -546,7 +652,7 @@ int cycle_final(fnls_ctx* c, bool fp64, Bufs& b, const void* b64, void* x, int f
         if ((rc = run_pass(c, false, d - 1, v, a, g)) != FNLS_OK) return rc;
     }
     // FP64 residual r = b - A x, with its complex64 copy as the next basis vector 0
-    Geo g = pass_geo(d, c->n, d - 1, true, c->max_dyn_lds);
+    Geo g = pass_geo(d, c->n, d - 1, true, c->max_dyn_lds, c->pcfg);
     PassArgs a = base_args(c, true, d - 1, g);
     a.in = x;
     a.cD = 1.0;
@@ -557,6 +663,7 @@ int cycle_final(fnls_ctx* c, bool fp64, Bufs& b, const void* b64, void* x, int f
         a.r64 = r64;
         a.r32 = r32;
         a.ir = 1;
+        a.pout = c->at<double2>(c->lay.pr);
         PassVariant v{IN_PLAIN, P_TOEP, Z_NONE, OUT_ACC_FIRST, FIN_RESID};
         return run_pass(c, true, 0, v, a, g);
     }
@@ -570,6 +677,7 @@ int cycle_final(fnls_ctx* c, bool fp64, Bufs& b, const void* b64, void* x, int f
     tmpl.r64 = r64;
     tmpl.r32 = r32;
     tmpl.ir = 1;
+    tmpl.pout = c->at<double2>(c->lay.pr);
     return toeplitz_tail(c, true, x, acc64, FIN_RESID, nullptr, tmpl, 0);
 }
 
@@ -646,11 +754,23 @@ int solve_impl(fnls_ctx* c, const fnls_c128* b, fnls_c128* x, const fnls_opts* o
     s.N = c->N;
     s.b64 = reinterpret_cast<const double2*>(b);
     s.r32 = fp64 ? nullptr : c->at<float2>(c->lay.V);
-    s.partials = c->at<double2>(c->lay.partials);
+    s.pout = c->at<double2>(c->lay.pr);
     s.pstride = c->lay.pstride;
     s.st = c->st();
     s.hs = c->hs_dev;
-    HIPCHK(c, launch_prepare(s, std::min(1024, stream_blocks(c->N)), c->stream));
+    {
+        const int rec = c->timing ? timing_begin(c, "prepare", (fp64 ? 16.0 : 24.0) * (double)c->N) : -1;
+        hipError_t e = launch_prepare(s, stream_blocks(c->N), c->stream);
+        timing_end(c, rec);
+        if (e != hipSuccess) return set_err(c, FNLS_ERR_HIP, "prepare launch failed: %s", hipGetErrorString(e));
+        StreamArgs f = s;
+        f.pin = c->at<double2>(c->lay.pr);
+        f.pin_nb = stream_blocks(c->N);
+        f.mode = 0;
+        int rc0 = reduce_if_wide(c, f, 1);
+        if (rc0 == FNLS_OK) rc0 = run_finish(c, f, "finish.prepare");
+        if (rc0 != FNLS_OK) return rc0;
+    }
     int first = 1;
     int status = FNLS_OK;
     while (true) {
@@ -726,7 +846,7 @@ const char* fnls_status_string(int s) {
 size_t fnls_workspace_bytes(int d, int n, int restart) {
     if (d < 1 || d > 3 || !valid_n(n) || restart < 1 || restart > kMaxRestart) return 0;
     // the LDS budget only changes the partial-sum stride; size for the smallest budget
-    return make_layout(d, n, restart, 48 * 1024).total;
+    return make_layout(d, n, restart).total;
 }
 
 int fnls_create(fnls_ctx** out, int device, void* hip_stream) {
@@ -796,13 +916,13 @@ int fnls_assemble(fnls_ctx* c, double alpha, double rho, int d, int n, double h,
     // largest restart length that fits
     int cap = 0;
     for (int r = kMaxRestart; r >= 1; --r) {
-        if (make_layout(d, n, r, c->max_dyn_lds).total <= workspace_bytes) {
+        if (make_layout(d, n, r).total <= workspace_bytes) {
             cap = r;
             break;
         }
     }
     if (cap < 1) return set_err(c, FNLS_ERR_WORKSPACE, "workspace too small (need %zu bytes for restart 1)",
-                                make_layout(d, n, 1, c->max_dyn_lds).total);
+                                make_layout(d, n, 1).total);
     HIPCHK(c, hipSetDevice(c->device));
     c->alpha = alpha;
     c->rho = rho;
@@ -815,7 +935,7 @@ int fnls_assemble(fnls_ctx* c, double alpha, double rho, int d, int n, double h,
     c->ws = reinterpret_cast<char*>(workspace);
     c->ws_bytes = workspace_bytes;
     c->restart_cap = cap;
-    c->lay = make_layout(d, n, cap, c->max_dyn_lds);
+    c->lay = make_layout(d, n, cap);
     c->tscale = 1.0;
     c->have_D = 0;
 
@@ -922,7 +1042,7 @@ int fnls_apply_precond(fnls_ctx* c, const fnls_c128* r, fnls_c128* z) {
     HIPCHK(c, hipSetDevice(c->device));
     Bufs b = bufs(c, true, nullptr);
     if (c->d == 1) {
-        Geo g = pass_geo(1, c->n, 0, true, c->max_dyn_lds);
+        Geo g = pass_geo(1, c->n, 0, true, c->max_dyn_lds, c->pcfg);
         PassArgs a = base_args(c, true, 0, g);
         a.in = r;
         a.out = z;
@@ -931,7 +1051,7 @@ int fnls_apply_precond(fnls_ctx* c, const fnls_c128* r, fnls_c128* z) {
     }
     void* t;
     if ((rc = precond_front(c, true, IN_PLAIN, r, 0, b, &t, 0)) != FNLS_OK) return rc;
-    Geo g = pass_geo(c->d, c->n, c->d - 1, true, c->max_dyn_lds);
+    Geo g = pass_geo(c->d, c->n, c->d - 1, true, c->max_dyn_lds, c->pcfg);
     PassArgs a = base_args(c, true, c->d - 1, g);
     a.in = t;
     a.out = z;
@@ -1035,6 +1155,22 @@ int fnls_timing_report(fnls_ctx* c, fnls_kernel_stat* out, int max_entries) {
     for (int i = 0; i < ncls && k < max_entries; ++i)
         if (agg[i].launches > 0) out[k++] = agg[i];
     return k;
+}
+
+int fnls_set_pass_config(fnls_ctx* c, int precision, int strided, int rmax, int lines) {
+    if (!c) return FNLS_ERR_INVALID_ARG;
+    if ((precision != FNLS_FP64 && precision != FNLS_FP32_IR) || (strided != 0 && strided != 1))
+        return set_err(c, FNLS_ERR_INVALID_ARG, "precision / axis kind out of range");
+    if (rmax != 4 && rmax != 8 && rmax != 16) return set_err(c, FNLS_ERR_INVALID_ARG, "rmax must be 4, 8 or 16");
+    if (lines < 1 || lines > 64 || (lines & (lines - 1)) != 0)
+        return set_err(c, FNLS_ERR_INVALID_ARG, "lines must be a power of two in [1, 64]");
+    if ((1024 / rmax) * lines > pass_threads_max(rmax))
+        return set_err(c, FNLS_ERR_INVALID_ARG, "too many threads per workgroup for rmax %d", rmax);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const int f = precision == FNLS_FP64 ? 1 : 0;
+    c->pcfg.rmax[f][strided] = rmax;
+    c->pcfg.lines[f][strided] = lines;
+    return FNLS_OK;
 }
 
 }  // extern "C"

@@ -10,7 +10,7 @@ namespace fnls {
 // Largest restart length supported by the fixed-size Hessenberg state.
 constexpr int kMaxRestart = 64;
 // Elements per thread in the streaming (CGS update / setup) kernels.
-constexpr int kEpt = 8;
+constexpr int kEpt = 16;
 constexpr int kStreamThreads = 256;
 
 // GMRES state kept in device memory (inside the caller's workspace).  Only
@@ -75,6 +75,7 @@ enum ZMode { Z_NONE = 0, Z_WRITE = 1, Z_XSET = 2, Z_XADD = 3 };
 struct PassArgs {
     // geometry
     int n, m, d, axis;
+    int lgm;          // log2(m)
     int G;            // threads per line in the transform phases (power of two)
     int L;            // lines per workgroup (power of two)
     int lgG, lgL;     // log2 of G and L
@@ -106,7 +107,7 @@ struct PassArgs {
     void* r32;            // FIN_RESID: optional complex64 copy of the residual
     double cD, ci, cT;    // OUT_ACC_FIRST coefficients
     // reductions
-    double2* partials;    // [nv][pstride]
+    double2* pout;        // per-workgroup partials written here, layout [i][pstride]
     int pstride;
     GmresState* st;
     HostStatus* hs;
@@ -130,12 +131,15 @@ struct StreamArgs {
     // norm / prepare
     const double2* b64;
     void* r32;            // optional complex64 copy
-    double2* partials;
+    const double2* pin;   // partials of the producer kernel, layout [i][pstride]
+    int pin_nb;           // number of producer workgroups
+    double2* pout;        // this kernel's partials
     int pstride;
     GmresState* st;
     HostStatus* hs;
     int check_active;
     int mode;
+    int ir;               // k_finish residual decision: 1 = refinement step of FP32-IR
 };
 
 }  // namespace fnls

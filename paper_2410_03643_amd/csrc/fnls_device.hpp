@@ -177,139 +177,217 @@ template <int RAD, bool INV, typename C> __device__ __forceinline__ void dft(C* 
     }
 }
 
+// LDS layout of a line: slot s lives at pad(s) = s + s/8, so that eight
+// lanes storing with a stride of 4 or 8 slots (first radix-4 / radix-8 stage,
+// sine-transform output pass) hit eight distinct 16-byte bank groups.
+__device__ __forceinline__ int pad(int s) { return s + (s >> 3); }
+__host__ __device__ constexpr int padded_len(int m) { return m + (m >> 3) + 1; }   // slots 0..m
+
 // One Stockham (self-sorting, decimation in time) stage of radix RAD on one
 // line buffer X, computed in registers.  The caller places a barrier between
-// stage_load and stage_store (in-place update).  Ns is the product of the
-// radices of the earlier stages; tw[s] = W_{2m}^s.
-template <typename R, int RAD>
+// stage_load and stage_store (in-place update).  Ns = 2^lgNs is the product of
+// the radices of the earlier stages.  twl[q] = W_m^q (q < m/4) lives in LDS.
+template <typename R, int RAD, int RMAX>
 struct StageRegs {
-    cplx<R> v[16 / RAD][RAD];
+    cplx<R> v[RMAX / RAD][RAD];
 };
 
-template <typename R, int RAD, bool INV>
-__device__ __forceinline__ void stage_load(StageRegs<R, RAD>& g, const cplx<R>* X, int m, int Ns, int lt, int G,
-                                           const cplx<R>* __restrict__ tw) {
+// W_m^q for any q < m from the quarter table twl[q'] = W_m^{q'}, q' < m/4:
+// W_m^{q + t m/4} = (-i)^t W_m^q.
+template <typename R>
+__device__ __forceinline__ cplx<R> tw_quarter(const cplx<R>* twl, int q, int lgm) {
+    const int t = q >> (lgm - 2);
+    const cplx<R> w = twl[pad(q & ((1 << (lgm - 2)) - 1))];   // table stored padded
+    // (-i)^t w without divergent branches: odd t swaps (x, y) -> (y, -x),
+    // t >= 2 negates
+    const bool odd = t & 1;
+    const R sg = (t & 2) ? R(-1) : R(1);
+    const R x = odd ? w.y : w.x;
+    const R y = odd ? -w.x : w.y;
+    return cm<R>(sg * x, sg * y);
+}
+
+template <int RAD> struct Lg;
+template <> struct Lg<2> { static constexpr int v = 1; };
+template <> struct Lg<4> { static constexpr int v = 2; };
+template <> struct Lg<8> { static constexpr int v = 3; };
+template <> struct Lg<16> { static constexpr int v = 4; };
+
+template <typename R, int RAD, int RMAX, bool INV>
+__device__ __forceinline__ void stage_load(StageRegs<R, RAD, RMAX>& g, const cplx<R>* X, int lgm, int lgNs, int lt,
+                                           int G, const cplx<R>* twl) {
     using C = cplx<R>;
-    constexpr int PER = 16 / RAD;
-    const int nb = m / RAD;
+    constexpr int PER = RMAX / RAD;
+    const int nb = (1 << lgm) >> Lg<RAD>::v;
+    const int tsh = lgm - lgNs - Lg<RAD>::v;   // W_{Ns RAD}^q = W_m^{q << tsh}
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
         const int b = lt + q * G;
         if (b < nb) {
 #pragma unroll
-            for (int r = 0; r < RAD; ++r) g.v[q][r] = X[b + r * nb];
-            const int k = b & (Ns - 1);
-            const int step = k * ((2 * m) / (Ns * RAD));
+            for (int r = 0; r < RAD; ++r) g.v[q][r] = X[pad(b + r * nb)];
+            const int k = b & ((1 << lgNs) - 1);
+            if (k != 0) {
+                // one table read per butterfly; W^{r k} as products of W^k
+                // (depth <= 4 multiplications, a few ulps)
+                C w[RAD];
+                w[1] = tw_quarter<R>(twl, k << tsh, lgm);
+                if (INV) w[1].y = -w[1].y;
+                if constexpr (RAD >= 4) {
+                    w[2] = cmul(w[1], w[1]);
+                    w[3] = cmul(w[2], w[1]);
+                }
+                if constexpr (RAD >= 8) {
+                    w[4] = cmul(w[2], w[2]);
+                    w[5] = cmul(w[4], w[1]);
+                    w[6] = cmul(w[4], w[2]);
+                    w[7] = cmul(w[4], w[3]);
+                }
+                if constexpr (RAD >= 16) {
+                    w[8] = cmul(w[4], w[4]);
 #pragma unroll
-            for (int r = 1; r < RAD; ++r) {
-                C w = tw[r * step];
-                if (INV) w.y = -w.y;
-                g.v[q][r] = cmul(g.v[q][r], w);
+                    for (int r = 9; r < 16; ++r) w[r] = cmul(w[8], w[r - 8]);
+                }
+#pragma unroll
+                for (int r = 1; r < RAD; ++r) g.v[q][r] = cmul(g.v[q][r], w[r]);
             }
             dft<RAD, INV>(g.v[q]);
         }
     }
 }
 
-template <typename R, int RAD>
-__device__ __forceinline__ void stage_store(const StageRegs<R, RAD>& g, cplx<R>* X, int m, int Ns, int lt, int G) {
-    constexpr int PER = 16 / RAD;
-    const int nb = m / RAD;
+template <typename R, int RAD, int RMAX>
+__device__ __forceinline__ void stage_store(const StageRegs<R, RAD, RMAX>& g, cplx<R>* X, int lgm, int lgNs, int lt,
+                                            int G) {
+    constexpr int PER = RMAX / RAD;
+    const int nb = (1 << lgm) >> Lg<RAD>::v;
+    const int Ns = 1 << lgNs;
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
         const int b = lt + q * G;
         if (b < nb) {
             const int k = b & (Ns - 1);
-            const int base = (b - k) * RAD + k;
+            const int base = ((b - k) << Lg<RAD>::v) + k;
 #pragma unroll
-            for (int r = 0; r < RAD; ++r) X[base + r * Ns] = g.v[q][r];
+            for (int r = 0; r < RAD; ++r) X[pad(base + r * Ns)] = g.v[q][r];
         }
     }
 }
 
-// Stage on A and (optionally) B with one buffer's registers live at a time:
-// load+compute A | barrier | store A, load+compute B | barrier | store B.
-// The barrier of the next stage (or the caller's) orders "store B" before
-// any later read of B.
-template <typename R, int RAD, bool INV>
-__device__ __forceinline__ void stockham_stage(cplx<R>* A, cplx<R>* B, bool both, int m, int Ns, int lt, int G,
-                                               const cplx<R>* __restrict__ tw) {
-    StageRegs<R, RAD> g;
-    stage_load<R, RAD, INV>(g, A, m, Ns, lt, G, tw);
-    __syncthreads();
-    stage_store<R, RAD>(g, A, m, Ns, lt, G);
-    if (both) {
-        stage_load<R, RAD, INV>(g, B, m, Ns, lt, G, tw);
+// Stage on A and (optionally) B.  For RMAX <= 8 both buffers' butterflies
+// are in registers together (twice the independent work between the two
+// barriers): load+compute A and B | barrier | store A and B | barrier.
+// For RMAX = 16 one buffer's registers are live at a time:
+// load+compute A | barrier | store A, load+compute B | barrier | store B,
+// and the next stage's first barrier (or the one ending line_fft) orders
+// "store B" before any later read of B.
+template <typename R, int RAD, int RMAX, bool INV>
+__device__ __forceinline__ void stockham_stage(cplx<R>* A, cplx<R>* B, bool both, int lgm, int lgNs, int lt,
+                                               int G, const cplx<R>* twl) {
+    if constexpr (RMAX <= 8) {
+        StageRegs<R, RAD, RMAX> ga, gb;
+        stage_load<R, RAD, RMAX, INV>(ga, A, lgm, lgNs, lt, G, twl);
+        if (both) stage_load<R, RAD, RMAX, INV>(gb, B, lgm, lgNs, lt, G, twl);
         __syncthreads();
-        stage_store<R, RAD>(g, B, m, Ns, lt, G);
+        stage_store<R, RAD, RMAX>(ga, A, lgm, lgNs, lt, G);
+        if (both) stage_store<R, RAD, RMAX>(gb, B, lgm, lgNs, lt, G);
+        __syncthreads();
     } else {
+        StageRegs<R, RAD, RMAX> g;
+        stage_load<R, RAD, RMAX, INV>(g, A, lgm, lgNs, lt, G, twl);
         __syncthreads();
+        stage_store<R, RAD, RMAX>(g, A, lgm, lgNs, lt, G);
+        if (both) {
+            stage_load<R, RAD, RMAX, INV>(g, B, lgm, lgNs, lt, G, twl);
+            __syncthreads();
+            stage_store<R, RAD, RMAX>(g, B, lgm, lgNs, lt, G);
+        } else {
+            __syncthreads();
+        }
+    }
+}
+
+// Compile-time stage plan (m = 2^LGM known at compile time): every index,
+// bound and radix folds to a constant.
+template <typename R, bool INV, int RMAX, int LGM, int LGNS>
+__device__ __forceinline__ void fft_stages_ct(cplx<R>* A, cplx<R>* B, bool both, int lt, const cplx<R>* twl) {
+    if constexpr (LGNS < LGM) {
+        constexpr int rem = LGM - LGNS;
+        constexpr int lr = rem < Lg<RMAX>::v ? rem : Lg<RMAX>::v;
+        constexpr int G = (1 << LGM) / RMAX;
+        stockham_stage<R, (1 << lr), RMAX, INV>(A, B, both, LGM, LGNS, lt, G, twl);
+        fft_stages_ct<R, INV, RMAX, LGM, LGNS + lr>(A, B, both, lt, twl);
     }
 }
 
 // Length-m FFT (unnormalised) of line buffer A (and B), natural order in and
-// out.  Ends with a barrier.
-template <typename R, bool INV>
-__device__ __forceinline__ void line_fft(cplx<R>* A, cplx<R>* B, bool both, int m, int lt, int G, const cplx<R>* __restrict__ tw) {
-    int Ns = 1;
-    while (Ns < m) {
-        const int rem = m / Ns;
-        if (rem >= 16) {
-            stockham_stage<R, 16, INV>(A, B, both, m, Ns, lt, G, tw);
-            Ns *= 16;
-        } else if (rem == 8) {
-            stockham_stage<R, 8, INV>(A, B, both, m, Ns, lt, G, tw);
-            Ns *= 8;
-        } else if (rem == 4) {
-            stockham_stage<R, 4, INV>(A, B, both, m, Ns, lt, G, tw);
-            Ns *= 4;
-        } else {
-            stockham_stage<R, 2, INV>(A, B, both, m, Ns, lt, G, tw);
-            Ns *= 2;
+// out (m = 2^lgm), radices up to RMAX (G >= m / RMAX threads per line).
+// LGM > 0 selects the compile-time plan for m = 2^LGM.  Ends with a barrier.
+template <typename R, bool INV, int RMAX, int LGM = 0>
+__device__ __forceinline__ void line_fft(cplx<R>* A, cplx<R>* B, bool both, int lgm, int lt, int G,
+                                         const cplx<R>* twl) {
+    if constexpr (LGM > 0) {
+        fft_stages_ct<R, INV, RMAX, LGM, 0>(A, B, both, lt, twl);
+    } else {
+        constexpr int LGMAX = Lg<RMAX>::v;
+        int lgNs = 0;
+        while (lgNs < lgm) {
+            const int rem = lgm - lgNs;
+            const int lr = rem < LGMAX ? rem : LGMAX;
+            if (lr == 4) {
+                if constexpr (RMAX >= 16) stockham_stage<R, 16, RMAX, INV>(A, B, both, lgm, lgNs, lt, G, twl);
+            } else if (lr == 3) {
+                if constexpr (RMAX >= 8) stockham_stage<R, 8, RMAX, INV>(A, B, both, lgm, lgNs, lt, G, twl);
+            } else if (lr == 2) {
+                stockham_stage<R, 4, RMAX, INV>(A, B, both, lgm, lgNs, lt, G, twl);
+            } else {
+                stockham_stage<R, 2, RMAX, INV>(A, B, both, lgm, lgNs, lt, G, twl);
+            }
+            lgNs += lr;
         }
-        // the next stage's first barrier orders this stage's stores to B; the
-        // caller is synchronised below after the last stage
     }
     __syncthreads();
 }
 
 // Orthonormal DST-I of the line in A (slots 1..m-1), result in A; B is scratch.
-// Caller has synchronised after writing A.
-template <typename R>
-__device__ __forceinline__ void line_dst(cplx<R>* A, cplx<R>* B, int m, int lt, int G, const cplx<R>* __restrict__ tw) {
+// Caller has synchronised after writing A.  tw[s] = W_{2m}^s (global table).
+template <typename R, int RMAX, int LGM = 0>
+__device__ __forceinline__ void line_dst(cplx<R>* A, cplx<R>* B, int lgm, int lt, int G,
+                                         const cplx<R>* __restrict__ tw, const cplx<R>* twl) {
     using C = cplx<R>;
+    const int m = 1 << lgm;
     const int half = m >> 1;
     for (int j = lt; j <= half; j += G) {
         if (j == 0) {
             A[0] = czero<C>();
             B[0] = czero<C>();
         } else {
-            const C xj = A[j];
-            const C xmj = A[m - j];
+            const C xj = A[pad(j)];
+            const C xmj = A[pad(m - j)];
             const C a = csub(xj, xmj);
             const C s = cadd(xj, xmj);
             if (j == half) {
-                A[j] = czero<C>();
-                B[j] = cmul(s, tw[j]);
+                A[pad(j)] = czero<C>();
+                B[pad(j)] = cmul(s, tw[j]);
             } else {
-                A[j] = a;
-                A[m - j] = cneg(a);
-                B[j] = cmul(s, tw[j]);
-                B[m - j] = cmul(s, tw[m - j]);
+                A[pad(j)] = a;
+                A[pad(m - j)] = cneg(a);
+                B[pad(j)] = cmul(s, tw[j]);
+                B[pad(m - j)] = cmul(s, tw[m - j]);
             }
         }
     }
     __syncthreads();
-    line_fft<R, false>(A, B, true, m, lt, G, tw);
+    line_fft<R, false, RMAX, LGM>(A, B, true, lgm, lt, G, twl);
     // y_{2p} = (i/sqrt(2m)) A_p, y_{2p+1} = (i/sqrt(2m)) B_p
-    constexpr int PER = 8;
+    constexpr int PER = RMAX / 2;
     C ra[PER], rb[PER];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
         const int p = lt + q * G;
         if (p < half) {
-            ra[q] = A[p];
-            rb[q] = B[p];
+            ra[q] = A[pad(p)];
+            rb[q] = B[pad(p)];
         }
     }
     __syncthreads();
@@ -318,8 +396,8 @@ __device__ __forceinline__ void line_dst(cplx<R>* A, cplx<R>* B, int m, int lt, 
     for (int q = 0; q < PER; ++q) {
         const int p = lt + q * G;
         if (p < half) {
-            A[2 * p] = (p == 0) ? czero<C>() : cm<R>(-sc * ra[q].y, sc * ra[q].x);
-            A[2 * p + 1] = cm<R>(-sc * rb[q].y, sc * rb[q].x);
+            A[pad(2 * p)] = (p == 0) ? czero<C>() : cm<R>(-sc * ra[q].y, sc * ra[q].x);
+            A[pad(2 * p + 1)] = cm<R>(-sc * rb[q].y, sc * rb[q].x);
         }
     }
     __syncthreads();
@@ -327,18 +405,21 @@ __device__ __forceinline__ void line_dst(cplx<R>* A, cplx<R>* B, int m, int lt, 
 
 // Toeplitz convolution core: on exit A holds IFFT_m(s_e FFT_m(x)) and B holds
 // IFFT_m(s_o FFT_m(W^j x)); the product at slot j is A[j] + conj(W_{2m}^j) B[j].
-template <typename R>
-__device__ __forceinline__ void line_toeplitz(cplx<R>* A, cplx<R>* B, int m, int lt, int G, const cplx<R>* __restrict__ tw,
-                              const R* __restrict__ sym_e, const R* __restrict__ sym_o, R tscale) {
-    for (int s = lt; s < m; s += G) B[s] = cmul(A[s], tw[s]);
+template <typename R, int RMAX, int LGM = 0>
+__device__ __forceinline__ void line_toeplitz(cplx<R>* A, cplx<R>* B, int lgm, int lt, int G,
+                                              const cplx<R>* __restrict__ tw, const cplx<R>* twl,
+                                              const R* __restrict__ sym_e, const R* __restrict__ sym_o,
+                                              R tscale) {
+    const int m = 1 << lgm;
+    for (int s = lt; s < m; s += G) B[pad(s)] = cmul(A[pad(s)], tw[s]);
     __syncthreads();
-    line_fft<R, false>(A, B, true, m, lt, G, tw);
+    line_fft<R, false, RMAX, LGM>(A, B, true, lgm, lt, G, twl);
     for (int p = lt; p < m; p += G) {
-        A[p] = cscale(A[p], sym_e[p] * tscale);
-        B[p] = cscale(B[p], sym_o[p] * tscale);
+        A[pad(p)] = cscale(A[pad(p)], sym_e[p] * tscale);
+        B[pad(p)] = cscale(B[pad(p)], sym_o[p] * tscale);
     }
     __syncthreads();
-    line_fft<R, true>(A, B, true, m, lt, G, tw);
+    line_fft<R, true, RMAX, LGM>(A, B, true, lgm, lt, G, twl);
 }
 
 // ---------------------------------------------------------------------------

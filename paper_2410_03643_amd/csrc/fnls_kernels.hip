@@ -16,17 +16,18 @@
 // k_cgs: streaming classical Gram-Schmidt update w -= sum_i c_i v_i fused with
 // the second-round dot products or with ||w||^2 and the Givens step.
 //
-// Reductions are two-level and in a fixed order (deterministic): every
-// workgroup writes its partial sums, the last workgroup to arrive (device-
-// scope atomic counter) sums the partials and updates the GMRES state.
+// Reductions are two-level and in a fixed order (deterministic), without
+// atomics: every workgroup writes its partial sums; the next kernel's
+// workgroups each sum them again (identical totals everywhere), and a
+// one-workgroup kernel (k_finish) takes the scalar decisions -- Givens step,
+// residual test -- and reports them to the host.
 #include "fnls_common.h"
 #include "fnls_device.hpp"
 
 namespace fnls {
 
 enum OpBits { OP_DST1 = 1, OP_DIV = 2, OP_DST2 = 4, OP_SCALE = 8, OP_TOEP = 16 };
-constexpr int kMaxEptLine = 16;   // elements per thread in the element phases of k_pass
-constexpr int kMaxWaves = 4;     // every kernel here runs at most 256 threads
+constexpr int kMaxWaves = 4;     // streaming and finish kernels run 256 threads (4 wavefronts)
 
 // ---------------------------------------------------------------------------
 // status reporting
@@ -163,48 +164,47 @@ __device__ void residual_finish(GmresState* st, HostStatus* hs, double rn2, int 
     report(st, hs, 0);
 }
 
-// Sum nv per-workgroup partials (layout [i][pstride]) in the last workgroup.
-// Returns true in the last workgroup; tot[i] (LDS) then holds the totals.
-__device__ bool last_block_reduce(double2* partials, int pstride, int nv, GmresState* st, double2* tot) {
-    __shared__ int s_last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned prev = atomicAdd(&st->counter, 1u);
-        s_last = (prev == gridDim.x - 1) ? 1 : 0;
-    }
-    __syncthreads();
-    if (!s_last) return false;
-    __threadfence();
+// Sum nv per-workgroup partials (layout [i][ps], nb producer workgroups) into
+// tot[i] (LDS) with every thread of the workgroup taking part.  The order is
+// fixed, so every consumer workgroup obtains bit-identical totals.
+__device__ void reduce_partials(const double2* __restrict__ p, int ps, int nb, int nv, double2* tot,
+                                double2* red) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int nw = (blockDim.x + 63) >> 6;
-    const int nb = gridDim.x;
-    for (int i = wave; i < nv; i += nw) {
+    for (int i = 0; i < nv; ++i) {
         double sx = 0.0, sy = 0.0;
-        const double2* p = partials + (size_t)i * pstride;
-        for (int b = lane; b < nb; b += 64) {
-            const double2 v = p[b];
+        const double2* pi = p + (size_t)i * ps;
+        for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+            const double2 v = pi[b];
             sx += v.x;
             sy += v.y;
         }
         sx = wave_sum(sx);
         sy = wave_sum(sy);
-        if (lane == 0) tot[i] = dmk(sx, sy);
+        if (lane == 0) red[i * nw + wave] = dmk(sx, sy);
     }
     __syncthreads();
-    return true;
+    for (int i = threadIdx.x; i < nv; i += blockDim.x) {
+        double sx = 0.0, sy = 0.0;
+        for (int w = 0; w < nw; ++w) {
+            sx += red[i * nw + w].x;
+            sy += red[i * nw + w].y;
+        }
+        tot[i] = dmk(sx, sy);
+    }
+    __syncthreads();
 }
 
-// Write this workgroup's partial of nv values: each thread contributes
-// acc[i] via the LDS array red[i][wave] (already wave-reduced by caller).
+// Write this workgroup's partial of nv values: red[i * nw + w] holds the
+// wavefront sums (nw wavefronts); summed in wavefront order.
 __device__ void block_partial_write(const double2* red, int nv, double2* partials, int pstride) {
     const int nw = (blockDim.x + 63) >> 6;
     for (int i = threadIdx.x; i < nv; i += blockDim.x) {
         double sx = 0.0, sy = 0.0;
         for (int w = 0; w < nw; ++w) {
-            sx += red[i * kMaxWaves + w].x;
-            sy += red[i * kMaxWaves + w].y;
+            sx += red[i * nw + w].x;
+            sy += red[i * nw + w].y;
         }
         partials[(size_t)i * pstride + blockIdx.x] = dmk(sx, sy);
     }
@@ -222,25 +222,40 @@ __device__ __forceinline__ void stc(void* p, long long idx, cplx<R> v) {
 // ---------------------------------------------------------------------------
 // the fused axis pass
 // ---------------------------------------------------------------------------
-template <typename R, int INM, int OPS, int ZM, int OUTM, int FIN>
-__global__ __launch_bounds__(256) void k_pass(PassArgs a) {
+// RMAX: largest FFT radix; G = m / RMAX threads per line, so every thread
+// owns about RMAX unknowns of its line in the element phases.
+template <int RMAX> struct PassThreads { static constexpr int v = 4096 / RMAX; };
+template <> struct PassThreads<16> { static constexpr int v = 256; };
+
+// LGM > 0: the line length m = 2^LGM is a compile-time constant (the host
+// launches this specialisation only when a.lgm == LGM); 0: generic.
+template <typename R, int RMAX, int LGM, int INM, int OPS, int ZM, int OUTM, int FIN>
+__global__ __launch_bounds__(PassThreads<RMAX>::v) void k_pass(PassArgs a) {
     using C = cplx<R>;
+    constexpr int kMaxEptLine = RMAX;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     if (a.check_active && a.st->active == 0) return;
 
-    const int n = a.n, m = a.m, G = a.G, L = a.L, lgL = a.lgL;
+    const int lgm = LGM ? LGM : a.lgm;
+    const int m = 1 << lgm;
+    const int n = m - 1;
+    const int G = LGM ? (1 << LGM) / RMAX : a.G;
+    const int lgG = LGM ? LGM - Lg<RMAX>::v : a.lgG;
+    const int L = a.L, lgL = a.lgL;
     const int T = G * L;
     const int tid = threadIdx.x;
-    const int line = tid >> a.lgG;
+    const int line = tid >> lgG;
     const int lt = tid & (G - 1);
     const long long stride = a.stride;
     const bool contiguous = (stride == 1);
-    const int LS = 2 * m + 2;
+    const int PA = padded_len(m);   // padded slots of one line buffer
+    const int LS = 2 * PA;          // line stride: buffers A and B
+    // dynamic LDS: L lines | quarter twiddle table | per-line base offsets | per-line Lambda
     C* lds = reinterpret_cast<C*>(smem_raw);
-    __shared__ R s_lamo[256];
-    __shared__ long long s_base[256];
-    __shared__ double2 s_red[(kMaxRestart + 2) * kMaxWaves];
-    __shared__ double2 s_tot[kMaxRestart + 2];
+    C* twl = lds + (size_t)L * LS;                    // W_m^q at pad(q), q < max(1, m/4)
+    const int nq = m >= 4 ? pad((m >> 2) - 1) + 1 : 1;
+    long long* s_base = reinterpret_cast<long long*>(twl + nq);
+    R* s_lamo = reinterpret_cast<R*>(s_base + L);
 
     const C* tw = reinterpret_cast<const C*>(a.tw);
     const R* lam = reinterpret_cast<const R*>(a.lam);
@@ -287,6 +302,7 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs a) {
         s_lamo[l] = lamo;
         lds[(size_t)l * LS] = czero<C>();   // slot 0: the Dirichlet zero
     }
+    for (int q = tid; q < (m >= 4 ? (m >> 2) : 1); q += T) twl[pad(q)] = tw[2 * q];
     __syncthreads();
 
     // ---- load phase
@@ -321,30 +337,30 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs a) {
                         v = cm<R>(static_cast<R>(sx), static_cast<R>(sy));
                     }
                 }
-                lds[(size_t)l * LS + j + 1] = v;
+                lds[(size_t)l * LS + pad(j + 1)] = v;
             }
         }
     }
     __syncthreads();
 
     C* A = lds + (size_t)line * LS;
-    C* B = A + m + 1;
+    C* B = A + PA;
 
     // ---- transform stages
-    if (OPS & OP_DST1) line_dst<R>(A, B, m, lt, G, tw);
+    if (OPS & OP_DST1) line_dst<R, RMAX, LGM>(A, B, lgm, lt, G, tw, twl);
     if (OPS & OP_DIV) {
         const R om = static_cast<R>(a.omega);
         const R lo = s_lamo[line];
         for (int k = lt + 1; k < m; k += G) {
             const R mu = lo + tscale * lam[k];
             const R den = om * om + mu * mu;
-            const C v = A[k];
+            const C v = A[pad(k)];
             // v / (om + i mu) = v (om - i mu) / den
-            A[k] = cm<R>((v.x * om + v.y * mu) / den, (v.y * om - v.x * mu) / den);
+            A[pad(k)] = cm<R>((v.x * om + v.y * mu) / den, (v.y * om - v.x * mu) / den);
         }
         __syncthreads();
     }
-    if (OPS & OP_DST2) line_dst<R>(A, B, m, lt, G, tw);
+    if (OPS & OP_DST2) line_dst<R, RMAX, LGM>(A, B, lgm, lt, G, tw, twl);
 
     constexpr bool kToep = (OPS & OP_TOEP) != 0;
     constexpr bool kKeepZ = kToep && (OUTM == OUT_ACC_FIRST);
@@ -363,7 +379,7 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs a) {
             int l, j;
             emap(e, l, j);
             const long long base = s_base[l];
-            C z = lds[(size_t)l * LS + j + 1];
+            C z = lds[(size_t)l * LS + pad(j + 1)];
             if (base >= 0) {
                 const long long gi = base + (long long)j * stride;
                 if (OPS & OP_SCALE) {
@@ -389,14 +405,14 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs a) {
                 if (!kToep && FIN == FIN_WRITE && a.out) stc<R>(a.out, gi, z);
             }
             if (kKeepZ) zreg[q] = z;
-            if (kToep) lds[(size_t)l * LS + j + 1] = z;
+            if (kToep) lds[(size_t)l * LS + pad(j + 1)] = z;
         }
         if (kToep) __syncthreads();
     }
 
     // ---- Toeplitz product and element phase 2
     if (kToep) {
-        line_toeplitz<R>(A, B, m, lt, G, tw, reinterpret_cast<const R*>(a.sym_e),
+        line_toeplitz<R, RMAX, LGM>(A, B, lgm, lt, G, tw, twl, reinterpret_cast<const R*>(a.sym_e),
                          reinterpret_cast<const R*>(a.sym_o), tscale);
         const R cT = static_cast<R>(a.cT);
 #pragma unroll
@@ -411,7 +427,7 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs a) {
             const long long gi = base + (long long)j * stride;
             const int s = j + 1;
             const C* Al = lds + (size_t)l * LS;
-            const C tz = cadd(Al[s], cmulc(Al[m + 1 + s], tw[s]));
+            const C tz = cadd(Al[pad(s)], cmulc(Al[PA + pad(s)], tw[s]));
             C o;
             if (OUTM == OUT_ACC_FIRST) {
                 const R Dj = Dv[gi];
@@ -439,7 +455,12 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs a) {
     }
     if (FIN == FIN_WRITE) return;
 
-    // ---- reductions: Arnoldi dot products (conj(v_i) w) or ||r||^2
+    // ---- reductions: Arnoldi dot products (conj(v_i) w) or ||r||^2.  The
+    // line buffers are free now; their LDS holds the per-wavefront sums
+    // (the host sizes the allocation for (kMaxRestart + 2) * waves entries).
+    __syncthreads();
+    double2* s_red = reinterpret_cast<double2*>(smem_raw);
+    const int nwv = T >> 6;
     const int lane = tid & 63, wave = tid >> 6;
     int nv = 1;
     if (FIN == FIN_WDOTS) {
@@ -463,33 +484,16 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs a) {
             }
             sx = wave_sum(sx);
             sy = wave_sum(sy);
-            if (lane == 0) s_red[i * kMaxWaves + wave] = dmk(sx, sy);
+            if (lane == 0) s_red[i * nwv + wave] = dmk(sx, sy);
         }
         nrm = wave_sum(nrm);
-        if (lane == 0) s_red[nb * kMaxWaves + wave] = dmk(nrm, 0.0);
+        if (lane == 0) s_red[nb * nwv + wave] = dmk(nrm, 0.0);
     } else {
         nrm = wave_sum(nrm);
         if (lane == 0) s_red[wave] = dmk(nrm, 0.0);
     }
     __syncthreads();
-    block_partial_write(s_red, nv, a.partials, a.pstride);
-    if (!last_block_reduce(a.partials, a.pstride, nv, a.st, s_tot)) return;
-    if (tid == 0) {
-        GmresState* st = a.st;
-        st->counter = 0;
-        if (FIN == FIN_WDOTS) {
-            const int nb = nv - 1;
-            for (int i = 0; i < nb; ++i) {
-                const double sg = st->sigma[i];
-                const double2 h = dmk(s_tot[i].x * sg, s_tot[i].y * sg);
-                st->hcol[i] = h;
-                st->coef[i] = dmk(h.x * sg, h.y * sg);
-            }
-            st->wnorm0 = sqrt(s_tot[nb].x);
-        } else {
-            residual_finish(st, a.hs, s_tot[0].x, a.ir);
-        }
-    }
+    block_partial_write(s_red, nv, a.pout, a.pstride);
 }
 
 // ---------------------------------------------------------------------------
@@ -509,26 +513,155 @@ __global__ void k_precond_setup(StreamArgs a) {
     }
 }
 
-// Solve start: ||b||^2 (optionally writing the complex64 copy of b), then the
-// last workgroup initialises the GMRES state.
+// Solve start: per-workgroup partials of ||b||^2 (optionally writing the
+// complex64 copy of b).  kEpt elements per thread, all loads issued first.
 __global__ __launch_bounds__(256) void k_prepare(StreamArgs a) {
-    __shared__ double2 s_red[(kMaxRestart + 2) * kMaxWaves];
-    __shared__ double2 s_tot[kMaxRestart + 2];
+    __shared__ double2 s_red[kMaxWaves];
     const long long N = a.N;
+    const long long base = (long long)blockIdx.x * (kStreamThreads * kEpt) + threadIdx.x;
+    double2 v[kEpt];
+#pragma unroll
+    for (int q = 0; q < kEpt; ++q) {
+        const long long i = base + (long long)q * kStreamThreads;
+        v[q] = i < N ? a.b64[i] : dmk(0.0, 0.0);
+    }
     double nrm = 0.0;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (long long)gridDim.x * blockDim.x) {
-        const double2 v = a.b64[i];
-        nrm += v.x * v.x + v.y * v.y;
-        if (a.r32) reinterpret_cast<float2*>(a.r32)[i] = make_float2((float)v.x, (float)v.y);
+#pragma unroll
+    for (int q = 0; q < kEpt; ++q) {
+        const long long i = base + (long long)q * kStreamThreads;
+        nrm += v[q].x * v[q].x + v[q].y * v[q].y;
+        if (a.r32 && i < N) reinterpret_cast<float2*>(a.r32)[i] = make_float2((float)v[q].x, (float)v[q].y);
     }
     nrm = wave_sum(nrm);
     if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = dmk(nrm, 0.0);
     __syncthreads();
-    block_partial_write(s_red, 1, a.partials, a.pstride);
-    if (!last_block_reduce(a.partials, a.pstride, 1, a.st, s_tot)) return;
-    if (threadIdx.x == 0) {
-        GmresState* st = a.st;
-        st->counter = 0;
+    block_partial_write(s_red, 1, a.pout, a.pstride);
+}
+
+// Classical Gram-Schmidt round on w.  MODE 0 (first update): the totals of
+// the producer's partials are the dot products d_i = conj(V_i) w (i < nv) and
+// ||w||^2; h_i = sigma_i d_i, w -= sum_i h_i v_i, then partials of the
+// second-round dot products.  MODE 1 (second update): totals are the
+// second-round d_i; w -= sum_i h_i v_i, then partials of ||w||^2.  Workgroup 0
+// records h in the GMRES state (h1 + h2 is the Hessenberg column).  V_i and w
+// are complex<R>; arithmetic in FP64.  Each thread owns kEpt elements
+// (stride = workgroup size: every load instruction of a wavefront is
+// contiguous) and issues all kEpt loads of a vector at once.
+template <typename R, int MODE>
+__global__ __launch_bounds__(256) void k_cgs(StreamArgs a) {
+    using C = cplx<R>;
+    __shared__ double2 s_red[(kMaxRestart + 2) * kMaxWaves];
+    __shared__ double2 s_tot[kMaxRestart + 2];
+    __shared__ double2 s_coef[kMaxRestart + 1];
+    if (a.check_active && a.st->active == 0) return;
+    const long long N = a.N;
+    const int nv = a.nv;
+    GmresState* st = a.st;
+    reduce_partials(a.pin, a.pstride, a.pin_nb, MODE == 0 ? nv + 1 : nv, s_tot, s_red);
+    if (threadIdx.x < nv) {
+        const int i = threadIdx.x;
+        const double sg = st->sigma[i];
+        const double2 h = dmk(s_tot[i].x * sg, s_tot[i].y * sg);
+        s_coef[i] = dmk(h.x * sg, h.y * sg);
+        if (blockIdx.x == 0) {
+            if (MODE == 0) {
+                st->hcol[i] = h;
+            } else {
+                st->hcol[i].x += h.x;
+                st->hcol[i].y += h.y;
+            }
+        }
+    }
+    if (MODE == 0 && blockIdx.x == 0 && threadIdx.x == 0) st->wnorm0 = sqrt(s_tot[nv].x);
+    __syncthreads();
+
+    const long long base = (long long)blockIdx.x * (kStreamThreads * kEpt) + threadIdx.x;
+    double wx[kEpt], wy[kEpt];
+#pragma unroll
+    for (int q = 0; q < kEpt; ++q) {
+        const long long i = base + (long long)q * kStreamThreads;
+        const C w = i < N ? ld<R>(a.w, i) : czero<C>();
+        wx[q] = w.x;
+        wy[q] = w.y;
+    }
+    for (int vi = 0; vi < nv; ++vi) {
+        const void* vp = (vi == 0) ? a.v0
+                                   : (const void*)(reinterpret_cast<const C*>(a.vbase) + (long long)(vi - 1) * N);
+        const double2 c = s_coef[vi];
+        C v[kEpt];
+#pragma unroll
+        for (int q = 0; q < kEpt; ++q) {
+            const long long i = base + (long long)q * kStreamThreads;
+            v[q] = i < N ? ld<R>(vp, i) : czero<C>();
+        }
+#pragma unroll
+        for (int q = 0; q < kEpt; ++q) {
+            wx[q] -= c.x * v[q].x - c.y * v[q].y;
+            wy[q] -= c.x * v[q].y + c.y * v[q].x;
+        }
+    }
+    C wr[kEpt];
+    double nrm = 0.0;
+#pragma unroll
+    for (int q = 0; q < kEpt; ++q) {
+        const long long i = base + (long long)q * kStreamThreads;
+        wr[q] = cm<R>(static_cast<R>(wx[q]), static_cast<R>(wy[q]));
+        if (i < N) stc<R>(a.w, i, wr[q]);
+        else wr[q] = czero<C>();
+        nrm += (double)wr[q].x * wr[q].x + (double)wr[q].y * wr[q].y;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int nout;
+    if (MODE == 0) {
+        for (int vi = 0; vi < nv; ++vi) {
+            const void* vp = (vi == 0) ? a.v0
+                                       : (const void*)(reinterpret_cast<const C*>(a.vbase) + (long long)(vi - 1) * N);
+            C v[kEpt];
+#pragma unroll
+            for (int q = 0; q < kEpt; ++q) {
+                const long long i = base + (long long)q * kStreamThreads;
+                v[q] = i < N ? ld<R>(vp, i) : czero<C>();
+            }
+            double sx = 0.0, sy = 0.0;
+#pragma unroll
+            for (int q = 0; q < kEpt; ++q) {
+                sx += (double)v[q].x * wr[q].x + (double)v[q].y * wr[q].y;
+                sy += (double)v[q].x * wr[q].y - (double)v[q].y * wr[q].x;
+            }
+            sx = wave_sum(sx);
+            sy = wave_sum(sy);
+            if (lane == 0) s_red[vi * kMaxWaves + wave] = dmk(sx, sy);   // blockDim 256: kMaxWaves waves
+        }
+        nout = nv;
+    } else {
+        nrm = wave_sum(nrm);
+        if (lane == 0) s_red[wave] = dmk(nrm, 0.0);
+        nout = 1;
+    }
+    __syncthreads();
+    block_partial_write(s_red, nout, a.pout, a.pstride);
+}
+
+// Scalar decision kernel (one workgroup): sums the producer's partials and
+//   FIN_K_PREPARE: initialises the GMRES state from ||b|| and reports;
+//   FIN_K_GIVENS:  finishes the Arnoldi step (Givens, stopping test);
+//   FIN_K_RESID:   takes the restart / refinement decision from ||b - A x||.
+enum FinishKind { FIN_K_PREPARE = 0, FIN_K_GIVENS = 1, FIN_K_RESID = 2, FIN_K_REDUCE = 3 };
+
+__global__ __launch_bounds__(256) void k_finish(StreamArgs a) {
+    __shared__ double2 s_red[(kMaxRestart + 2) * kMaxWaves];
+    __shared__ double2 s_tot[kMaxRestart + 2];
+    GmresState* st = a.st;
+    if (a.check_active && st->active == 0) return;
+    const int nv = (a.mode == FIN_K_REDUCE) ? a.nv : 1;
+    reduce_partials(a.pin, a.pstride, a.pin_nb, nv, s_tot, s_red);
+    if (a.mode == FIN_K_REDUCE) {
+        // totals written as the partials of a single producer workgroup
+        for (int i = threadIdx.x; i < nv; i += blockDim.x) a.pout[(size_t)i * a.pstride] = s_tot[i];
+        return;
+    }
+    if (threadIdx.x != 0) return;
+    if (a.mode == FIN_K_PREPARE) {
         const double bn = sqrt(s_tot[0].x);
         st->bnorm = bn;
         st->refnorm = bn;
@@ -547,85 +680,10 @@ __global__ __launch_bounds__(256) void k_prepare(StreamArgs a) {
         st->done = ok ? 0 : 1;
         if (!ok) st->relres = 0.0;
         report(st, a.hs, 0);
-    }
-}
-
-// w -= sum_{i<nv} coef_i V_i, then either the dot products conj(V_i) w
-// (mode 0, second Gram-Schmidt round) or ||w||^2 and the Arnoldi finish
-// (mode 1).  V_i and w are complex<R>; arithmetic in FP64.
-template <typename R, int MODE>
-__global__ __launch_bounds__(256) void k_cgs(StreamArgs a) {
-    using C = cplx<R>;
-    __shared__ double2 s_red[(kMaxRestart + 2) * kMaxWaves];
-    __shared__ double2 s_tot[kMaxRestart + 2];
-    if (a.check_active && a.st->active == 0) return;
-    const long long N = a.N;
-    const int nv = a.nv;
-    GmresState* st = a.st;
-    C wreg[kEpt];
-    long long idx[kEpt];
-    const long long T = (long long)gridDim.x * blockDim.x;
-    const long long t0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    double nrm = 0.0;
-#pragma unroll
-    for (int q = 0; q < kEpt; ++q) {
-        idx[q] = t0 + q * T;
-        if (idx[q] < N) {
-            const C w = ld<R>(a.w, idx[q]);
-            double sx = w.x, sy = w.y;
-            for (int i = 0; i < nv; ++i) {
-                const C v = (i == 0) ? ld<R>(a.v0, idx[q]) : ld<R>(a.vbase, (long long)(i - 1) * N + idx[q]);
-                const double2 c = st->coef[i];
-                sx -= c.x * v.x - c.y * v.y;
-                sy -= c.x * v.y + c.y * v.x;
-            }
-            const C wn = cm<R>(static_cast<R>(sx), static_cast<R>(sy));
-            stc<R>(a.w, idx[q], wn);
-            wreg[q] = wn;
-            nrm += (double)wn.x * wn.x + (double)wn.y * wn.y;
-        } else {
-            wreg[q] = czero<C>();
-        }
-    }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    int nout;
-    if (MODE == 0) {
-        for (int i = 0; i < nv; ++i) {
-            double sx = 0.0, sy = 0.0;
-#pragma unroll
-            for (int q = 0; q < kEpt; ++q) {
-                if (idx[q] >= N) continue;
-                const C v = (i == 0) ? ld<R>(a.v0, idx[q]) : ld<R>(a.vbase, (long long)(i - 1) * N + idx[q]);
-                const C w = wreg[q];
-                sx += (double)v.x * w.x + (double)v.y * w.y;
-                sy += (double)v.x * w.y - (double)v.y * w.x;
-            }
-            sx = wave_sum(sx);
-            sy = wave_sum(sy);
-            if (lane == 0) s_red[i * kMaxWaves + wave] = dmk(sx, sy);
-        }
-        nout = nv;
+    } else if (a.mode == FIN_K_GIVENS) {
+        arnoldi_finish(st, a.hs, s_tot[0].x);
     } else {
-        nrm = wave_sum(nrm);
-        if (lane == 0) s_red[wave] = dmk(nrm, 0.0);
-        nout = 1;
-    }
-    __syncthreads();
-    block_partial_write(s_red, nout, a.partials, a.pstride);
-    if (!last_block_reduce(a.partials, a.pstride, nout, st, s_tot)) return;
-    if (threadIdx.x == 0) {
-        st->counter = 0;
-        if (MODE == 0) {
-            for (int i = 0; i < nv; ++i) {
-                const double s = st->sigma[i];
-                const double2 h = dmk(s_tot[i].x * s, s_tot[i].y * s);
-                st->hcol[i].x += h.x;
-                st->hcol[i].y += h.y;
-                st->coef[i] = dmk(h.x * s, h.y * s);
-            }
-        } else {
-            arnoldi_finish(st, a.hs, s_tot[0].x);
-        }
+        residual_finish(st, a.hs, s_tot[0].x, a.ir);
     }
 }
 
@@ -652,9 +710,9 @@ __global__ void k_config(GmresState* st, double tol, double outer_tol, int resta
 
 namespace fnls {
 
-template <typename R, int INM, int OPS, int ZM, int OUTM, int FIN>
+template <typename R, int RMAX, int LGM, int INM, int OPS, int ZM, int OUTM, int FIN>
 static hipError_t launch_pass_t(const PassArgs& a, int blocks, size_t lds, hipStream_t s) {
-    auto kern = k_pass<R, INM, OPS, ZM, OUTM, FIN>;
+    auto kern = k_pass<R, RMAX, LGM, INM, OPS, ZM, OUTM, FIN>;
     // dynamic LDS above 64 KiB must be allowed per kernel; remember the largest granted
     static size_t granted = 64 * 1024;
     if (lds > granted) {
@@ -663,14 +721,30 @@ static hipError_t launch_pass_t(const PassArgs& a, int blocks, size_t lds, hipSt
         if (e != hipSuccess) return e;
         granted = lds;
     }
+    if (a.G * a.L > PassThreads<RMAX>::v) return hipErrorInvalidConfiguration;
+    if (LGM && (a.lgm != LGM || a.G != (1 << LGM) / RMAX)) return hipErrorInvalidConfiguration;
     (void)hipGetLastError();   // clear errors of earlier, unrelated runtime calls
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(a.G * a.L), lds, s, a);
     return hipGetLastError();
 }
 
+template <typename R, int INM, int OPS, int ZM, int OUTM, int FIN>
+static hipError_t launch_pass_r(int rmax, const PassArgs& a, int blocks, size_t lds, hipStream_t s) {
+    if (a.lgm == 10) {   // m = 1024: compile-time plan
+        if (rmax == 4) return launch_pass_t<R, 4, 10, INM, OPS, ZM, OUTM, FIN>(a, blocks, lds, s);
+        if (rmax == 8) return launch_pass_t<R, 8, 10, INM, OPS, ZM, OUTM, FIN>(a, blocks, lds, s);
+    }
+    switch (rmax) {
+        case 4: return launch_pass_t<R, 4, 0, INM, OPS, ZM, OUTM, FIN>(a, blocks, lds, s);
+        case 8: return launch_pass_t<R, 8, 0, INM, OPS, ZM, OUTM, FIN>(a, blocks, lds, s);
+        case 16: return launch_pass_t<R, 16, 0, INM, OPS, ZM, OUTM, FIN>(a, blocks, lds, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 #define FNLS_PASS_CASE(R, INM, OPS, ZM, OUTM, FIN)                                            \
     if (v.inm == INM && v.ops == (OPS) && v.zm == ZM && v.outm == OUTM && v.fin == FIN)       \
-        return launch_pass_t<R, INM, OPS, ZM, OUTM, FIN>(a, blocks, lds, s);
+        return launch_pass_r<R, INM, OPS, ZM, OUTM, FIN>(v.rmax, a, blocks, lds, s);
 
 template <typename R>
 static hipError_t dispatch_pass(const PassVariant& v, const PassArgs& a, int blocks, size_t lds, hipStream_t s) {
@@ -720,6 +794,12 @@ hipError_t launch_precond_setup(const StreamArgs& a, int blocks, hipStream_t s) 
 hipError_t launch_prepare(const StreamArgs& a, int blocks, hipStream_t s) {
     (void)hipGetLastError();
     hipLaunchKernelGGL(k_prepare, dim3(blocks), dim3(kStreamThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish(const StreamArgs& a, hipStream_t s) {
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(kStreamThreads), 0, s, a);
     return hipGetLastError();
 }
 

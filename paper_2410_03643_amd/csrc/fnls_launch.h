@@ -9,6 +9,7 @@ namespace fnls {
 
 struct PassVariant {
     int inm, ops, zm, outm, fin;
+    int rmax;   // largest FFT radix (4, 8, 16); threads per line G = m / rmax
 };
 
 enum PassOps { P_DST1 = 1, P_DIV = 2, P_DST2 = 4, P_SCALE = 8, P_TOEP = 16 };
@@ -16,6 +17,8 @@ enum PassOps { P_DST1 = 1, P_DIV = 2, P_DST2 = 4, P_SCALE = 8, P_TOEP = 16 };
 hipError_t launch_pass(int fp64, const PassVariant& v, const PassArgs& a, int blocks, size_t lds, hipStream_t s);
 hipError_t launch_precond_setup(const StreamArgs& a, int blocks, hipStream_t s);
 hipError_t launch_prepare(const StreamArgs& a, int blocks, hipStream_t s);
+// one workgroup: StreamArgs::mode = 0 prepare, 1 Givens, 2 residual (nv = 1 for IR), 3 reduce nv values
+hipError_t launch_finish(const StreamArgs& a, hipStream_t s);
 hipError_t launch_cgs(int fp64, int mode, const StreamArgs& a, int blocks, hipStream_t s);
 hipError_t launch_config(GmresState* st, double tol, double outer_tol, int restart, int maxit, int fixed_iters,
                          int max_outer, hipStream_t s);

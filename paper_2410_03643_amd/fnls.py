@@ -100,6 +100,8 @@ def lib() -> ctypes.CDLL:
     L.fnls_last_error.restype = ctypes.c_char_p
     L.fnls_status_string.argtypes = [ci]
     L.fnls_status_string.restype = ctypes.c_char_p
+    L.fnls_set_pass_config.argtypes = [vp, ci, ci, ci, ci]
+    L.fnls_set_pass_config.restype = ci
     L.fnls_timing.argtypes = [vp, ci]
     L.fnls_timing.restype = ci
     L.fnls_timing_report.argtypes = [vp, ctypes.POINTER(KernelStat), ci]
@@ -246,6 +248,11 @@ class Solver:
         self._check(lib().fnls_first_step(self._ctx, self._vec(u0, "u0"), self._vec(u1, "u1"),
                                           ctypes.byref(o), ctypes.byref(info)))
         return u1, self._info(info)
+
+    def set_pass_config(self, precision, strided: bool, rmax: int, lines: int):
+        """Transform-pass tuning: largest radix and lines per workgroup."""
+        p = {"fp64": FP64, "fp32_ir": FP32_IR}[precision] if isinstance(precision, str) else precision
+        self._check(lib().fnls_set_pass_config(self._ctx, p, 1 if strided else 0, rmax, lines))
 
     def timing(self, enable: bool):
         """Start (clearing earlier records) or stop per-launch event timing."""

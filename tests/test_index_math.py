@@ -13,26 +13,56 @@ import numpy as np
 import pytest
 
 MAX_LDS_BLOCK = 163840      # MI355X: maximum LDS per workgroup
-STATIC_LDS = 12 * 1024      # budget the host reserves for the kernel's static LDS
-MAX_EPT_LINE = 16
-KEPT = 8
+STATIC_LDS = 8 * 1024       # budget the host reserves for the kernel's static LDS
+KEPT = 16
 STREAM_THREADS = 256
 
 
-def pass_geo(d, n, axis, fp64, max_dyn):
+DEFAULT_CFG = {"rmax": (4, 4), "lines": (1, 4)}   # (contiguous axis, strided axes)
+CONFIGS = [DEFAULT_CFG,
+           {"rmax": (4, 8), "lines": (2, 4)},       # FP64 default
+           {"rmax": (4, 8), "lines": (1, 4)},       # FP32 default
+           {"rmax": (8, 8), "lines": (1, 4)},
+           {"rmax": (16, 16), "lines": (1, 4)},
+           {"rmax": (8, 8), "lines": (2, 4)},
+           {"rmax": (4, 8), "lines": (1, 2)},
+           {"rmax": (16, 4), "lines": (4, 1)}]
+
+
+def padded_len(m):
+    return m + (m >> 3) + 1
+
+
+def pad(s):
+    return s + (s >> 3)
+
+
+def threads_max(rmax):
+    return 256 if rmax == 16 else 4096 // rmax
+
+
+def pass_geo(d, n, axis, fp64, max_dyn, cfg=DEFAULT_CFG):
     m = n + 1
-    G = max(1, min(64, m // 16))
+    col = 0 if axis == d - 1 else 1
+    rmax = cfg["rmax"][col]
+    G = max(1, m // rmax)
+    tmax = threads_max(rmax)
     elem = 16 if fp64 else 8
-    perline = (2 * m + 2) * elem
-    L = 256 // G
-    while L > 1 and L * perline > max_dyn:
+    perline = 2 * padded_len(m) * elem
+    q4 = m // 4 if m >= 4 else 1
+    table = ((q4 - 1) + ((q4 - 1) >> 3) + 1 if m >= 4 else 1) * elem
+    gref = 1024 // rmax
+    L = cfg["lines"][col] * max(1, gref // G)
+    L = max(1, min(L, tmax // G))
+    while L > 1 and L * (perline + 8 + elem // 2) + table > max_dyn:
         L //= 2
     while G * L < 64:
         L *= 2
     stride = n ** (d - 1 - axis)
     nlines = n ** (d - 1)
     blocks = (nlines + L - 1) // L
-    return dict(G=G, L=L, lds=L * perline, stride=stride, nlines=nlines, blocks=blocks)
+    lds = L * perline + table + L * (8 + elem // 2)
+    return dict(G=G, L=L, lds=lds, stride=stride, nlines=nlines, blocks=blocks, rmax=rmax, tmax=tmax)
 
 
 def magic(n):
@@ -53,22 +83,26 @@ SIZES = [(d, n) for d in (1, 2, 3) for n in (1, 3, 7, 15, 31, 63, 127, 255, 511,
          if n ** d <= 1023 ** 2 or (d == 3 and n <= 255)]
 
 
+@pytest.mark.parametrize("cfg", range(len(CONFIGS)))
 @pytest.mark.parametrize("max_dyn", [MAX_LDS_BLOCK - STATIC_LDS, 64 * 1024 - STATIC_LDS])
 @pytest.mark.parametrize("d,n", SIZES)
-def test_pass_addresses(d, n, max_dyn):
+def test_pass_addresses(d, n, max_dyn, cfg):
     N = n ** d
     m = n + 1
     for axis in range(d):
         for fp64 in (True, False):
-            g = pass_geo(d, n, axis, fp64, max_dyn)
+            g = pass_geo(d, n, axis, fp64, max_dyn, CONFIGS[cfg])
             G, L, stride = g["G"], g["L"], g["stride"]
             T = G * L
-            assert 64 <= T <= 256 and T % 64 == 0
+            assert 64 <= T <= g["tmax"] and T % 64 == 0
             assert g["lds"] <= max_dyn
-            assert L <= 256 and (L & (L - 1)) == 0 and (G & (G - 1)) == 0
-            assert G >= m // 16          # per-thread register arrays of the stages
+            assert (L & (L - 1)) == 0 and (G & (G - 1)) == 0
+            assert G >= m // g["rmax"]      # per-thread register arrays of the stages
+            MAX_EPT_LINE = g["rmax"]
             assert -(-n // G) <= MAX_EPT_LINE
-            LS = 2 * m + 2
+            # reduction scratch ((restart max + 2) x wavefronts complex sums) fits the line buffers
+            assert 66 * (T // 64) * 16 <= L * 2 * padded_len(m) * (16 if fp64 else 8)
+            LS = 2 * padded_len(m)
             contiguous = stride == 1
             mg = magic(n)
             # all blocks for small grids, a sample for large ones
@@ -89,7 +123,7 @@ def test_pass_addresses(d, n, max_dyn):
                 # each (line, unknown) exactly once
                 assert len(set(zip(ls.tolist(), js.tolist()))) == E
                 # LDS slot of the element
-                assert (ls * LS + js + 1).max() < L * LS
+                assert (ls * LS + np.array([pad(int(j) + 1) for j in js])).max() < L * LS
                 lg = blk * L + ls
                 valid = lg < g["nlines"]
                 o = lg // stride
@@ -105,22 +139,36 @@ def test_pass_addresses(d, n, max_dyn):
                 assert np.all(seen == 1), (axis, fp64)
 
 
-def stage_plan(m):
+def stage_plan(m, rmax):
     plan, ns = [], 1
     while ns < m:
         rem = m // ns
-        r = 16 if rem >= 16 else rem
+        r = rmax if rem >= rmax else rem
         plan.append((r, ns))
         ns *= r
     return plan
 
 
+@pytest.mark.parametrize("rmax", [4, 8, 16])
 @pytest.mark.parametrize("m", [2, 4, 8, 16, 32, 64, 128, 256, 512, 1024])
-def test_line_fft_and_line_ops_indices(m):
-    G = max(1, min(64, m // 16))
-    for R, Ns in stage_plan(m):
+def test_line_fft_and_line_ops_indices(m, rmax):
+    G = max(1, m // rmax)
+    lgm = m.bit_length() - 1
+    PA = padded_len(m)
+    assert pad(m) < PA                     # slots 0..m fit one padded buffer
+    # padded first-stage stores (radix 4 and 8) and the stride-2 sine-transform
+    # output of 8 consecutive lanes hit 8 distinct 16-byte bank groups
+    for R in (4, 8):
+        if m >= 8 * R:
+            for r in range(R):
+                assert len({pad(b * R + r) % 8 for b in range(8)}) == 8
+    if m >= 16:
+        assert len({pad(2 * p) % 8 for p in range(8)}) == 8
+        # the padded quarter twiddle table holds m/4 entries
+        assert pad(m // 4 - 1) < (m // 4 - 1) + ((m // 4 - 1) >> 3) + 1
+    for R, Ns in stage_plan(m, rmax):
         nb = m // R
-        per = 16 // R
+        per = rmax // R
         touched_in, touched_out = [], []
         for lt in range(G):
             for q in range(per):
@@ -129,10 +177,15 @@ def test_line_fft_and_line_ops_indices(m):
                     continue
                 k = b & (Ns - 1)
                 step = k * ((2 * m) // (Ns * R))
+                tsh = lgm - (Ns.bit_length() - 1) - (R.bit_length() - 1)
                 for r in range(R):
                     touched_in.append(b + r * nb)
                     touched_out.append((b - k) * R + k + r * Ns)
                     assert r * step < 2 * m          # twiddle table W_{2m}
+                    q = (r * k) << tsh               # W_{Ns R}^{r k} = W_m^q
+                    assert q < m
+                    if k and r:
+                        assert lgm >= 2 and (q & ((1 << (lgm - 2)) - 1)) < max(1, m // 4)
         assert sorted(touched_in) == list(range(m))   # every slot read once
         assert sorted(touched_out) == list(range(m))  # and written once
     # sine-transform pairs (j, m-j), j <= m/2, and the output pass p < m/2
@@ -143,12 +196,12 @@ def test_line_fft_and_line_ops_indices(m):
             for s in ([0] if j == 0 else ([j] if j == half else [j, m - j])):
                 assert 0 <= s < m
                 slots.add(s)
-        for q in range(8):
+        for q in range(rmax // 2):
             p = lt + q * G
             if p < half:
                 assert 2 * p + 1 < m
     assert slots == set(range(m))
-    assert half // G <= 8 or G == 1 and half <= 8
+    assert -(-half // G) <= max(1, rmax // 2)
 
 
 @pytest.mark.parametrize("d,n", [(1, 1023), (2, 1023), (3, 255), (2, 7)])
@@ -159,9 +212,11 @@ def test_stream_kernels_and_partials(d, n):
     pmax = blocks
     for axis in range(d):
         for fp64 in (True, False):
-            pmax = max(pmax, pass_geo(d, n, axis, fp64, MAX_LDS_BLOCK - STATIC_LDS)["blocks"])
+            for cfg in CONFIGS:
+                assert pass_geo(d, n, axis, fp64, MAX_LDS_BLOCK - STATIC_LDS, cfg)["blocks"] <= n ** (d - 1)
+    pmax = max(blocks, n ** (d - 1))
     # reductions use at most pstride workgroups
-    assert min(1024, blocks) <= pmax
+    assert blocks <= pmax
     # FP32 basis (restart + 1 vectors of 8N bytes) fits the FP64 basis region
     for restart in (1, 2, 30, 64):
         assert (restart + 1) * 8 * N <= restart * 16 * N
