@@ -18,6 +18,9 @@ each launch in a separate instrumented run of the same steps; "cpu_baseline"
 times the CPU oracle on a bounded sample of the same workload.
 """
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -28,6 +31,9 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 TOL = 1e-10
+COPY_KERNEL = "__amd_rocclr_copyBuffer"
+COPY_BYTES = 256 << 20
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pass64_toep_next_wdots_d2_n1023.txt")
 
 
 def log(msg):
@@ -62,6 +68,95 @@ def kernel_profile(torch, s, u, un, steps, precision):
         r["ms_per_step"] = r["total_ms"] / steps
     rep.sort(key=lambda r: -r["total_ms"])
     return rep
+
+
+def source_hash():
+    """SHA-256 over the HIP sources and headers the library is built from."""
+    h = hashlib.sha256()
+    src = os.path.join(ROOT, "paper_2410_03643_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(src, "*"))):
+        if f.endswith((".hip", ".h", ".hpp")):
+            h.update(os.path.basename(f).encode())
+            with open(f, "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def read_keyvals(path):
+    out = {}
+    with open(path) as fh:
+        for line in fh:
+            line = line.strip()
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].split(": ", 1)
+                out[k.strip()] = v.strip().strip("`")
+    return out
+
+
+def committed_traffic(timing_name):
+    """HBM bytes per launch of `timing_name` from the committed counter summary,
+    or None when there is none or the kernels changed since it was taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = read_keyvals(TRAFFIC_FILE)
+    if kv.get("timing_name") != timing_name or kv.get("source_sha256") != source_hash():
+        return None
+    return float(kv["hbm_bytes_per_launch"])
+
+
+def summarize(dirs, timing_name, kernel_regex):
+    """Markdown summary of rocprofv3 CSV output (kernel stats and/or counters)."""
+    import re
+    rx = re.compile(kernel_regex) if kernel_regex else None
+    lines = []
+    per = {}   # (counter, kernel) -> [values]
+    for d in dirs:
+        for f in sorted(glob.glob(os.path.join(d, "**", "*_kernel_stats.csv"), recursive=True)):
+            lines.append("Kernel statistics (`%s`), durations in microseconds:" % os.path.basename(f))
+            lines.append("")
+            lines.append("| kernel | calls | avg us | min us | max us | total us | % |")
+            lines.append("|---|---|---|---|---|---|---|")
+            with open(f) as fh:
+                for r in csv.DictReader(fh):
+                    lines.append("| `%s` | %s | %.2f | %.2f | %.2f | %.1f | %.2f |" % (
+                        r["Name"], r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
+                        float(r["MaxNs"]) / 1e3, float(r["TotalDurationNs"]) / 1e3, float(r["Percentage"])))
+            lines.append("")
+        for f in sorted(glob.glob(os.path.join(d, "**", "*_counter_collection.csv"), recursive=True)):
+            with open(f) as fh:
+                for r in csv.DictReader(fh):
+                    per.setdefault((r["Counter_Name"], r["Kernel_Name"]), []).append(float(r["Counter_Value"]))
+    if per:
+        lines.append("Counters, KiB per dispatch (mean over dispatches):")
+        lines.append("")
+        lines.append("| counter | kernel | dispatches | mean KiB |")
+        lines.append("|---|---|---|---|")
+        factors = {}
+        for (cn, kn), vals in sorted(per.items()):
+            if kn == COPY_KERNEL:
+                # the calibration copies are the large dispatches of the copy kernel
+                vals = [v for v in vals if v >= 0.5 * max(vals)]
+                per[(cn, kn)] = vals
+                factors[cn] = (COPY_BYTES / 1024.0) / (sum(vals) / len(vals))
+            lines.append("| %s | `%s` | %d | %.1f |" % (cn, kn, len(vals), sum(vals) / len(vals)))
+        lines.append("")
+        for cn, fct in sorted(factors.items()):
+            lines.append("- %s_copy_factor: %.4f" % (cn.lower(), fct))
+        if rx:
+            tot = 0.0
+            for cn in ("FETCH_SIZE", "WRITE_SIZE"):
+                vals = [v for (c, kn), vs in per.items() if c == cn and rx.search(kn) for v in vs]
+                if not vals or cn not in factors:
+                    tot = None
+                    break
+                b = sum(vals) / len(vals) * 1024.0 * factors[cn]
+                lines.append("- %s_bytes_per_launch: %.0f" % (cn.lower(), b))
+                tot += b
+            if tot is not None:
+                lines.append("- timing_name: %s" % timing_name)
+                lines.append("- hbm_bytes_per_launch: %.0f" % tot)
+                lines.append("- source_sha256: %s" % source_hash())
+    print("\n".join(lines))
 
 
 def cpu_baseline(p, seconds):
@@ -100,9 +195,18 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run three plain 256 MiB device copies (reference for HBM byte counters)")
+    ap.add_argument("--summarize", nargs="+", metavar="DIR",
+                    help="print a markdown summary of rocprofv3 CSV output directories and exit (no GPU)")
+    ap.add_argument("--kernel-regex", default=None,
+                    help="with --summarize: the kernel whose counters give the traffic figure")
+    ap.add_argument("--timing-name", default="pass64.toep_next_wdots.ax0",
+                    help="with --summarize: that kernel's name in the per-launch timing report")
     args = ap.parse_args()
+    if args.summarize:
+        summarize(args.summarize, args.timing_name, args.kernel_regex)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the solver has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
@@ -113,12 +217,12 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda", 0)
     if args.copy_calibration:
-        src = torch.ones(256 << 20, dtype=torch.uint8, device=dev)
+        src = torch.ones(COPY_BYTES, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
-        log("copy calibration: 3 x 256 MiB device-to-device copies")
+        log("copy calibration: 3 x %d MiB device-to-device copies" % (COPY_BYTES >> 20))
         del src, dst
     p = inputs.metric_case()
     log("workload %s: N=%d" % (p.name, p.N))
@@ -146,9 +250,10 @@ def main():
     other = "fp32_ir" if args.precision == "fp64" else "fp64"
     steps = args.steps
     dom = head["prof"][0]
+    traffic = committed_traffic(dom["name"])
     roofline = {"bound": "hbm", "kernel": dom["name"], "achieved": round(dom["gbs"], 1),
                 "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(dom["gbs"] / PEAK_HBM_GBS, 4),
-                "traffic": None, "avg_us": round(dom["avg_us"], 2),
+                "traffic": None if traffic is None else int(traffic), "avg_us": round(dom["avg_us"], 2),
                 "bytes_per_launch": int(dom["bytes_per_launch"])}
     total_bytes = sum(r["bytes"] for r in head["prof"]) / args.profile_steps
     step_ms = 1e3 * head["wall"] / steps

@@ -172,13 +172,16 @@ int fnls_first_step(fnls_ctx *ctx, const fnls_c128 *u0, fnls_c128 *u1, const fnl
                     fnls_info *info);
 
 /* Per-kernel timing (optional instrumentation, used by the benchmark).
- * fnls_timing(ctx, 1) clears earlier records and brackets every following
- * kernel launch of this context with a pair of HIP events on its stream;
- * fnls_timing(ctx, 0) stops recording.  fnls_timing_report waits for the
+ * fnls_timing(ctx, 1) clears earlier records; every following kernel launch
+ * of this context then carries a pair of HIP events that the runtime records
+ * at the kernel's start and end (hipExtLaunchKernel), so a record is the
+ * kernel's own execution time; fnls_timing(ctx, 0) stops recording.  fnls_timing_report waits for the
  * stream and writes one entry per kernel class (at most max_entries): the
  * number of launches, their summed event time in milliseconds, and their
  * summed algorithmic bytes (every vector a launch must read once and write
- * once).  Returns the number of entries written, or a negative status. */
+ * once).  Launches of GMRES iterations that were enqueued ahead of the
+ * stopping decision and then skipped by the device count with their time and
+ * zero bytes.  Returns the number of entries written, or a negative status. */
 typedef struct {
     char name[64];
     int launches;

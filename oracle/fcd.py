@@ -10,9 +10,11 @@ Test infrastructure only (see the package docstring).
   (c_0, ..., c_{M-1}), mu = dt / h^alpha (Sec. 2.1).
 * HC(T_1), tau(T_1) = T_1 - HC(T_1) (Sec. 4, tau-matrix definition and
   Hankel-correction layout; the garbled middle rows are read as three zero
-  anti-diagonals).
+  anti-diagonals r + s in {M, M+1, M+2}, the one reading under which the sine
+  transform diagonalises tau(T_1)).
 * S, the sine transform (Sec. 4), with the orthonormal scaling sqrt(2/(M+1))
-  (the printed sqrt(1/(M+1)) would make S^2 = I/2).
+  (the printed sqrt(1/(M+1)) would make S^2 = I/2, so tau = S Lambda S could
+  not hold).
 * lambda_k, the eigenvalues of tau(T_1), from the cosine sum of its first
   row (Sec. 4: "determined by its first column").
 """

@@ -3,11 +3,12 @@
 Test infrastructure only (see the package docstring).
 
 Follows the protocol of Sec. 5: zero initial guess, stopping on the l2
-relative residual ||b - A x|| / ||b||, at most 2000 iterations.  The readings
-for what the paper leaves open (right preconditioning, classical Gram-Schmidt
-applied twice, the Givens convention, the restart length, the breakdown test)
-are listed in the design doc; this loop fixes one convention so that the GPU
-solver's intermediate quantities are directly comparable:
+relative residual ||b - A x|| / ||b||, at most 2000 iterations.  The paper
+leaves open the side of the preconditioner, the Arnoldi variant, the Givens
+convention, the restart length and the breakdown test; this loop takes right
+preconditioning (so the monitored residual is the true one), classical
+Gram-Schmidt applied twice, restart 30 and the conventions below, so that the
+GPU solver's intermediate quantities are directly comparable:
 
 * Arnoldi step j: w = A (P^{-1} v_j); h1 = V^H w; w -= V h1; h2 = V^H w;
   w -= V h2; h_{:, j} = h1 + h2; h_{j+1, j} = ||w||; v_{j+1} = w / h_{j+1, j}.

@@ -26,7 +26,8 @@ def build(verbose: bool = False, extra_flags=()) -> str:
     """Compile every HIP source into libfnls.so (always recompiles)."""
     objs = []
     flags = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
-             # packed FP32 instructions stay disabled (see DESIGN.md)
+             # packed FP32 instructions stay disabled: some of their forms have
+             # given wrong results on MI355X with no error
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-I", os.path.join(ROOT, "include"), "-I", CSRC, *extra_flags]
     for src in SOURCES:

@@ -179,7 +179,7 @@ struct fnls_ctx {
     // optional per-launch timing (fnls_timing / fnls_timing_report)
     struct TimingRec {
         int cls;
-        hipEvent_t a, b;
+        LaunchEvents ev;
         double bytes;
     };
     int timing = 0;
@@ -234,22 +234,23 @@ int class_id(fnls_ctx* c, const std::string& name) {
     return (int)c->class_names.size() - 1;
 }
 
-// Begin a timed launch; returns the record index or -1 when timing is off.
-int timing_begin(fnls_ctx* c, const std::string& name, double bytes) {
-    if (!c->timing) return -1;
+// Start a timing record for the next launch: returns the events the runtime
+// records at that kernel's start and end, or nullptr when timing is off.
+const LaunchEvents* timing_begin(fnls_ctx* c, const std::string& name, double bytes) {
+    if (!c->timing) return nullptr;
     fnls_ctx::TimingRec r;
     r.cls = class_id(c, name);
-    r.a = pool_event(c);
-    r.b = pool_event(c);
+    r.ev.start = pool_event(c);
+    r.ev.stop = pool_event(c);
     r.bytes = bytes;
-    if (!r.a || !r.b) return -1;
-    (void)hipEventRecord(r.a, c->stream);
+    if (!r.ev.start || !r.ev.stop) return nullptr;
     c->recs.push_back(r);
-    return (int)c->recs.size() - 1;
+    return &c->recs.back().ev;
 }
 
-void timing_end(fnls_ctx* c, int rec) {
-    if (rec >= 0) (void)hipEventRecord(c->recs[rec].b, c->stream);
+// Drop the record of a launch that failed (its events were never recorded).
+void timing_failed(fnls_ctx* c, const LaunchEvents* te) {
+    if (te && !c->recs.empty()) c->recs.pop_back();
 }
 
 }  // namespace
@@ -330,9 +331,9 @@ double pass_bytes(fnls_ctx* c, bool fp64, const PassVariant& v, const PassArgs& 
 
 int run_pass(fnls_ctx* c, bool fp64, int axis, PassVariant v, PassArgs& a, const Geo& g) {
     v.rmax = g.rmax;
-    const int rec = c->timing ? timing_begin(c, pass_name(fp64, v, axis), pass_bytes(c, fp64, v, a)) : -1;
-    hipError_t e = launch_pass(fp64 ? 1 : 0, v, a, g.blocks, g.lds, c->stream);
-    timing_end(c, rec);
+    const LaunchEvents* te = c->timing ? timing_begin(c, pass_name(fp64, v, axis), pass_bytes(c, fp64, v, a)) : nullptr;
+    hipError_t e = launch_pass(fp64 ? 1 : 0, v, a, g.blocks, g.lds, c->stream, te);
+    if (e != hipSuccess) timing_failed(c, te);
     if (e != hipSuccess)
         return set_err(c, FNLS_ERR_HIP, "pass launch (axis %d, ops %d) failed: %s", axis, v.ops, hipGetErrorString(e));
     return FNLS_OK;
@@ -461,9 +462,9 @@ int matvec64(fnls_ctx* c, const void* x, void* y, double cD, double ci, double c
 
 // One-workgroup decision / reduction kernel (k_finish).
 int run_finish(fnls_ctx* c, const StreamArgs& s, const char* name) {
-    const int rec = c->timing ? timing_begin(c, name, 16.0 * s.pin_nb) : -1;
-    hipError_t e = launch_finish(s, c->stream);
-    timing_end(c, rec);
+    const LaunchEvents* te = c->timing ? timing_begin(c, name, 16.0 * s.pin_nb) : nullptr;
+    hipError_t e = launch_finish(s, c->stream, te);
+    if (e != hipSuccess) timing_failed(c, te);
     if (e != hipSuccess) return set_err(c, FNLS_ERR_HIP, "finish launch failed: %s", hipGetErrorString(e));
     return FNLS_OK;
 }
@@ -546,18 +547,18 @@ int arnoldi_step(fnls_ctx* c, bool fp64, Bufs& b, int j) {
     s.pin_nb = nb1;
     if ((rc = reduce_if_wide(c, s, j + 2)) != FNLS_OK) return rc;
     s.pout = c->at<double2>(c->lay.p2);
-    int rec = c->timing ? timing_begin(c, fp64 ? "cgs64.update_dots" : "cgs32.update_dots", cgs_bytes) : -1;
-    hipError_t e = launch_cgs(fp64 ? 1 : 0, 0, s, blocks, c->stream);
-    timing_end(c, rec);
+    const LaunchEvents* te = c->timing ? timing_begin(c, fp64 ? "cgs64.update_dots" : "cgs32.update_dots", cgs_bytes) : nullptr;
+    hipError_t e = launch_cgs(fp64 ? 1 : 0, 0, s, blocks, c->stream, te);
+    if (e != hipSuccess) timing_failed(c, te);
     if (e != hipSuccess) return set_err(c, FNLS_ERR_HIP, "cgs launch failed: %s", hipGetErrorString(e));
     // second update (reorthogonalisation)
     s.pin = c->at<double2>(c->lay.p2);
     s.pin_nb = blocks;
     if ((rc = reduce_if_wide(c, s, j + 1)) != FNLS_OK) return rc;
     s.pout = c->at<double2>(c->lay.p3);
-    rec = c->timing ? timing_begin(c, fp64 ? "cgs64.update_norm" : "cgs32.update_norm", cgs_bytes) : -1;
-    e = launch_cgs(fp64 ? 1 : 0, 1, s, blocks, c->stream);
-    timing_end(c, rec);
+    te = c->timing ? timing_begin(c, fp64 ? "cgs64.update_norm" : "cgs32.update_norm", cgs_bytes) : nullptr;
+    e = launch_cgs(fp64 ? 1 : 0, 1, s, blocks, c->stream, te);
+    if (e != hipSuccess) timing_failed(c, te);
     if (e != hipSuccess) return set_err(c, FNLS_ERR_HIP, "cgs launch failed: %s", hipGetErrorString(e));
     // Givens step and stopping decision
     s.pin = c->at<double2>(c->lay.p3);
@@ -706,12 +707,23 @@ int wait_status(fnls_ctx* c, hipEvent_t ev, HostStatus* out) {
 // `lookahead` iterations enqueued beyond the one whose status is awaited.
 // Returns FNLS_OK and sets *done when the solve ended before the cycle
 // started (b == 0 or non-finite b).
-int run_cycle(fnls_ctx* c, bool fp64, Bufs& b, int restart, int lookahead, int* done) {
+int run_cycle(fnls_ctx* c, bool fp64, Bufs& b, int restart, int lookahead, int total_before, int* total_after,
+              int* done) {
     int issued = 0, waited = 0;
     *done = 0;
     HostStatus hs;
+    // first timing record of every issued iteration: launches of iterations
+    // that the device skipped (issued ahead of the stopping decision) carry
+    // no algorithmic bytes
+    std::vector<size_t> rec_first;
+    auto unbill = [&](int active) {
+        if (!c->timing) return;
+        for (int i = std::max(0, active); i < issued; ++i)
+            for (size_t r = rec_first[i]; r < c->recs.size(); ++r) c->recs[r].bytes = 0.0;
+    };
     while (true) {
         while (issued < restart && issued <= waited + lookahead) {
+            rec_first.push_back(c->recs.size());
             int rc = arnoldi_step(c, fp64, b, issued);
             if (rc != FNLS_OK) return rc;
             HIPCHK(c, hipEventRecord(c->ev[issued % kEvents], c->stream));
@@ -722,11 +734,14 @@ int run_cycle(fnls_ctx* c, bool fp64, Bufs& b, int restart, int lookahead, int* 
         ++waited;
         if (hs.done) {
             *done = 1;
+            unbill(0);
             return FNLS_OK;
         }
         if (hs.stopped || waited >= restart) break;
     }
-    c->cur_k = hs.total - c->cur_k;   // iterations of this cycle (caller set cur_k = total before)
+    *total_after = hs.total;
+    c->cur_k = hs.total - total_before;   // iterations of this cycle
+    unbill(c->cur_k);
     // let any speculative (inactive) iterations drain before the final passes
     return FNLS_OK;
 }
@@ -759,9 +774,9 @@ int solve_impl(fnls_ctx* c, const fnls_c128* b, fnls_c128* x, const fnls_opts* o
     s.st = c->st();
     s.hs = c->hs_dev;
     {
-        const int rec = c->timing ? timing_begin(c, "prepare", (fp64 ? 16.0 : 24.0) * (double)c->N) : -1;
-        hipError_t e = launch_prepare(s, stream_blocks(c->N), c->stream);
-        timing_end(c, rec);
+        const LaunchEvents* te = c->timing ? timing_begin(c, "prepare", (fp64 ? 16.0 : 24.0) * (double)c->N) : nullptr;
+        hipError_t e = launch_prepare(s, stream_blocks(c->N), c->stream, te);
+        if (e != hipSuccess) timing_failed(c, te);
         if (e != hipSuccess) return set_err(c, FNLS_ERR_HIP, "prepare launch failed: %s", hipGetErrorString(e));
         StreamArgs f = s;
         f.pin = c->at<double2>(c->lay.pr);
@@ -773,11 +788,11 @@ int solve_impl(fnls_ctx* c, const fnls_c128* b, fnls_c128* x, const fnls_opts* o
     }
     int first = 1;
     int status = FNLS_OK;
+    int total = 0;   // iterations so far, as last reported by the device
     while (true) {
         Bufs bf = bufs(c, fp64, first ? (const void*)b : (const void*)c->at<double2>(c->lay.r64));
         int done = 0;
-        c->cur_k = c->hs->total;
-        int rc = run_cycle(c, fp64, bf, restart, std::max(0, o->lookahead), &done);
+        int rc = run_cycle(c, fp64, bf, restart, std::max(0, o->lookahead), total, &total, &done);
         if (rc != FNLS_OK) return rc;
         if (done) {
             // b == 0 (x = 0) or non-finite b
@@ -1000,7 +1015,12 @@ static int precond_setup_scaled(fnls_ctx* c, const fnls_c128* u, const double* V
     s.rho = c->rho;
     s.tau = tau;
     const int blocks = (int)std::min<long long>(4096, (c->N + 255) / 256);
-    HIPCHK(c, launch_precond_setup(s, blocks, c->stream));
+    const LaunchEvents* te = c->timing ? timing_begin(c, "precond_setup", 28.0 * (double)c->N) : nullptr;
+    hipError_t e = launch_precond_setup(s, blocks, c->stream, te);
+    if (e != hipSuccess) {
+        timing_failed(c, te);
+        return set_err(c, FNLS_ERR_HIP, "precond_setup launch failed: %s", hipGetErrorString(e));
+    }
     c->omega = omega;
     c->have_D = 1;
     return FNLS_OK;
@@ -1146,7 +1166,7 @@ int fnls_timing_report(fnls_ctx* c, fnls_kernel_stat* out, int max_entries) {
     }
     for (const auto& r : c->recs) {
         float ms = 0.f;
-        HIPCHK(c, hipEventElapsedTime(&ms, r.a, r.b));
+        HIPCHK(c, hipEventElapsedTime(&ms, r.ev.start, r.ev.stop));
         agg[r.cls].launches += 1;
         agg[r.cls].total_ms += ms;
         agg[r.cls].bytes += r.bytes;

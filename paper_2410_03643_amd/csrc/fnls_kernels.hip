@@ -219,6 +219,20 @@ __device__ __forceinline__ void stc(void* p, long long idx, cplx<R> v) {
     reinterpret_cast<cplx<R>*>(p)[idx] = v;
 }
 
+// Workgroups are dealt round-robin to the 8 XCDs, each with its own L2.
+// Remap the workgroup index so that every XCD works through one contiguous
+// range of line blocks: on strided axes neighbouring blocks share 128-byte
+// cache lines (a block covers L < 8 complex values per row), and they then
+// meet in the same L2 instead of each XCD fetching the whole line.
+__device__ __forceinline__ int xcd_block() {
+    constexpr int kXcd = 8;
+    const int nb = (int)gridDim.x;
+    const int i = (int)blockIdx.x;
+    const int x = i % kXcd, q = i / kXcd;
+    const int base = nb / kXcd, rem = nb % kXcd;
+    return x * base + min(x, rem) + q;
+}
+
 // ---------------------------------------------------------------------------
 // the fused axis pass
 // ---------------------------------------------------------------------------
@@ -276,8 +290,9 @@ __global__ __launch_bounds__(PassThreads<RMAX>::v) void k_pass(PassArgs a) {
     };
 
     // per-line base offset and Lambda of the other axes
+    const int blk = xcd_block();
     for (int l = tid; l < L; l += T) {
-        const long long lg = (long long)blockIdx.x * L + l;
+        const long long lg = (long long)blk * L + l;
         long long base = -1;
         R lamo = 0;
         if (lg < a.nlines) {
@@ -706,12 +721,29 @@ __global__ void k_config(GmresState* st, double tol, double outer_tol, int resta
 // ---------------------------------------------------------------------------
 }  // namespace fnls
 
+#include <hip/hip_ext.h>
+
 #include "fnls_launch.h"
 
 namespace fnls {
 
+// Launch `kern` with the given arguments; with events, the runtime records
+// them at the kernel's start and end.
+template <typename K, typename... Args>
+static hipError_t launch_k(K kern, dim3 grid, dim3 block, size_t lds, hipStream_t s, const LaunchEvents* te,
+                           Args... args) {
+    (void)hipGetLastError();   // clear errors of earlier, unrelated runtime calls
+    if (te) {
+        void* argv[] = {reinterpret_cast<void*>(&args)...};
+        return hipExtLaunchKernel(reinterpret_cast<const void*>(kern), grid, block, argv, lds, s, te->start,
+                                  te->stop, 0);
+    }
+    hipLaunchKernelGGL(kern, grid, block, lds, s, args...);
+    return hipGetLastError();
+}
+
 template <typename R, int RMAX, int LGM, int INM, int OPS, int ZM, int OUTM, int FIN>
-static hipError_t launch_pass_t(const PassArgs& a, int blocks, size_t lds, hipStream_t s) {
+static hipError_t launch_pass_t(const PassArgs& a, int blocks, size_t lds, hipStream_t s, const LaunchEvents* te) {
     auto kern = k_pass<R, RMAX, LGM, INM, OPS, ZM, OUTM, FIN>;
     // dynamic LDS above 64 KiB must be allowed per kernel; remember the largest granted
     static size_t granted = 64 * 1024;
@@ -723,31 +755,31 @@ static hipError_t launch_pass_t(const PassArgs& a, int blocks, size_t lds, hipSt
     }
     if (a.G * a.L > PassThreads<RMAX>::v) return hipErrorInvalidConfiguration;
     if (LGM && (a.lgm != LGM || a.G != (1 << LGM) / RMAX)) return hipErrorInvalidConfiguration;
-    (void)hipGetLastError();   // clear errors of earlier, unrelated runtime calls
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(a.G * a.L), lds, s, a);
-    return hipGetLastError();
+    return launch_k(kern, dim3(blocks), dim3(a.G * a.L), lds, s, te, a);
 }
 
 template <typename R, int INM, int OPS, int ZM, int OUTM, int FIN>
-static hipError_t launch_pass_r(int rmax, const PassArgs& a, int blocks, size_t lds, hipStream_t s) {
+static hipError_t launch_pass_r(int rmax, const PassArgs& a, int blocks, size_t lds, hipStream_t s,
+                                const LaunchEvents* te) {
     if (a.lgm == 10) {   // m = 1024: compile-time plan
-        if (rmax == 4) return launch_pass_t<R, 4, 10, INM, OPS, ZM, OUTM, FIN>(a, blocks, lds, s);
-        if (rmax == 8) return launch_pass_t<R, 8, 10, INM, OPS, ZM, OUTM, FIN>(a, blocks, lds, s);
+        if (rmax == 4) return launch_pass_t<R, 4, 10, INM, OPS, ZM, OUTM, FIN>(a, blocks, lds, s, te);
+        if (rmax == 8) return launch_pass_t<R, 8, 10, INM, OPS, ZM, OUTM, FIN>(a, blocks, lds, s, te);
     }
     switch (rmax) {
-        case 4: return launch_pass_t<R, 4, 0, INM, OPS, ZM, OUTM, FIN>(a, blocks, lds, s);
-        case 8: return launch_pass_t<R, 8, 0, INM, OPS, ZM, OUTM, FIN>(a, blocks, lds, s);
-        case 16: return launch_pass_t<R, 16, 0, INM, OPS, ZM, OUTM, FIN>(a, blocks, lds, s);
+        case 4: return launch_pass_t<R, 4, 0, INM, OPS, ZM, OUTM, FIN>(a, blocks, lds, s, te);
+        case 8: return launch_pass_t<R, 8, 0, INM, OPS, ZM, OUTM, FIN>(a, blocks, lds, s, te);
+        case 16: return launch_pass_t<R, 16, 0, INM, OPS, ZM, OUTM, FIN>(a, blocks, lds, s, te);
         default: return hipErrorInvalidValue;
     }
 }
 
 #define FNLS_PASS_CASE(R, INM, OPS, ZM, OUTM, FIN)                                            \
     if (v.inm == INM && v.ops == (OPS) && v.zm == ZM && v.outm == OUTM && v.fin == FIN)       \
-        return launch_pass_r<R, INM, OPS, ZM, OUTM, FIN>(v.rmax, a, blocks, lds, s);
+        return launch_pass_r<R, INM, OPS, ZM, OUTM, FIN>(v.rmax, a, blocks, lds, s, te);
 
 template <typename R>
-static hipError_t dispatch_pass(const PassVariant& v, const PassArgs& a, int blocks, size_t lds, hipStream_t s) {
+static hipError_t dispatch_pass(const PassVariant& v, const PassArgs& a, int blocks, size_t lds, hipStream_t s,
+                                const LaunchEvents* te) {
     constexpr int DST = OP_DST1;
     constexpr int DDD = OP_DST1 | OP_DIV | OP_DST2;
     constexpr int LASTDST = OP_DST1 | OP_SCALE;
@@ -781,45 +813,34 @@ static hipError_t dispatch_pass(const PassVariant& v, const PassArgs& a, int blo
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_pass(int fp64, const PassVariant& v, const PassArgs& a, int blocks, size_t lds, hipStream_t s) {
-    return fp64 ? dispatch_pass<double>(v, a, blocks, lds, s) : dispatch_pass<float>(v, a, blocks, lds, s);
+hipError_t launch_pass(int fp64, const PassVariant& v, const PassArgs& a, int blocks, size_t lds, hipStream_t s,
+                       const LaunchEvents* te) {
+    return fp64 ? dispatch_pass<double>(v, a, blocks, lds, s, te) : dispatch_pass<float>(v, a, blocks, lds, s, te);
 }
 
-hipError_t launch_precond_setup(const StreamArgs& a, int blocks, hipStream_t s) {
-    (void)hipGetLastError();
-    hipLaunchKernelGGL(k_precond_setup, dim3(blocks), dim3(kStreamThreads), 0, s, a);
-    return hipGetLastError();
+hipError_t launch_precond_setup(const StreamArgs& a, int blocks, hipStream_t s, const LaunchEvents* te) {
+    return launch_k(k_precond_setup, dim3(blocks), dim3(kStreamThreads), 0, s, te, a);
 }
 
-hipError_t launch_prepare(const StreamArgs& a, int blocks, hipStream_t s) {
-    (void)hipGetLastError();
-    hipLaunchKernelGGL(k_prepare, dim3(blocks), dim3(kStreamThreads), 0, s, a);
-    return hipGetLastError();
+hipError_t launch_prepare(const StreamArgs& a, int blocks, hipStream_t s, const LaunchEvents* te) {
+    return launch_k(k_prepare, dim3(blocks), dim3(kStreamThreads), 0, s, te, a);
 }
 
-hipError_t launch_finish(const StreamArgs& a, hipStream_t s) {
-    (void)hipGetLastError();
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(kStreamThreads), 0, s, a);
-    return hipGetLastError();
+hipError_t launch_finish(const StreamArgs& a, hipStream_t s, const LaunchEvents* te) {
+    return launch_k(k_finish, dim3(1), dim3(kStreamThreads), 0, s, te, a);
 }
 
-hipError_t launch_cgs(int fp64, int mode, const StreamArgs& a, int blocks, hipStream_t s) {
-    (void)hipGetLastError();
-    if (fp64) {
-        if (mode == 0) hipLaunchKernelGGL((k_cgs<double, 0>), dim3(blocks), dim3(kStreamThreads), 0, s, a);
-        else hipLaunchKernelGGL((k_cgs<double, 1>), dim3(blocks), dim3(kStreamThreads), 0, s, a);
-    } else {
-        if (mode == 0) hipLaunchKernelGGL((k_cgs<float, 0>), dim3(blocks), dim3(kStreamThreads), 0, s, a);
-        else hipLaunchKernelGGL((k_cgs<float, 1>), dim3(blocks), dim3(kStreamThreads), 0, s, a);
-    }
-    return hipGetLastError();
+hipError_t launch_cgs(int fp64, int mode, const StreamArgs& a, int blocks, hipStream_t s, const LaunchEvents* te) {
+    const dim3 g(blocks), b(kStreamThreads);
+    if (fp64)
+        return mode == 0 ? launch_k(k_cgs<double, 0>, g, b, 0, s, te, a) : launch_k(k_cgs<double, 1>, g, b, 0, s, te, a);
+    return mode == 0 ? launch_k(k_cgs<float, 0>, g, b, 0, s, te, a) : launch_k(k_cgs<float, 1>, g, b, 0, s, te, a);
 }
 
 hipError_t launch_config(GmresState* st, double tol, double outer_tol, int restart, int maxit, int fixed_iters,
                          int max_outer, hipStream_t s) {
-    (void)hipGetLastError();
-    hipLaunchKernelGGL(k_config, dim3(1), dim3(1), 0, s, st, tol, outer_tol, restart, maxit, fixed_iters, max_outer);
-    return hipGetLastError();
+    return launch_k(k_config, dim3(1), dim3(1), 0, s, nullptr, st, tol, outer_tol, restart, maxit, fixed_iters,
+                    max_outer);
 }
 
 }  // namespace fnls

@@ -14,12 +14,20 @@ struct PassVariant {
 
 enum PassOps { P_DST1 = 1, P_DIV = 2, P_DST2 = 4, P_SCALE = 8, P_TOEP = 16 };
 
-hipError_t launch_pass(int fp64, const PassVariant& v, const PassArgs& a, int blocks, size_t lds, hipStream_t s);
-hipError_t launch_precond_setup(const StreamArgs& a, int blocks, hipStream_t s);
-hipError_t launch_prepare(const StreamArgs& a, int blocks, hipStream_t s);
+// Optional pair of events that the runtime records at the start and at the end
+// of one kernel's execution (hipExtLaunchKernel); nullptr: plain launch.
+struct LaunchEvents {
+    hipEvent_t start, stop;
+};
+
+hipError_t launch_pass(int fp64, const PassVariant& v, const PassArgs& a, int blocks, size_t lds, hipStream_t s,
+                       const LaunchEvents* te = nullptr);
+hipError_t launch_precond_setup(const StreamArgs& a, int blocks, hipStream_t s, const LaunchEvents* te = nullptr);
+hipError_t launch_prepare(const StreamArgs& a, int blocks, hipStream_t s, const LaunchEvents* te = nullptr);
 // one workgroup: StreamArgs::mode = 0 prepare, 1 Givens, 2 residual (nv = 1 for IR), 3 reduce nv values
-hipError_t launch_finish(const StreamArgs& a, hipStream_t s);
-hipError_t launch_cgs(int fp64, int mode, const StreamArgs& a, int blocks, hipStream_t s);
+hipError_t launch_finish(const StreamArgs& a, hipStream_t s, const LaunchEvents* te = nullptr);
+hipError_t launch_cgs(int fp64, int mode, const StreamArgs& a, int blocks, hipStream_t s,
+                      const LaunchEvents* te = nullptr);
 hipError_t launch_config(GmresState* st, double tol, double outer_tol, int restart, int maxit, int fixed_iters,
                          int max_outer, hipStream_t s);
 

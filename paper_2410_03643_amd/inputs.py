@@ -13,10 +13,9 @@ shape (n,)*d.  The LAST axis is the first coordinate x_1 (it is the fastest
 running index, as in the column-stacking vec() of Sec. 2.2), the first axis is
 the last coordinate.
 
-The workloads (sizes, domains, alpha, rho, time step) follow the
-configurations listed in the design doc; the paper's own experiments (Sec. 5.1,
-5.2) use the same kind of data: u0 = sech(x) exp(2 i x) on [-20, 20] and a
-Gaussian on [-5, 5]^2.
+The named workloads below fix sizes, domains, alpha, rho and the time step;
+the paper's own experiments (Sec. 5.1, 5.2) use the same kind of data:
+u0 = sech(x) exp(2 i x) on [-20, 20] and a Gaussian on [-5, 5]^2.
 """
 from __future__ import annotations
 

@@ -139,6 +139,23 @@ def test_pass_addresses(d, n, max_dyn, cfg):
                 assert np.all(seen == 1), (axis, fp64)
 
 
+def xcd_block(i, nb, xcd=8):
+    x, q = i % xcd, i // xcd
+    base, rem = nb // xcd, nb % xcd
+    return x * base + min(x, rem) + q
+
+
+@pytest.mark.parametrize("nb", [1, 2, 7, 8, 9, 15, 16, 17, 63, 64, 255, 256, 257, 1023, 4097, 65025])
+def test_xcd_block_remap_is_a_permutation(nb):
+    """The workgroup -> line-block remap covers every block exactly once, and
+    the blocks of one XCD (workgroups i = x mod 8) are one contiguous range."""
+    lb = np.array([xcd_block(i, nb) for i in range(nb)])
+    assert sorted(lb.tolist()) == list(range(nb))
+    for x in range(min(8, nb)):
+        own = lb[x::8]
+        assert np.all(np.diff(own) == 1)
+
+
 def stage_plan(m, rmax):
     plan, ns = [], 1
     while ns < m:

@@ -136,7 +136,8 @@ def test_paper_1d_iteration_counts_are_an_upper_bound():
     """Sec. 5.1 tables print IT = 6 at tol 1e-8 for M = 6400 (time step not
     stated).  For any of a range of plausible time steps the oracle needs at
     most that many iterations (complex GMRES never needs more than the real
-    block form)."""
+    block form: the real Krylov space maps isometrically into the complex
+    one)."""
     table = json.load(open(os.path.join(GOLDEN, "paper_iteration_counts.json")))
     it_paper = table["tau_gmres_IT_1d"]["1.4"][0]
     n = table["tau_gmres_IT_1d"]["M"][0]
