@@ -473,6 +473,7 @@ int run_finish(fnls_ctx* c, const StreamArgs& s, const char* name) {
 // (one workgroup) so that consumer workgroups read a single entry per value.
 int reduce_if_wide(fnls_ctx* c, StreamArgs& s, int nv) {
     if (s.pin_nb <= kRedundantMax) return FNLS_OK;
+    if (nv > kMaxRestart + 2) return set_err(c, FNLS_ERR_INVALID_ARG, "reduction of %d values exceeds px", nv);
     StreamArgs r = s;
     r.mode = 3;
     r.nv = nv;
@@ -481,6 +482,7 @@ int reduce_if_wide(fnls_ctx* c, StreamArgs& s, int nv) {
     if (rc != FNLS_OK) return rc;
     s.pin = c->at<double2>(c->lay.px);
     s.pin_nb = 1;
+    s.pin_stride = 1;
     return FNLS_OK;
 }
 
@@ -545,6 +547,7 @@ int arnoldi_step(fnls_ctx* c, bool fp64, Bufs& b, int j) {
     // first Gram-Schmidt update (consumes the dots of the last pass)
     s.pin = c->at<double2>(c->lay.p1);
     s.pin_nb = nb1;
+    s.pin_stride = c->lay.pstride;
     if ((rc = reduce_if_wide(c, s, j + 2)) != FNLS_OK) return rc;
     s.pout = c->at<double2>(c->lay.p2);
     const LaunchEvents* te = c->timing ? timing_begin(c, fp64 ? "cgs64.update_dots" : "cgs32.update_dots", cgs_bytes) : nullptr;
@@ -554,6 +557,7 @@ int arnoldi_step(fnls_ctx* c, bool fp64, Bufs& b, int j) {
     // second update (reorthogonalisation)
     s.pin = c->at<double2>(c->lay.p2);
     s.pin_nb = blocks;
+    s.pin_stride = c->lay.pstride;
     if ((rc = reduce_if_wide(c, s, j + 1)) != FNLS_OK) return rc;
     s.pout = c->at<double2>(c->lay.p3);
     te = c->timing ? timing_begin(c, fp64 ? "cgs64.update_norm" : "cgs32.update_norm", cgs_bytes) : nullptr;
@@ -563,6 +567,7 @@ int arnoldi_step(fnls_ctx* c, bool fp64, Bufs& b, int j) {
     // Givens step and stopping decision
     s.pin = c->at<double2>(c->lay.p3);
     s.pin_nb = blocks;
+    s.pin_stride = c->lay.pstride;
     if ((rc = reduce_if_wide(c, s, 1)) != FNLS_OK) return rc;
     s.mode = 1;
     return run_finish(c, s, "finish.givens");
@@ -580,6 +585,7 @@ int cycle_final(fnls_ctx* c, bool fp64, Bufs& b, const void* b64, void* x, int f
     std::memset(&s, 0, sizeof s);
     s.pin = c->at<double2>(c->lay.pr);
     s.pin_nb = pass_geo(c->d, c->n, 0, true, c->max_dyn_lds, c->pcfg).blocks;
+    s.pin_stride = c->lay.pstride;
     s.pstride = c->lay.pstride;
     s.st = c->st();
     s.hs = c->hs_dev;
@@ -781,6 +787,7 @@ int solve_impl(fnls_ctx* c, const fnls_c128* b, fnls_c128* x, const fnls_opts* o
         StreamArgs f = s;
         f.pin = c->at<double2>(c->lay.pr);
         f.pin_nb = stream_blocks(c->N);
+        f.pin_stride = c->lay.pstride;
         f.mode = 0;
         int rc0 = reduce_if_wide(c, f, 1);
         if (rc0 == FNLS_OK) rc0 = run_finish(c, f, "finish.prepare");

@@ -131,9 +131,10 @@ struct StreamArgs {
     // norm / prepare
     const double2* b64;
     void* r32;            // optional complex64 copy
-    const double2* pin;   // partials of the producer kernel, layout [i][pstride]
+    const double2* pin;   // partials of the producer kernel, layout [i][pin_stride]
     int pin_nb;           // number of producer workgroups
-    double2* pout;        // this kernel's partials
+    int pin_stride;       // distance between the partials of consecutive values
+    double2* pout;        // this kernel's partials, layout [i][pstride]
     int pstride;
     GmresState* st;
     HostStatus* hs;

@@ -572,7 +572,7 @@ __global__ __launch_bounds__(256) void k_cgs(StreamArgs a) {
     const long long N = a.N;
     const int nv = a.nv;
     GmresState* st = a.st;
-    reduce_partials(a.pin, a.pstride, a.pin_nb, MODE == 0 ? nv + 1 : nv, s_tot, s_red);
+    reduce_partials(a.pin, a.pin_stride, a.pin_nb, MODE == 0 ? nv + 1 : nv, s_tot, s_red);
     if (threadIdx.x < nv) {
         const int i = threadIdx.x;
         const double sg = st->sigma[i];
@@ -669,10 +669,11 @@ __global__ __launch_bounds__(256) void k_finish(StreamArgs a) {
     GmresState* st = a.st;
     if (a.check_active && st->active == 0) return;
     const int nv = (a.mode == FIN_K_REDUCE) ? a.nv : 1;
-    reduce_partials(a.pin, a.pstride, a.pin_nb, nv, s_tot, s_red);
+    reduce_partials(a.pin, a.pin_stride, a.pin_nb, nv, s_tot, s_red);
     if (a.mode == FIN_K_REDUCE) {
-        // totals written as the partials of a single producer workgroup
-        for (int i = threadIdx.x; i < nv; i += blockDim.x) a.pout[(size_t)i * a.pstride] = s_tot[i];
+        // totals written contiguously: the partials of a single producer
+        // workgroup with stride 1 (pout holds kMaxRestart + 2 values)
+        for (int i = threadIdx.x; i < nv; i += blockDim.x) a.pout[i] = s_tot[i];
         return;
     }
     if (threadIdx.x != 0) return;

@@ -221,6 +221,40 @@ def test_line_fft_and_line_ops_indices(m, rmax):
     assert -(-half // G) <= max(1, rmax // 2)
 
 
+MAX_RESTART = 64
+REDUNDANT_MAX = 1024
+
+
+@pytest.mark.parametrize("cfg", range(len(CONFIGS)))
+@pytest.mark.parametrize("d,n", SIZES)
+def test_partial_buffers(d, n, cfg):
+    """Every per-workgroup partial written, and every one read back, lies in
+    its buffer: p1, p2 hold (restart max + 2) values x pstride, p3 and pr one
+    value x pstride, px (the pre-summed totals when a producer had more than
+    1024 workgroups) restart max + 2 contiguous values."""
+    N = n ** d
+    sblocks = max(1, -(-N // (STREAM_THREADS * KEPT)))
+    pstride = max(sblocks, n ** (d - 1))
+    size = {"p1": (MAX_RESTART + 2) * pstride, "p2": (MAX_RESTART + 2) * pstride,
+            "p3": pstride, "pr": pstride, "px": MAX_RESTART + 2}
+    for fp64 in (True, False):
+        nb0 = pass_geo(d, n, 0, fp64, MAX_LDS_BLOCK - STATIC_LDS, CONFIGS[cfg])["blocks"]
+        for restart in (1, 30, MAX_RESTART):
+            for j in range(restart):
+                # producer -> buffer, number of values, producer workgroups
+                chain = [("p1", j + 2, nb0),        # pass with the first dot products and ||w||^2
+                         ("p2", j + 1, sblocks),    # first update: second-round dots
+                         ("p3", 1, sblocks)]        # second update: ||w||^2
+                for buf, nv, nbp in chain:
+                    assert nbp <= pstride
+                    assert (nv - 1) * pstride + (nbp - 1) < size[buf]
+                    if nbp > REDUNDANT_MAX:
+                        # pre-sum kernel reads [i][pstride], writes px[i]
+                        assert nv <= size["px"]
+            for buf, nbp in (("pr", nb0), ("pr", sblocks)):  # residual, prepare
+                assert nbp <= pstride and nbp - 1 < size[buf]
+
+
 @pytest.mark.parametrize("d,n", [(1, 1023), (2, 1023), (3, 255), (2, 7)])
 def test_stream_kernels_and_partials(d, n):
     N = n ** d
