@@ -86,7 +86,10 @@ typedef struct {
     int restart;       /* GMRES restart length m (default 30; <= workspace capacity)     */
     int maxit;         /* total GMRES iterations allowed (default 2000, Sec. 5)          */
     int precision;     /* fnls_precision (default FNLS_FP64)                             */
-    double inner_tol;  /* FNLS_FP32_IR: inner relative tolerance (default 1e-5)          */
+    double inner_tol;  /* FNLS_FP32_IR: inner relative tolerance of the first refinement
+                          step (default 1e-5); later steps stop at
+                          max(inner_tol, tol / (2 relres)), relres the current outer
+                          relative residual                                              */
     int max_outer;     /* FNLS_FP32_IR: maximum refinement steps (default 20)            */
     int fixed_iters;   /* > 0: run exactly this many iterations, no tolerance test (FP64) */
     int lookahead;     /* iterations enqueued ahead of the host's convergence check

@@ -34,6 +34,7 @@ struct GmresState {
     double relres;      // last recomputed ||b - A x|| / ||b||
     double tol;         // GMRES tolerance for the estimate
     double outer_tol;   // tolerance on the recomputed residual
+    double inner_tol0;  // FP32-IR: requested inner tolerance (floor of the adaptive one)
     int j;              // current iteration within the cycle
     int k;              // basis size of the stopped cycle
     int total;          // total iterations

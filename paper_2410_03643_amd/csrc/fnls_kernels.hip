@@ -152,6 +152,10 @@ __device__ void residual_finish(GmresState* st, HostStatus* hs, double rn2, int 
     }
     st->done = done;
     if (!done) {
+        // FP32-IR: the next inner solve only has to bring this residual down
+        // to the outer tolerance (with a factor 2 to spare); never below the
+        // requested inner tolerance
+        if (ir) st->tol = fmax(st->inner_tol0, 0.5 * st->outer_tol / st->relres);
         st->refnorm = ir ? rn : st->bnorm;
         st->g[0] = dmk(rn, 0.0);
         st->sigma[0] = 1.0 / rn;
@@ -707,6 +711,7 @@ __global__ __launch_bounds__(256) void k_finish(StreamArgs a) {
 __global__ void k_config(GmresState* st, double tol, double outer_tol, int restart, int maxit, int fixed_iters,
                          int max_outer) {
     st->tol = tol;
+    st->inner_tol0 = tol;
     st->outer_tol = outer_tol;
     st->restart = restart;
     st->maxit = maxit;
