@@ -106,7 +106,7 @@ int stream_blocks(long long N) {
 struct Layout {
     size_t tw64, tw32, syme64, symo64, lam64, syme32, symo32, lam32;
     size_t state, p1, p2, p3, pr, px, D64, D32;
-    size_t t1, t2, zb, acc, r64, bbuf, V;
+    size_t t1, t2, Z, acc, r64, bbuf, V;
     size_t total;
     int pstride;
 };
@@ -144,7 +144,7 @@ Layout make_layout(int d, int n, int restart) {
     l.D32 = take((size_t)N * 4);
     l.t1 = take((size_t)N * 16);
     l.t2 = take((size_t)N * 16);
-    l.zb = take((size_t)N * 16);
+    l.Z = take((size_t)N * 16 * restart);   // preconditioned basis z_j = P^{-1} v_j
     l.acc = take((size_t)N * 16);
     l.r64 = take((size_t)N * 16);
     l.bbuf = take((size_t)N * 16);
@@ -343,7 +343,7 @@ int run_pass(fnls_ctx* c, bool fp64, int axis, PassVariant v, PassArgs& a, const
 struct Bufs {
     void* t1;
     void* t2;
-    void* zb;
+    void* zbase;  // preconditioned basis vectors z_j (typed), slot j at zbase + j N
     void* acc;
     void* v0;     // basis vector 0
     void* vbase;  // basis vectors 1..
@@ -353,7 +353,7 @@ Bufs bufs(fnls_ctx* c, bool fp64, const void* v0_fp64) {
     Bufs b;
     b.t1 = c->at<char>(c->lay.t1);
     b.t2 = c->at<char>(c->lay.t2);
-    b.zb = c->at<char>(c->lay.zb);
+    b.zbase = c->at<char>(c->lay.Z);
     b.acc = c->at<char>(c->lay.acc);
     if (fp64) {
         b.v0 = const_cast<void*>(v0_fp64);
@@ -514,7 +514,8 @@ int arnoldi_step(fnls_ctx* c, bool fp64, Bufs& b, int j) {
         Geo g = pass_geo(d, c->n, d - 1, fp64, c->max_dyn_lds, c->pcfg);
         PassArgs a = base_args(c, fp64, d - 1, g);
         a.in = t;
-        a.zout = b.zb;
+        void* zj = (char*)b.zbase + (size_t)j * c->N * esz;
+        a.zout = zj;
         a.out = b.acc;
         a.cD = 1.0;
         a.ci = 1.0;
@@ -527,7 +528,7 @@ int arnoldi_step(fnls_ctx* c, bool fp64, Bufs& b, int j) {
         tmpl.v0 = b.v0;
         tmpl.vbase = b.vbase;
         tmpl.basis_j = j;
-        if ((rc = toeplitz_tail(c, fp64, b.zb, b.acc, FIN_WDOTS, w, tmpl, 1)) != FNLS_OK) return rc;
+        if ((rc = toeplitz_tail(c, fp64, zj, b.acc, FIN_WDOTS, w, tmpl, 1)) != FNLS_OK) return rc;
     }
     StreamArgs s;
     std::memset(&s, 0, sizeof s);
@@ -600,14 +601,15 @@ int cycle_final_passes(fnls_ctx* c, bool fp64, Bufs& b, const void* b64, void* x
     double2* r64 = c->at<double2>(c->lay.r64);
     float2* r32 = fp64 ? nullptr : c->at<float2>(c->lay.V);
     int rc;
-    if (fp64) {
-        if (d == 1) {
-            Geo g = pass_geo(d, c->n, 0, true, c->max_dyn_lds, c->pcfg);
-            PassArgs a = base_args(c, true, 0, g);
-            a.v0 = b.v0;
-            a.vbase = b.vbase;
-            a.x64 = (double2*)x;
-            a.first_cycle = first;
+    if (d == 1) {
+        // one line: x (+)= Ptilde^{-1} (V y) in a single pass (FP64: with the residual)
+        Geo g = pass_geo(d, c->n, 0, fp64, c->max_dyn_lds, c->pcfg);
+        PassArgs a = base_args(c, fp64, 0, g);
+        a.v0 = b.v0;
+        a.vbase = b.vbase;
+        a.x64 = (double2*)x;
+        a.first_cycle = first;
+        if (fp64) {
             a.cD = 1.0;
             a.ci = 1.0;
             a.cT = -1.0;
@@ -617,59 +619,42 @@ int cycle_final_passes(fnls_ctx* c, bool fp64, Bufs& b, const void* b64, void* x
             PassVariant v{IN_COMBO, P_DST1 | P_DIV | P_DST2 | P_SCALE | P_TOEP, Z_XADD, OUT_ACC_FIRST, FIN_RESID};
             return run_pass(c, true, 0, v, a, g);
         }
-        void* t;
-        if ((rc = precond_front(c, true, IN_COMBO, nullptr, 0, b, &t, 0)) != FNLS_OK) return rc;
-        Geo g = pass_geo(d, c->n, d - 1, true, c->max_dyn_lds, c->pcfg);
-        PassArgs a = base_args(c, true, d - 1, g);
-        a.in = t;
-        a.x64 = (double2*)x;
-        a.first_cycle = first;
-        a.out = b.acc;
-        a.cD = 1.0;
-        a.ci = 1.0;
-        a.cT = -1.0;
-        PassVariant v{IN_PLAIN, P_DST1 | P_SCALE | P_TOEP, Z_XADD, OUT_ACC_FIRST, FIN_WRITE};
-        if ((rc = run_pass(c, true, d - 1, v, a, g)) != FNLS_OK) return rc;
-        PassArgs tmpl;
-        std::memset(&tmpl, 0, sizeof tmpl);
-        tmpl.b64 = (const double2*)b64;
-        tmpl.r64 = r64;
-        tmpl.pout = c->at<double2>(c->lay.pr);
-        return toeplitz_tail(c, true, x, b.acc, FIN_RESID, nullptr, tmpl, 0);
-    }
-    // FP32 correction
-    if (d == 1) {
-        Geo g = pass_geo(d, c->n, 0, false, c->max_dyn_lds, c->pcfg);
-        PassArgs a = base_args(c, false, 0, g);
-        a.v0 = b.v0;
-        a.vbase = b.vbase;
-        a.x64 = (double2*)x;
-        a.first_cycle = first;
         PassVariant v{IN_COMBO, P_DST1 | P_DIV | P_DST2 | P_SCALE, Z_XADD, OUT_LINE, FIN_WRITE};
         if ((rc = run_pass(c, false, 0, v, a, g)) != FNLS_OK) return rc;
     } else {
-        void* t;
-        if ((rc = precond_front(c, false, IN_COMBO, nullptr, 0, b, &t, 0)) != FNLS_OK) return rc;
-        Geo g = pass_geo(d, c->n, d - 1, false, c->max_dyn_lds, c->pcfg);
-        PassArgs a = base_args(c, false, d - 1, g);
-        a.in = t;
-        a.x64 = (double2*)x;
-        a.first_cycle = first;
-        PassVariant v{IN_PLAIN, P_DST1 | P_SCALE, Z_XADD, OUT_LINE, FIN_WRITE};
-        if ((rc = run_pass(c, false, d - 1, v, a, g)) != FNLS_OK) return rc;
+        // x (+)= sum_k y_k z_k over the preconditioned basis stored by the Arnoldi passes
+        // (equal to Ptilde^{-1} (V y) by linearity)
+        StreamArgs s;
+        std::memset(&s, 0, sizeof s);
+        s.N = c->N;
+        s.vbase = b.zbase;
+        s.x64 = (double2*)x;
+        s.mode = first;
+        s.st = c->st();
+        const double e = fp64 ? 16.0 : 8.0;
+        const LaunchEvents* te =
+            c->timing ? timing_begin(c, fp64 ? "zupdate64" : "zupdate32",
+                                     (c->cur_k * e + (first ? 16.0 : 32.0)) * (double)c->N)
+                      : nullptr;
+        hipError_t e2 = launch_zupdate(fp64 ? 1 : 0, s, stream_blocks(c->N), c->stream, te);
+        if (e2 != hipSuccess) {
+            timing_failed(c, te);
+            return set_err(c, FNLS_ERR_HIP, "zupdate launch failed: %s", hipGetErrorString(e2));
+        }
     }
-    // FP64 residual r = b - A x, with its complex64 copy as the next basis vector 0
+    // FP64 residual r = b - A x (IR: with its complex64 copy as the next basis vector 0)
     Geo g = pass_geo(d, c->n, d - 1, true, c->max_dyn_lds, c->pcfg);
     PassArgs a = base_args(c, true, d - 1, g);
     a.in = x;
     a.cD = 1.0;
     a.ci = 1.0;
     a.cT = -1.0;
+    const int ir = fp64 ? 0 : 1;
     if (d == 1) {
         a.b64 = (const double2*)b64;
         a.r64 = r64;
         a.r32 = r32;
-        a.ir = 1;
+        a.ir = ir;
         a.pout = c->at<double2>(c->lay.pr);
         PassVariant v{IN_PLAIN, P_TOEP, Z_NONE, OUT_ACC_FIRST, FIN_RESID};
         return run_pass(c, true, 0, v, a, g);
@@ -683,7 +668,7 @@ int cycle_final_passes(fnls_ctx* c, bool fp64, Bufs& b, const void* b64, void* x
     tmpl.b64 = (const double2*)b64;
     tmpl.r64 = r64;
     tmpl.r32 = r32;
-    tmpl.ir = 1;
+    tmpl.ir = ir;
     tmpl.pout = c->at<double2>(c->lay.pr);
     return toeplitz_tail(c, true, x, acc64, FIN_RESID, nullptr, tmpl, 0);
 }

@@ -140,8 +140,9 @@ struct StreamArgs {
     GmresState* st;
     HostStatus* hs;
     int check_active;
-    int mode;
+    int mode;             // k_finish: FinishKind; k_zupdate: 1 = first correction (x = 0 before)
     int ir;               // k_finish residual decision: 1 = refinement step of FP32-IR
+    double2* x64;         // k_zupdate: the iterate
 };
 
 }  // namespace fnls

@@ -45,9 +45,10 @@ __device__ void report(GmresState* st, HostStatus* hs, int stopped) {
         hs->relres = st->relres;
         hs->bnorm = st->bnorm;
         if (st->total >= 1 && st->total <= 64) hs->hist[st->total - 1] = st->hist[st->total - 1];
-        __threadfence_system();
         hs->seq = st->seq;
-        __threadfence_system();
+        // no fence: the host reads this block only after waiting on an event
+        // recorded after this kernel, and kernel completion makes its writes
+        // to host memory visible
     }
 }
 
@@ -63,14 +64,15 @@ __device__ __forceinline__ double dabs(double2 a) { return hypot(a.x, a.y); }
 // the cycle stops -- the least-squares solution y and combination
 // coefficients y_i sigma_i.  Rotation convention: c = |a|/r,
 // s = (a/|a|) conj(b)/r, (x, y) -> (c x + s y, -conj(s) x + c y).
-__device__ void arnoldi_finish(GmresState* st, HostStatus* hs, double hn2) {
-    const int j = st->j;
+// s_col holds the new Hessenberg column (rows 0..j), s_cs / s_sn the earlier
+// rotations, all staged in LDS by the whole workgroup; one thread runs this.
+__device__ void arnoldi_finish(GmresState* st, HostStatus* hs, double hn2, int j, double2* s_col,
+                               const double* s_cs, const double2* s_sn) {
     const double hn = sqrt(hn2);
-    double2* col = st->R[j];   // column j is built in place (rows 0..j)
-    for (int i = 0; i <= j; ++i) col[i] = st->hcol[i];
+    double2* col = s_col;
     for (int i = 0; i < j; ++i) {
-        const double c = st->cs[i];
-        const double2 s = st->sn[i];
+        const double c = s_cs[i];
+        const double2 s = s_sn[i];
         const double2 a = col[i];
         const double2 b = col[i + 1];
         // t = c a + s b ; b' = -conj(s) a + c b
@@ -94,6 +96,7 @@ __device__ void arnoldi_finish(GmresState* st, HostStatus* hs, double hn2) {
     st->cs[j] = c;
     st->sn[j] = s;
     col[j] = dmk(c * a.x + s.x * hn, c * a.y + s.y * hn);
+    for (int i = 0; i <= j; ++i) st->R[j][i] = col[i];
     const double2 gj = st->g[j];
     st->g[j + 1] = dmk(-(s.x * gj.x + s.y * gj.y), -(s.x * gj.y - s.y * gj.x));
     st->g[j] = dmk(c * gj.x, c * gj.y);
@@ -557,6 +560,46 @@ __global__ __launch_bounds__(256) void k_prepare(StreamArgs a) {
     block_partial_write(s_red, 1, a.pout, a.pstride);
 }
 
+// End of a cycle, flexible form: x (+)= sum_{k < st->k} y_k z_k, with z_k the
+// preconditioned basis vectors P^{-1} v_k that the Arnoldi passes stored
+// (complex<R>, `vbase` + k N); x in FP64.  first = 1 sets x instead of adding.
+template <typename R>
+__global__ __launch_bounds__(256) void k_zupdate(StreamArgs a) {
+    using C = cplx<R>;
+    const long long N = a.N;
+    const int k = a.st->k;
+    const long long base = (long long)blockIdx.x * (kStreamThreads * kEpt) + threadIdx.x;
+    double2* x = a.x64;
+    double ax[kEpt], ay[kEpt];
+#pragma unroll
+    for (int q = 0; q < kEpt; ++q) {
+        const long long i = base + (long long)q * kStreamThreads;
+        const double2 v = (a.mode == 0 && i < N) ? x[i] : dmk(0.0, 0.0);
+        ax[q] = v.x;
+        ay[q] = v.y;
+    }
+    for (int kk = 0; kk < k; ++kk) {
+        const C* zp = reinterpret_cast<const C*>(a.vbase) + (long long)kk * N;
+        const double2 c = a.st->y[kk];
+        C z[kEpt];
+#pragma unroll
+        for (int q = 0; q < kEpt; ++q) {
+            const long long i = base + (long long)q * kStreamThreads;
+            z[q] = i < N ? zp[i] : czero<C>();
+        }
+#pragma unroll
+        for (int q = 0; q < kEpt; ++q) {
+            ax[q] += c.x * (double)z[q].x - c.y * (double)z[q].y;
+            ay[q] += c.x * (double)z[q].y + c.y * (double)z[q].x;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kEpt; ++q) {
+        const long long i = base + (long long)q * kStreamThreads;
+        if (i < N) x[i] = dmk(ax[q], ay[q]);
+    }
+}
+
 // Classical Gram-Schmidt round on w.  MODE 0 (first update): the totals of
 // the producer's partials are the dot products d_i = conj(V_i) w (i < nv) and
 // ||w||^2; h_i = sigma_i d_i, w -= sum_i h_i v_i, then partials of the
@@ -680,6 +723,20 @@ __global__ __launch_bounds__(256) void k_finish(StreamArgs a) {
         for (int i = threadIdx.x; i < nv; i += blockDim.x) a.pout[i] = s_tot[i];
         return;
     }
+    if (a.mode == FIN_K_GIVENS) {
+        __shared__ double2 s_col[kMaxRestart + 1];
+        __shared__ double2 s_sn[kMaxRestart];
+        __shared__ double s_cs[kMaxRestart];
+        const int j = st->j;
+        for (int i = threadIdx.x; i <= j; i += blockDim.x) s_col[i] = st->hcol[i];
+        for (int i = threadIdx.x; i < j; i += blockDim.x) {
+            s_cs[i] = st->cs[i];
+            s_sn[i] = st->sn[i];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) arnoldi_finish(st, a.hs, s_tot[0].x, j, s_col, s_cs, s_sn);
+        return;
+    }
     if (threadIdx.x != 0) return;
     if (a.mode == FIN_K_PREPARE) {
         const double bn = sqrt(s_tot[0].x);
@@ -700,8 +757,6 @@ __global__ __launch_bounds__(256) void k_finish(StreamArgs a) {
         st->done = ok ? 0 : 1;
         if (!ok) st->relres = 0.0;
         report(st, a.hs, 0);
-    } else if (a.mode == FIN_K_GIVENS) {
-        arnoldi_finish(st, a.hs, s_tot[0].x);
     } else {
         residual_finish(st, a.hs, s_tot[0].x, a.ir);
     }
@@ -796,20 +851,15 @@ static hipError_t dispatch_pass(const PassVariant& v, const PassArgs& a, int blo
     // forward / middle sine transforms
     FNLS_PASS_CASE(R, IN_PLAIN, DST, Z_NONE, OUT_LINE, FIN_WRITE)
     FNLS_PASS_CASE(R, IN_BASIS, DST, Z_NONE, OUT_LINE, FIN_WRITE)
-    FNLS_PASS_CASE(R, IN_COMBO, DST, Z_NONE, OUT_LINE, FIN_WRITE)
     FNLS_PASS_CASE(R, IN_PLAIN, DDD, Z_NONE, OUT_LINE, FIN_WRITE)
     // last sine transform of the preconditioner (d >= 2)
     FNLS_PASS_CASE(R, IN_PLAIN, LASTDST, Z_NONE, OUT_LINE, FIN_WRITE)
-    FNLS_PASS_CASE(R, IN_PLAIN, LASTDST, Z_XSET, OUT_LINE, FIN_WRITE)
-    FNLS_PASS_CASE(R, IN_PLAIN, LASTDST, Z_XADD, OUT_LINE, FIN_WRITE)
     FNLS_PASS_CASE(R, IN_PLAIN, LASTDST_T, Z_WRITE, OUT_ACC_FIRST, FIN_WRITE)
-    FNLS_PASS_CASE(R, IN_PLAIN, LASTDST_T, Z_XADD, OUT_ACC_FIRST, FIN_WRITE)
     // d = 1: the whole preconditioned operator on one line
     FNLS_PASS_CASE(R, IN_PLAIN, FULL1, Z_NONE, OUT_LINE, FIN_WRITE)
     FNLS_PASS_CASE(R, IN_BASIS, FULL1_T, Z_NONE, OUT_ACC_FIRST, FIN_WDOTS)
     FNLS_PASS_CASE(R, IN_COMBO, FULL1_T, Z_XADD, OUT_ACC_FIRST, FIN_RESID)
     FNLS_PASS_CASE(R, IN_COMBO, FULL1, Z_XADD, OUT_LINE, FIN_WRITE)
-    FNLS_PASS_CASE(R, IN_COMBO, FULL1, Z_XSET, OUT_LINE, FIN_WRITE)
     // Toeplitz passes
     FNLS_PASS_CASE(R, IN_PLAIN, TOEP, Z_NONE, OUT_ACC_FIRST, FIN_WRITE)
     FNLS_PASS_CASE(R, IN_PLAIN, TOEP, Z_NONE, OUT_ACC_FIRST, FIN_RESID)
@@ -841,6 +891,11 @@ hipError_t launch_cgs(int fp64, int mode, const StreamArgs& a, int blocks, hipSt
     if (fp64)
         return mode == 0 ? launch_k(k_cgs<double, 0>, g, b, 0, s, te, a) : launch_k(k_cgs<double, 1>, g, b, 0, s, te, a);
     return mode == 0 ? launch_k(k_cgs<float, 0>, g, b, 0, s, te, a) : launch_k(k_cgs<float, 1>, g, b, 0, s, te, a);
+}
+
+hipError_t launch_zupdate(int fp64, const StreamArgs& a, int blocks, hipStream_t s, const LaunchEvents* te) {
+    const dim3 g(blocks), b(kStreamThreads);
+    return fp64 ? launch_k(k_zupdate<double>, g, b, 0, s, te, a) : launch_k(k_zupdate<float>, g, b, 0, s, te, a);
 }
 
 hipError_t launch_config(GmresState* st, double tol, double outer_tol, int restart, int maxit, int fixed_iters,

@@ -28,6 +28,9 @@ hipError_t launch_prepare(const StreamArgs& a, int blocks, hipStream_t s, const 
 hipError_t launch_finish(const StreamArgs& a, hipStream_t s, const LaunchEvents* te = nullptr);
 hipError_t launch_cgs(int fp64, int mode, const StreamArgs& a, int blocks, hipStream_t s,
                       const LaunchEvents* te = nullptr);
+// x (+)= sum_k y_k z_k over the stored preconditioned basis (vbase, st->k vectors)
+hipError_t launch_zupdate(int fp64, const StreamArgs& a, int blocks, hipStream_t s,
+                          const LaunchEvents* te = nullptr);
 hipError_t launch_config(GmresState* st, double tol, double outer_tol, int restart, int maxit, int fixed_iters,
                          int max_outer, hipStream_t s);
 
