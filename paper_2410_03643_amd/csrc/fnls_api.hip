@@ -61,7 +61,7 @@ PassConfig default_pass_config() {
     PassConfig p;
     p.rmax[0][0] = 4;
     p.lines[0][0] = 1;
-    p.rmax[0][1] = 8;
+    p.rmax[0][1] = 4;
     p.lines[0][1] = 4;
     p.rmax[1][0] = 4;
     p.lines[1][0] = 2;

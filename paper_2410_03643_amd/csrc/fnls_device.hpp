@@ -349,55 +349,108 @@ __device__ __forceinline__ void line_fft(cplx<R>* A, cplx<R>* B, bool both, int 
     __syncthreads();
 }
 
-// Orthonormal DST-I of the line in A (slots 1..m-1), result in A; B is scratch.
+// Exclusive prefix sum of v over the G threads of a line (threads lt = 0..G-1
+// are consecutive lanes of the workgroup, G a power of two): a tree scan
+// within each wavefront segment, then the totals of the line's earlier
+// wavefronts from LDS.  Must be reached by the whole workgroup.
+template <typename R>
+__device__ __forceinline__ cplx<R> line_exclusive_scan(cplx<R> v, int G) {
+    using C = cplx<R>;
+    __shared__ C s_wtot[16];   // one total per wavefront (<= 1024 threads)
+    const int lane = threadIdx.x & 63;
+    const int sw = G < 64 ? G : 64;     // segment width
+    const int ls = lane & (sw - 1);     // position in the segment
+    C inc = v;
+    for (int d = 1; d < sw; d <<= 1) {
+        const R tx = __shfl_up(inc.x, d, sw);
+        const R ty = __shfl_up(inc.y, d, sw);
+        if (ls >= d) {
+            inc.x += tx;
+            inc.y += ty;
+        }
+    }
+    C exc;
+    exc.x = __shfl_up(inc.x, 1, sw);
+    exc.y = __shfl_up(inc.y, 1, sw);
+    if (ls == 0) exc = czero<C>();
+    if (G > 64) {
+        const int wave = threadIdx.x >> 6;
+        if (lane == 63) s_wtot[wave] = inc;
+        __syncthreads();
+        const int w0 = (threadIdx.x - (threadIdx.x & (G - 1))) >> 6;   // first wavefront of the line
+        for (int w = w0; w < wave; ++w) exc = cadd(exc, s_wtot[w]);
+        __syncthreads();   // s_wtot is reused by the next call
+    }
+    return exc;
+}
+
+// Orthonormal DST-I of the line in A (slots 1..m-1), result in A, with one
+// length-m FFT.  With x_0 = x_m = 0, a_j = x_j - x_{m-j} and
+// b_j = (x_j + x_{m-j}) W_{2m}^j, the transforms A = FFT_m(a), B = FFT_m(b)
+// give y_{2p} = (i/sqrt(2m)) A_p and y_{2p+1} = (i/sqrt(2m)) B_p.  Only
+// C = FFT_m(a + b) is computed: a is odd about m/2 (A_{m-p} = -A_p) and b
+// changes sign under j -> m - j after the half-sample shift
+// (B_{m-1-p} = -B_p), so C_p + C_{m-p} = B_p - B_{p-1} and B_0 = C_0:
+// B_p = C_0 + sum_{q=1..p} (C_q + C_{m-q}), A_p = C_p - B_p.  The sum is a
+// prefix scan over p < m/2 (each thread owns a contiguous range of p).
 // Caller has synchronised after writing A.  tw[s] = W_{2m}^s (global table).
+// B is not used.
 template <typename R, int RMAX, int LGM = 0>
 __device__ __forceinline__ void line_dst(cplx<R>* A, cplx<R>* B, int lgm, int lt, int G,
                                          const cplx<R>* __restrict__ tw, const cplx<R>* twl) {
     using C = cplx<R>;
+    (void)B;
     const int m = 1 << lgm;
     const int half = m >> 1;
+    // c_j = a_j + b_j for the pair (j, m - j)
     for (int j = lt; j <= half; j += G) {
         if (j == 0) {
             A[0] = czero<C>();
-            B[0] = czero<C>();
         } else {
             const C xj = A[pad(j)];
-            const C xmj = A[pad(m - j)];
-            const C a = csub(xj, xmj);
-            const C s = cadd(xj, xmj);
             if (j == half) {
-                A[pad(j)] = czero<C>();
-                B[pad(j)] = cmul(s, tw[j]);
+                // a = 0, b = 2 x W_{2m}^{m/2} = -2 i x
+                A[pad(j)] = cm<R>(R(2) * xj.y, R(-2) * xj.x);
             } else {
-                A[pad(j)] = a;
-                A[pad(m - j)] = cneg(a);
-                B[pad(j)] = cmul(s, tw[j]);
-                B[pad(m - j)] = cmul(s, tw[m - j]);
+                const C xmj = A[pad(m - j)];
+                const C a = csub(xj, xmj);
+                const C sw = cadd(xj, xmj);
+                const C w = tw[j];
+                A[pad(j)] = cadd(a, cmul(sw, w));        // a_j + s_j W^j
+                A[pad(m - j)] = csub(cneg(a), cmulc(sw, w));   // -a_j + s_j W^{m-j} = -a_j - s_j conj(W^j)
             }
         }
     }
     __syncthreads();
-    line_fft<R, false, RMAX, LGM>(A, B, true, lgm, lt, G, twl);
-    // y_{2p} = (i/sqrt(2m)) A_p, y_{2p+1} = (i/sqrt(2m)) B_p
+    line_fft<R, false, RMAX, LGM>(A, A, false, lgm, lt, G, twl);
+    // p range of this thread: [lt E, lt E + E), E = half / G (G <= half unless m < 2 RMAX... E >= 1)
     constexpr int PER = RMAX / 2;
-    C ra[PER], rb[PER];
+    const int E = half >= G ? half / G : 1;
+    const int p0 = lt * E;
+    C cp[PER], dinc[PER];
+    C run = czero<C>();
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-        const int p = lt + q * G;
-        if (p < half) {
-            ra[q] = A[pad(p)];
-            rb[q] = B[pad(p)];
+    for (int e = 0; e < PER; ++e) {
+        const int p = p0 + e;
+        if (e < E && p < half) {
+            cp[e] = A[pad(p)];
+            if (p > 0) run = cadd(run, cadd(cp[e], A[pad(m - p)]));
+            dinc[e] = run;
         }
     }
-    __syncthreads();
+    const C c0 = A[0];
+    const C off = cadd(c0, line_exclusive_scan<R>(run, G));
+    __syncthreads();   // every read of C is done before the outputs overwrite it
     const R sc = static_cast<R>(1.0 / sqrt(2.0 * m));
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-        const int p = lt + q * G;
-        if (p < half) {
-            A[pad(2 * p)] = (p == 0) ? czero<C>() : cm<R>(-sc * ra[q].y, sc * ra[q].x);
-            A[pad(2 * p + 1)] = cm<R>(-sc * rb[q].y, sc * rb[q].x);
+    for (int e = 0; e < PER; ++e) {
+        const int p = p0 + e;
+        if (e < E && p < half) {
+            const C bp = cadd(off, dinc[e]);
+            const C ap = csub(cp[e], bp);
+            // y = (i sc) v
+            A[pad(2 * p)] = (p == 0) ? czero<C>() : cm<R>(-sc * ap.y, sc * ap.x);
+            A[pad(2 * p + 1)] = cm<R>(-sc * bp.y, sc * bp.x);
         }
     }
     __syncthreads();

@@ -213,12 +213,22 @@ def test_line_fft_and_line_ops_indices(m, rmax):
             for s in ([0] if j == 0 else ([j] if j == half else [j, m - j])):
                 assert 0 <= s < m
                 slots.add(s)
-        for q in range(rmax // 2):
-            p = lt + q * G
+    # one-FFT sine transform: thread lt owns p in [lt E, lt E + E), E = half / G
+    E = half // G if half >= G else 1
+    assert E <= max(1, rmax // 2)
+    owned = []
+    for lt in range(G):
+        for e in range(E):
+            p = lt * E + e
             if p < half:
-                assert 2 * p + 1 < m
+                assert 2 * p + 1 < m and m - p <= m
+                owned.append(p)
+    assert sorted(owned) == list(range(half))
     assert slots == set(range(m))
-    assert -(-half // G) <= max(1, rmax // 2)
+    # scan segments: G lanes of a line inside a wavefront, or whole wavefronts
+    sw = min(G, 64)
+    assert 64 % sw == 0 and (G <= 64 or G % 64 == 0)
+    assert (1024 // 64) <= 16   # wavefront totals of one workgroup fit the scan's LDS array
 
 
 MAX_RESTART = 64
