@@ -90,6 +90,15 @@ def soliton(d: int, n: int, lo: float, hi: float, *, center=None, phase: float =
     return np.ascontiguousarray(u)
 
 
+def gaussian(d: int, n: int, lo: float, hi: float, *, amplitude: float = 1.0,
+             width2: float = 1.0) -> np.ndarray:
+    """amplitude * exp(-|x|^2 / width2) on the interior grid (Sec. 5.2 uses
+    amplitude 2/sqrt(pi), width2 1 on [-5, 5]^2)."""
+    xs = mesh(d, n, lo, hi)
+    r2 = sum(x * x for x in xs)
+    return np.ascontiguousarray(amplitude * np.exp(-r2 / width2), dtype=np.complex128)
+
+
 def random_field(shape, seed: int, scale: float = 1.0) -> np.ndarray:
     """A dense random complex field (for operator-level parity tests)."""
     return np.ascontiguousarray(complex_noise(shape, scale, seed))
