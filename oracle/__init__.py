@@ -24,6 +24,8 @@ stepping  the three-level linearly implicit schemes of Sec. 2 as repeated
           solves, the two-level starter and the discrete mass.
 solver    OracleSolver: the same call sequence as the C ABI
           (assemble, precond_setup, solve, step, first_step).
+adjoint   reverse mode of the stepper: adjoint solves and the gradient of a
+          real loss of the final state with respect to u^0 and a potential V.
 
 Parity status: every function is pinned by at least one CPU test in
 tests/test_oracle_*.py against something other than itself (closed forms,
@@ -31,5 +33,5 @@ dense LU, library routines, brute force, paper bounds, the paper's printed
 mass-error table).  None is "parity unpinned".
 """
 
-from . import fcd, system, gmres, stepping, solver  # noqa: F401
+from . import fcd, system, gmres, stepping, solver, adjoint  # noqa: F401
 from .solver import OracleSolver  # noqa: F401
