@@ -174,6 +174,37 @@ int fnls_step(fnls_ctx *ctx, const fnls_c128 *u_prev, const fnls_c128 *u_cur, fn
 int fnls_first_step(fnls_ctx *ctx, const fnls_c128 *u0, fnls_c128 *u1, const fnls_opts *opts,
                     fnls_info *info);
 
+/* A real potential V added to the diagonal by fnls_step, fnls_first_step
+ * and their reverse modes: D = rho dt |u_cur|^2 + dt V (the paper's D is the
+ * case V = 0; the potential is an extension for differentiating with respect
+ * to a spatially varying coefficient).  V is a device pointer to N doubles,
+ * owned by the caller, kept by the context and read by every later step until
+ * replaced; NULL removes it.  fnls_precond_setup takes its own V argument and
+ * ignores this one. */
+int fnls_set_potential(fnls_ctx *ctx, const double *V);
+
+/* Reverse mode of fnls_step (one three-level step of Sec. 2.1 / 2.2,
+ * u_next = A^{-1} B u_prev with A = D - T_d + iI, B = iI + T_d - D and
+ * D = rho dt |u_cur|^2 + dt V).  For a real loss L with gradients taken as
+ * g_z = dL/dRe z + i dL/dIm z (PyTorch's convention for complex tensors),
+ * given g_next for u_next this ACCUMULATES
+ *     g_prev += B^H lam,   g_cur += 2 dt rho g_D u_cur,   g_V += dt g_D
+ * (g_V may be NULL), where lam solves the adjoint system A^H lam = g_next and
+ * g_D = -Re(conj(lam) (u_next + u_prev)).  A is complex symmetric, so the
+ * adjoint solve is the same preconditioned GMRES applied to conj(g_next)
+ * (opts / info as for fnls_solve; info describes that solve).  u_next must be
+ * the forward result for (u_prev, u_cur).  Gradient outputs must not alias
+ * each other or the inputs.  Returns when the result is complete. */
+int fnls_step_backward(fnls_ctx *ctx, const fnls_c128 *u_prev, const fnls_c128 *u_cur,
+                       const fnls_c128 *u_next, const fnls_c128 *g_next, fnls_c128 *g_prev,
+                       fnls_c128 *g_cur, double *g_V, const fnls_opts *opts, fnls_info *info);
+
+/* Reverse mode of fnls_first_step (the starter: the same system with dt / 2
+ * and u_prev = u_cur = u0): g0 += (both contributions), g_V += (dt/2) g_D. */
+int fnls_first_step_backward(fnls_ctx *ctx, const fnls_c128 *u0, const fnls_c128 *u1,
+                             const fnls_c128 *g1, fnls_c128 *g0, double *g_V,
+                             const fnls_opts *opts, fnls_info *info);
+
 /* Per-kernel timing (optional instrumentation, used by the benchmark).
  * fnls_timing(ctx, 1) clears earlier records; every following kernel launch
  * of this context then carries a pair of HIP events that the runtime records

@@ -106,7 +106,7 @@ int stream_blocks(long long N) {
 struct Layout {
     size_t tw64, tw32, syme64, symo64, lam64, syme32, symo32, lam32;
     size_t state, p1, p2, p3, pr, px, D64, D32;
-    size_t t1, t2, Z, acc, r64, bbuf, V;
+    size_t t1, t2, Z, acc, r64, bbuf, adj, V;
     size_t total;
     int pstride;
 };
@@ -148,6 +148,7 @@ Layout make_layout(int d, int n, int restart) {
     l.acc = take((size_t)N * 16);
     l.r64 = take((size_t)N * 16);
     l.bbuf = take((size_t)N * 16);
+    l.adj = take((size_t)N * 16);   // adjoint solution (reverse mode)
     l.V = take((size_t)N * 16 * restart);
     l.total = off;
     return l;
@@ -169,6 +170,7 @@ struct fnls_ctx {
     double tscale = 1.0;
     double omega = 1.0;
     int have_D = 0;
+    const double* Vpot = nullptr;   // potential added to D by the steppers (fnls_set_potential)
     // workspace
     char* ws = nullptr;
     size_t ws_bytes = 0;
@@ -1113,7 +1115,7 @@ int fnls_step(fnls_ctx* c, const fnls_c128* u_prev, const fnls_c128* u_cur, fnls
     if ((rc = resolve_opts(c, opts, &o)) != FNLS_OK) return rc;
     HIPCHK(c, hipSetDevice(c->device));
     c->tscale = 1.0;
-    if ((rc = precond_setup_scaled(c, u_cur, nullptr, c->omega > 0 ? c->omega : 1.0, c->tau)) != FNLS_OK) return rc;
+    if ((rc = precond_setup_scaled(c, u_cur, c->Vpot, c->omega > 0 ? c->omega : 1.0, c->tau)) != FNLS_OK) return rc;
     fnls_c128* bb = c->at<fnls_c128>(c->lay.bbuf);
     if ((rc = matvec64(c, u_prev, bb, -1.0, 1.0, 1.0)) != FNLS_OK) return rc;
     return solve_impl(c, bb, u_next, &o, info);
@@ -1129,13 +1131,109 @@ int fnls_first_step(fnls_ctx* c, const fnls_c128* u0, fnls_c128* u1, const fnls_
     HIPCHK(c, hipSetDevice(c->device));
     const double omega = c->omega > 0 ? c->omega : 1.0;
     c->tscale = 0.5;
-    rc = precond_setup_scaled(c, u0, nullptr, omega, 0.5 * c->tau);
+    rc = precond_setup_scaled(c, u0, c->Vpot, omega, 0.5 * c->tau);
     fnls_c128* bb = c->at<fnls_c128>(c->lay.bbuf);
     if (rc == FNLS_OK) rc = matvec64(c, u0, bb, -1.0, 1.0, 1.0);
     if (rc == FNLS_OK || rc == FNLS_NOT_CONVERGED) rc = solve_impl(c, bb, u1, &o, info);
     c->tscale = 1.0;
     c->have_D = 0;   // D belongs to the starter system; the next step recomputes it
     return rc;
+}
+
+int fnls_set_potential(fnls_ctx* c, const double* V) {
+    if (!c) return FNLS_ERR_INVALID_ARG;
+    c->Vpot = V;
+    return FNLS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+// Reverse mode of the step with time-step factor tfac (1: three-level step,
+// 0.5: starter with u_prev = u_cur): lam = conj(A^{-1} conj(g_next)), then
+// g_prev += conj(B conj(lam)) and the g_D terms.
+int step_backward_impl(fnls_ctx* c, const fnls_c128* u_prev, const fnls_c128* u_cur, const fnls_c128* u_next,
+                       const fnls_c128* g_next, fnls_c128* g_prev, fnls_c128* g_cur, double* g_V,
+                       const fnls_opts* opts, fnls_info* info, double tfac) {
+    fnls_opts o;
+    int rc = resolve_opts(c, opts, &o);
+    if (rc != FNLS_OK) return rc;
+    HIPCHK(c, hipSetDevice(c->device));
+    const double omega = c->omega > 0 ? c->omega : 1.0;
+    c->tscale = tfac;
+    rc = precond_setup_scaled(c, u_cur, c->Vpot, omega, tfac * c->tau);
+    double2* bb = c->at<double2>(c->lay.bbuf);
+    double2* sol = c->at<double2>(c->lay.adj);
+    if (rc == FNLS_OK) {
+        hipError_t e = launch_conj(reinterpret_cast<const double2*>(g_next), bb, c->N, c->stream);
+        if (e != hipSuccess) rc = set_err(c, FNLS_ERR_HIP, "conj launch failed: %s", hipGetErrorString(e));
+    }
+    int srt = FNLS_OK;
+    if (rc == FNLS_OK) {
+        srt = solve_impl(c, reinterpret_cast<const fnls_c128*>(bb), reinterpret_cast<fnls_c128*>(sol), &o, info);
+        if (srt < 0) rc = srt;
+    }
+    // w = B sol into the (now free) right-hand-side buffer
+    if (rc == FNLS_OK) rc = matvec64(c, sol, bb, -1.0, 1.0, 1.0);
+    if (rc == FNLS_OK) {
+        AdjointArgs a;
+        std::memset(&a, 0, sizeof a);
+        a.N = c->N;
+        a.sol = sol;
+        a.w = bb;
+        a.u_prev = reinterpret_cast<const double2*>(u_prev);
+        a.u_cur = reinterpret_cast<const double2*>(u_cur);
+        a.u_next = reinterpret_cast<const double2*>(u_next);
+        a.g_prev = reinterpret_cast<double2*>(g_prev);
+        a.g_cur = reinterpret_cast<double2*>(g_cur);
+        a.g_V = g_V;
+        a.dt = tfac * c->tau;
+        a.rho = c->rho;
+        const LaunchEvents* te = c->timing ? timing_begin(c, "adjoint", (16.0 * 7 + (g_cur ? 32.0 : 0.0) +
+                                                                          (g_V ? 16.0 : 0.0)) * (double)c->N)
+                                           : nullptr;
+        hipError_t e = launch_adjoint(a, c->stream, te);
+        if (e != hipSuccess) {
+            timing_failed(c, te);
+            rc = set_err(c, FNLS_ERR_HIP, "adjoint launch failed: %s", hipGetErrorString(e));
+        }
+    }
+    if (rc == FNLS_OK) {
+        hipError_t e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) rc = set_err(c, FNLS_ERR_HIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
+    }
+    c->tscale = 1.0;
+    if (tfac != 1.0) c->have_D = 0;
+    return rc == FNLS_OK ? srt : rc;
+}
+
+bool same(const void* a, const void* b) { return a && a == b; }
+}  // namespace
+
+extern "C" {
+
+int fnls_step_backward(fnls_ctx* c, const fnls_c128* u_prev, const fnls_c128* u_cur, const fnls_c128* u_next,
+                       const fnls_c128* g_next, fnls_c128* g_prev, fnls_c128* g_cur, double* g_V,
+                       const fnls_opts* opts, fnls_info* info) {
+    int rc = check_ready(c);
+    if (rc != FNLS_OK) return rc;
+    if (!u_prev || !u_cur || !u_next || !g_next || !g_prev || !g_cur)
+        return set_err(c, FNLS_ERR_INVALID_ARG, "NULL vector");
+    if (same(g_prev, g_cur) || same(g_prev, g_next) || same(g_cur, g_next) || same(g_prev, u_prev) ||
+        same(g_prev, u_cur) || same(g_prev, u_next) || same(g_cur, u_prev) || same(g_cur, u_cur) ||
+        same(g_cur, u_next))
+        return set_err(c, FNLS_ERR_INVALID_ARG, "gradient outputs must not alias each other or the inputs");
+    return step_backward_impl(c, u_prev, u_cur, u_next, g_next, g_prev, g_cur, g_V, opts, info, 1.0);
+}
+
+int fnls_first_step_backward(fnls_ctx* c, const fnls_c128* u0, const fnls_c128* u1, const fnls_c128* g1,
+                             fnls_c128* g0, double* g_V, const fnls_opts* opts, fnls_info* info) {
+    int rc = check_ready(c);
+    if (rc != FNLS_OK) return rc;
+    if (!u0 || !u1 || !g1 || !g0) return set_err(c, FNLS_ERR_INVALID_ARG, "NULL vector");
+    if (same(g0, g1) || same(g0, u0) || same(g0, u1))
+        return set_err(c, FNLS_ERR_INVALID_ARG, "g0 must not alias the inputs");
+    return step_backward_impl(c, u0, u0, u1, g1, g0, nullptr, g_V, opts, info, 0.5);
 }
 
 int fnls_timing(fnls_ctx* c, int enable) {

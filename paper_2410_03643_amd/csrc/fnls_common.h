@@ -145,4 +145,18 @@ struct StreamArgs {
     double2* x64;         // k_zupdate: the iterate
 };
 
+// Reverse mode of one step: gradient accumulation after the adjoint solve.
+struct AdjointArgs {
+    long long N;
+    const double2* sol;      // A^{-1} conj(g_next) = conj(lam)
+    const double2* w;        // B sol (so B^H lam = conj(w))
+    const double2* u_prev;
+    const double2* u_cur;
+    const double2* u_next;
+    double2* g_prev;         // += conj(w) (+ the u_cur term when g_cur is null)
+    double2* g_cur;          // += 2 dt rho g_D u_cur (may be null: added to g_prev)
+    double* g_V;             // += dt g_D (may be null)
+    double dt, rho;          // time step of the system (dt/2 for the starter)
+};
+
 }  // namespace fnls

@@ -600,6 +600,42 @@ __global__ __launch_bounds__(256) void k_zupdate(StreamArgs a) {
     }
 }
 
+// out = conj(in) (complex128).
+__global__ __launch_bounds__(256) void k_conj(const double2* in, double2* out, long long N) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (long long)gridDim.x * blockDim.x) {
+        const double2 v = in[i];
+        out[i] = dmk(v.x, -v.y);
+    }
+}
+
+// Gradient accumulation of one step's reverse mode (a.sol = conj(lam)):
+// g_D = -Re(conj(lam) u_next) - Re(conj(lam) u_prev), g_prev += conj(w),
+// g_cur += 2 dt rho g_D u_cur, g_V += dt g_D.
+__global__ __launch_bounds__(256) void k_adjoint(AdjointArgs a) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < a.N;
+         i += (long long)gridDim.x * blockDim.x) {
+        const double2 s = a.sol[i];
+        const double2 un = a.u_next[i], up = a.u_prev[i], uc = a.u_cur[i];
+        const double gD = -(s.x * un.x - s.y * un.y) - (s.x * up.x - s.y * up.y);
+        const double2 w = a.w[i];
+        const double c = 2.0 * a.dt * a.rho * gD;
+        double2 gp = a.g_prev[i];
+        gp.x += w.x;
+        gp.y -= w.y;
+        if (a.g_cur) {
+            double2 gc = a.g_cur[i];
+            gc.x += c * uc.x;
+            gc.y += c * uc.y;
+            a.g_cur[i] = gc;
+        } else {
+            gp.x += c * uc.x;
+            gp.y += c * uc.y;
+        }
+        a.g_prev[i] = gp;
+        if (a.g_V) a.g_V[i] += a.dt * gD;
+    }
+}
+
 // Classical Gram-Schmidt round on w.  MODE 0 (first update): the totals of
 // the producer's partials are the dot products d_i = conj(V_i) w (i < nv) and
 // ||w||^2; h_i = sigma_i d_i, w -= sum_i h_i v_i, then partials of the
@@ -784,6 +820,8 @@ __global__ void k_config(GmresState* st, double tol, double outer_tol, int resta
 
 #include <hip/hip_ext.h>
 
+#include <algorithm>
+
 #include "fnls_launch.h"
 
 namespace fnls {
@@ -896,6 +934,16 @@ hipError_t launch_cgs(int fp64, int mode, const StreamArgs& a, int blocks, hipSt
 hipError_t launch_zupdate(int fp64, const StreamArgs& a, int blocks, hipStream_t s, const LaunchEvents* te) {
     const dim3 g(blocks), b(kStreamThreads);
     return fp64 ? launch_k(k_zupdate<double>, g, b, 0, s, te, a) : launch_k(k_zupdate<float>, g, b, 0, s, te, a);
+}
+
+hipError_t launch_conj(const double2* in, double2* out, long long N, hipStream_t s) {
+    const int blocks = (int)std::min<long long>(4096, (N + 255) / 256);
+    return launch_k(k_conj, dim3(blocks), dim3(256), 0, s, nullptr, in, out, N);
+}
+
+hipError_t launch_adjoint(const AdjointArgs& a, hipStream_t s, const LaunchEvents* te) {
+    const int blocks = (int)std::min<long long>(4096, (a.N + 255) / 256);
+    return launch_k(k_adjoint, dim3(blocks), dim3(256), 0, s, te, a);
 }
 
 hipError_t launch_config(GmresState* st, double tol, double outer_tol, int restart, int maxit, int fixed_iters,

@@ -28,6 +28,10 @@ hipError_t launch_prepare(const StreamArgs& a, int blocks, hipStream_t s, const 
 hipError_t launch_finish(const StreamArgs& a, hipStream_t s, const LaunchEvents* te = nullptr);
 hipError_t launch_cgs(int fp64, int mode, const StreamArgs& a, int blocks, hipStream_t s,
                       const LaunchEvents* te = nullptr);
+// out = conj(in), complex128
+hipError_t launch_conj(const double2* in, double2* out, long long N, hipStream_t s);
+// gradient accumulation of one step's reverse mode
+hipError_t launch_adjoint(const AdjointArgs& a, hipStream_t s, const LaunchEvents* te = nullptr);
 // x (+)= sum_k y_k z_k over the stored preconditioned basis (vbase, st->k vectors)
 hipError_t launch_zupdate(int fp64, const StreamArgs& a, int blocks, hipStream_t s,
                           const LaunchEvents* te = nullptr);

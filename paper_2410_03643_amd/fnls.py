@@ -106,6 +106,12 @@ def lib() -> ctypes.CDLL:
     L.fnls_timing.restype = ci
     L.fnls_timing_report.argtypes = [vp, ctypes.POINTER(KernelStat), ci]
     L.fnls_timing_report.restype = ci
+    L.fnls_set_potential.argtypes = [vp, vp]
+    L.fnls_set_potential.restype = ci
+    L.fnls_step_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(Opts), ctypes.POINTER(Info)]
+    L.fnls_step_backward.restype = ci
+    L.fnls_first_step_backward.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(Opts), ctypes.POINTER(Info)]
+    L.fnls_first_step_backward.restype = ci
     _lib = L
     return L
 
@@ -248,6 +254,43 @@ class Solver:
         self._check(lib().fnls_first_step(self._ctx, self._vec(u0, "u0"), self._vec(u1, "u1"),
                                           ctypes.byref(o), ctypes.byref(info)))
         return u1, self._info(info)
+
+    def _real(self, V, name):
+        if V is None:
+            return None
+        if not isinstance(V, self.torch.Tensor) or V.dtype != self.torch.float64 \
+                or tuple(V.shape) != self.shape or not V.is_contiguous() or V.device != self.device:
+            raise ValueError("%s must be a contiguous float64 tensor of shape %s on %s"
+                             % (name, self.shape, self.device))
+        return ctypes.c_void_p(V.data_ptr())
+
+    def set_potential(self, V):
+        """Real potential added to D by step / first_step and their reverse
+        modes (None removes it).  The tensor must stay alive while in use."""
+        self._potential = V          # keep the storage alive
+        self._check(lib().fnls_set_potential(self._ctx, self._real(V, "V")))
+
+    def step_backward(self, u_prev, u_cur, u_next, g_next, g_prev, g_cur, g_V=None, *, tol=1e-10,
+                      restart=30, maxit=2000, lookahead=1):
+        """Accumulate the reverse mode of step(u_prev, u_cur) -> u_next into
+        g_prev, g_cur (complex) and g_V (real, optional)."""
+        o = self._opts(tol, restart, maxit, "fp64", 1e-5, 20, 0, lookahead)
+        info = Info()
+        self._check(lib().fnls_step_backward(
+            self._ctx, self._vec(u_prev, "u_prev"), self._vec(u_cur, "u_cur"), self._vec(u_next, "u_next"),
+            self._vec(g_next, "g_next"), self._vec(g_prev, "g_prev"), self._vec(g_cur, "g_cur"),
+            self._real(g_V, "g_V"), ctypes.byref(o), ctypes.byref(info)))
+        return self._info(info)
+
+    def first_step_backward(self, u0, u1, g1, g0, g_V=None, *, tol=1e-10, restart=30, maxit=2000,
+                            lookahead=1):
+        """Accumulate the reverse mode of first_step(u0) -> u1 into g0 and g_V."""
+        o = self._opts(tol, restart, maxit, "fp64", 1e-5, 20, 0, lookahead)
+        info = Info()
+        self._check(lib().fnls_first_step_backward(
+            self._ctx, self._vec(u0, "u0"), self._vec(u1, "u1"), self._vec(g1, "g1"), self._vec(g0, "g0"),
+            self._real(g_V, "g_V"), ctypes.byref(o), ctypes.byref(info)))
+        return self._info(info)
 
     def set_pass_config(self, precision, strided: bool, rmax: int, lines: int):
         """Transform-pass tuning: largest radix and lines per workgroup."""

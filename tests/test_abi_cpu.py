@@ -67,6 +67,9 @@ def test_null_context_is_rejected(L):
     assert L.fnls_set_pass_config(None, 0, 0, 4, 1) == fnls.ERR_INVALID_ARG
     assert L.fnls_timing(None, 1) == fnls.ERR_INVALID_ARG
     assert L.fnls_timing_report(None, None, 0) == fnls.ERR_INVALID_ARG
+    assert L.fnls_set_potential(None, None) == fnls.ERR_INVALID_ARG
+    assert L.fnls_step_backward(None, None, None, None, None, None, None, None, None, None) == fnls.ERR_INVALID_ARG
+    assert L.fnls_first_step_backward(None, None, None, None, None, None, None, None) == fnls.ERR_INVALID_ARG
     L.fnls_destroy(None)
     assert L.fnls_last_error(None) == b"null context"
 
