@@ -205,7 +205,7 @@ __device__ void reduce_partials(const double2* __restrict__ p, int ps, int nb, i
 
 // Write this workgroup's partial of nv values: red[i * nw + w] holds the
 // wavefront sums (nw wavefronts); summed in wavefront order.
-__device__ void block_partial_write(const double2* red, int nv, double2* partials, int pstride) {
+__device__ void block_partial_write(const double2* red, int nv, double2* partials, int pstride, int blk) {
     const int nw = (blockDim.x + 63) >> 6;
     for (int i = threadIdx.x; i < nv; i += blockDim.x) {
         double sx = 0.0, sy = 0.0;
@@ -213,7 +213,7 @@ __device__ void block_partial_write(const double2* red, int nv, double2* partial
             sx += red[i * nw + w].x;
             sy += red[i * nw + w].y;
         }
-        partials[(size_t)i * pstride + blockIdx.x] = dmk(sx, sy);
+        partials[(size_t)i * pstride + blk] = dmk(sx, sy);
     }
 }
 
@@ -231,13 +231,23 @@ __device__ __forceinline__ void stc(void* p, long long idx, cplx<R> v) {
 // range of line blocks: on strided axes neighbouring blocks share 128-byte
 // cache lines (a block covers L < 8 complex values per row), and they then
 // meet in the same L2 instead of each XCD fetching the whole line.
-__device__ __forceinline__ int xcd_block() {
+__device__ __forceinline__ int xcd_block(int i, int nb) {
     constexpr int kXcd = 8;
-    const int nb = (int)gridDim.x;
-    const int i = (int)blockIdx.x;
     const int x = i % kXcd, q = i / kXcd;
     const int base = nb / kXcd, rem = nb % kXcd;
     return x * base + min(x, rem) + q;
+}
+
+// Batched launches: workgroups of instance i are the (logical) block range
+// [offs[i], offs[i+1]); returns i for block g (offs is ascending, offs[0] = 0).
+__device__ __forceinline__ int batch_find(const int* offs, int count, int g) {
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (offs[mid] <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
 }
 
 // ---------------------------------------------------------------------------
@@ -251,7 +261,7 @@ template <> struct PassThreads<16> { static constexpr int v = 256; };
 // LGM > 0: the line length m = 2^LGM is a compile-time constant (the host
 // launches this specialisation only when a.lgm == LGM); 0: generic.
 template <typename R, int RMAX, int LGM, int INM, int OPS, int ZM, int OUTM, int FIN>
-__global__ __launch_bounds__(PassThreads<RMAX>::v) void k_pass(PassArgs a) {
+__device__ __forceinline__ void pass_body(const PassArgs& a, int blk) {
     using C = cplx<R>;
     constexpr int kMaxEptLine = RMAX;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -297,7 +307,6 @@ __global__ __launch_bounds__(PassThreads<RMAX>::v) void k_pass(PassArgs a) {
     };
 
     // per-line base offset and Lambda of the other axes
-    const int blk = xcd_block();
     for (int l = tid; l < L; l += T) {
         const long long lg = (long long)blk * L + l;
         long long base = -1;
@@ -515,7 +524,21 @@ __global__ __launch_bounds__(PassThreads<RMAX>::v) void k_pass(PassArgs a) {
         if (lane == 0) s_red[wave] = dmk(nrm, 0.0);
     }
     __syncthreads();
-    block_partial_write(s_red, nv, a.pout, a.pstride);
+    block_partial_write(s_red, nv, a.pout, a.pstride, blk);
+}
+
+template <typename R, int RMAX, int LGM, int INM, int OPS, int ZM, int OUTM, int FIN>
+__global__ __launch_bounds__(PassThreads<RMAX>::v) void k_pass(PassArgs a) {
+    pass_body<R, RMAX, LGM, INM, OPS, ZM, OUTM, FIN>(a, xcd_block((int)blockIdx.x, (int)gridDim.x));
+}
+
+// One launch over the lines of many instances (each with its own PassArgs).
+template <typename R, int RMAX, int INM, int OPS, int ZM, int OUTM, int FIN>
+__global__ __launch_bounds__(PassThreads<RMAX>::v) void k_pass_batch(const PassArgs* args, const int* offs,
+                                                                      int count) {
+    const int g = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int i = batch_find(offs, count, g);
+    pass_body<R, RMAX, 0, INM, OPS, ZM, OUTM, FIN>(args[i], g - offs[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -523,10 +546,10 @@ __global__ __launch_bounds__(PassThreads<RMAX>::v) void k_pass(PassArgs a) {
 // ---------------------------------------------------------------------------
 
 // D = rho tau |u|^2 (+ tau V), FP64 and FP32 copies.
-__global__ void k_precond_setup(StreamArgs a) {
+__device__ __forceinline__ void precond_setup_body(const StreamArgs& a, int blk, int nblk) {
     const long long N = a.N;
     const double2* u = reinterpret_cast<const double2*>(a.u);
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (long long)gridDim.x * blockDim.x) {
+    for (long long i = (long long)blk * blockDim.x + threadIdx.x; i < N; i += (long long)nblk * blockDim.x) {
         const double2 v = u[i];
         double Dj = a.rho * a.tau * (v.x * v.x + v.y * v.y);
         if (a.V) Dj += a.tau * a.V[i];
@@ -537,10 +560,10 @@ __global__ void k_precond_setup(StreamArgs a) {
 
 // Solve start: per-workgroup partials of ||b||^2 (optionally writing the
 // complex64 copy of b).  kEpt elements per thread, all loads issued first.
-__global__ __launch_bounds__(256) void k_prepare(StreamArgs a) {
+__device__ __forceinline__ void prepare_body(const StreamArgs& a, int blk) {
     __shared__ double2 s_red[kMaxWaves];
     const long long N = a.N;
-    const long long base = (long long)blockIdx.x * (kStreamThreads * kEpt) + threadIdx.x;
+    const long long base = (long long)blk * (kStreamThreads * kEpt) + threadIdx.x;
     double2 v[kEpt];
 #pragma unroll
     for (int q = 0; q < kEpt; ++q) {
@@ -557,18 +580,18 @@ __global__ __launch_bounds__(256) void k_prepare(StreamArgs a) {
     nrm = wave_sum(nrm);
     if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = dmk(nrm, 0.0);
     __syncthreads();
-    block_partial_write(s_red, 1, a.pout, a.pstride);
+    block_partial_write(s_red, 1, a.pout, a.pstride, blk);
 }
 
 // End of a cycle, flexible form: x (+)= sum_{k < st->k} y_k z_k, with z_k the
 // preconditioned basis vectors P^{-1} v_k that the Arnoldi passes stored
 // (complex<R>, `vbase` + k N); x in FP64.  first = 1 sets x instead of adding.
 template <typename R>
-__global__ __launch_bounds__(256) void k_zupdate(StreamArgs a) {
+__device__ __forceinline__ void zupdate_body(const StreamArgs& a, int blk) {
     using C = cplx<R>;
     const long long N = a.N;
     const int k = a.st->k;
-    const long long base = (long long)blockIdx.x * (kStreamThreads * kEpt) + threadIdx.x;
+    const long long base = (long long)blk * (kStreamThreads * kEpt) + threadIdx.x;
     double2* x = a.x64;
     double ax[kEpt], ay[kEpt];
 #pragma unroll
@@ -646,7 +669,7 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs a) {
 // (stride = workgroup size: every load instruction of a wavefront is
 // contiguous) and issues all kEpt loads of a vector at once.
 template <typename R, int MODE>
-__global__ __launch_bounds__(256) void k_cgs(StreamArgs a) {
+__device__ __forceinline__ void cgs_body(const StreamArgs& a, int blk) {
     using C = cplx<R>;
     __shared__ double2 s_red[(kMaxRestart + 2) * kMaxWaves];
     __shared__ double2 s_tot[kMaxRestart + 2];
@@ -661,7 +684,7 @@ __global__ __launch_bounds__(256) void k_cgs(StreamArgs a) {
         const double sg = st->sigma[i];
         const double2 h = dmk(s_tot[i].x * sg, s_tot[i].y * sg);
         s_coef[i] = dmk(h.x * sg, h.y * sg);
-        if (blockIdx.x == 0) {
+        if (blk == 0) {
             if (MODE == 0) {
                 st->hcol[i] = h;
             } else {
@@ -670,10 +693,10 @@ __global__ __launch_bounds__(256) void k_cgs(StreamArgs a) {
             }
         }
     }
-    if (MODE == 0 && blockIdx.x == 0 && threadIdx.x == 0) st->wnorm0 = sqrt(s_tot[nv].x);
+    if (MODE == 0 && blk == 0 && threadIdx.x == 0) st->wnorm0 = sqrt(s_tot[nv].x);
     __syncthreads();
 
-    const long long base = (long long)blockIdx.x * (kStreamThreads * kEpt) + threadIdx.x;
+    const long long base = (long long)blk * (kStreamThreads * kEpt) + threadIdx.x;
     double wx[kEpt], wy[kEpt];
 #pragma unroll
     for (int q = 0; q < kEpt; ++q) {
@@ -737,7 +760,7 @@ __global__ __launch_bounds__(256) void k_cgs(StreamArgs a) {
         nout = 1;
     }
     __syncthreads();
-    block_partial_write(s_red, nout, a.pout, a.pstride);
+    block_partial_write(s_red, nout, a.pout, a.pstride, blk);
 }
 
 // Scalar decision kernel (one workgroup): sums the producer's partials and
@@ -746,7 +769,7 @@ __global__ __launch_bounds__(256) void k_cgs(StreamArgs a) {
 //   FIN_K_RESID:   takes the restart / refinement decision from ||b - A x||.
 enum FinishKind { FIN_K_PREPARE = 0, FIN_K_GIVENS = 1, FIN_K_RESID = 2, FIN_K_REDUCE = 3 };
 
-__global__ __launch_bounds__(256) void k_finish(StreamArgs a) {
+__device__ __forceinline__ void finish_body(const StreamArgs& a) {
     __shared__ double2 s_red[(kMaxRestart + 2) * kMaxWaves];
     __shared__ double2 s_tot[kMaxRestart + 2];
     GmresState* st = a.st;
@@ -799,8 +822,8 @@ __global__ __launch_bounds__(256) void k_finish(StreamArgs a) {
 }
 
 // Configure GMRES limits in the device state (single thread).
-__global__ void k_config(GmresState* st, double tol, double outer_tol, int restart, int maxit, int fixed_iters,
-                         int max_outer) {
+__device__ __forceinline__ void config_one(GmresState* st, double tol, double outer_tol, int restart, int maxit,
+                                           int fixed_iters, int max_outer) {
     st->tol = tol;
     st->inner_tol0 = tol;
     st->outer_tol = outer_tol;
@@ -812,6 +835,56 @@ __global__ void k_config(GmresState* st, double tol, double outer_tol, int resta
     st->active = 0;
     st->done = 0;
 }
+
+// ---------------------------------------------------------------------------
+// kernel entry points: one instance, or many instances in one launch (the
+// workgroups of instance i form the block range [offs[i], offs[i+1]))
+// ---------------------------------------------------------------------------
+__global__ void k_config(GmresState* st, double tol, double outer_tol, int restart, int maxit, int fixed_iters,
+                         int max_outer) {
+    config_one(st, tol, outer_tol, restart, maxit, fixed_iters, max_outer);
+}
+__global__ void k_config_batch(const StreamArgs* args, int count, double tol, double outer_tol, int restart,
+                               int maxit, int fixed_iters, int max_outer) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) config_one(args[i].st, tol, outer_tol, restart, maxit, fixed_iters, max_outer);
+}
+
+__global__ void k_precond_setup(StreamArgs a) { precond_setup_body(a, (int)blockIdx.x, (int)gridDim.x); }
+__global__ void k_precond_setup_batch(const StreamArgs* args, const int* offs, int count) {
+    const int g = (int)blockIdx.x;
+    const int i = batch_find(offs, count, g);
+    precond_setup_body(args[i], g - offs[i], offs[i + 1] - offs[i]);
+}
+
+__global__ __launch_bounds__(256) void k_prepare(StreamArgs a) { prepare_body(a, (int)blockIdx.x); }
+__global__ __launch_bounds__(256) void k_prepare_batch(const StreamArgs* args, const int* offs, int count) {
+    const int g = (int)blockIdx.x;
+    const int i = batch_find(offs, count, g);
+    prepare_body(args[i], g - offs[i]);
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_zupdate(StreamArgs a) { zupdate_body<R>(a, (int)blockIdx.x); }
+template <typename R>
+__global__ __launch_bounds__(256) void k_zupdate_batch(const StreamArgs* args, const int* offs, int count) {
+    const int g = (int)blockIdx.x;
+    const int i = batch_find(offs, count, g);
+    zupdate_body<R>(args[i], g - offs[i]);
+}
+
+template <typename R, int MODE>
+__global__ __launch_bounds__(256) void k_cgs(StreamArgs a) { cgs_body<R, MODE>(a, (int)blockIdx.x); }
+template <typename R, int MODE>
+__global__ __launch_bounds__(256) void k_cgs_batch(const StreamArgs* args, const int* offs, int count) {
+    const int g = (int)blockIdx.x;
+    const int i = batch_find(offs, count, g);
+    cgs_body<R, MODE>(args[i], g - offs[i]);
+}
+
+__global__ __launch_bounds__(256) void k_finish(StreamArgs a) { finish_body(a); }
+// one workgroup per instance
+__global__ __launch_bounds__(256) void k_finish_batch(const StreamArgs* args) { finish_body(args[blockIdx.x]); }
 
 // ---------------------------------------------------------------------------
 // host-side launchers (declared in fnls_launch.h)
