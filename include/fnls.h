@@ -205,6 +205,41 @@ int fnls_first_step_backward(fnls_ctx *ctx, const fnls_c128 *u0, const fnls_c128
                              const fnls_c128 *g1, fnls_c128 *g0, double *g_V,
                              const fnls_opts *opts, fnls_info *info);
 
+/* Batches: many independent systems of uneven sizes (each an assembled
+ * context with its own operator, workspace and preconditioner setup)
+ * advanced together.  Every GMRES iteration issues one launch per transform
+ * pass, Gram-Schmidt update and Givens step for all instances together;
+ * each instance keeps its own convergence state, and instances that have
+ * converged drop out.  All contexts must share device, stream and d (d >= 2),
+ * with n >= 31 and n^(d-1) <= 262144.  The batch does not own the contexts. */
+typedef struct fnls_batch fnls_batch;
+
+/* Bytes of caller-owned device workspace for a batch of `count` instances
+ * (argument staging); 0 for count outside [1, 4096]. */
+size_t fnls_batch_workspace_bytes(int count);
+
+/* Create a batch over ctxs[0..count-1] (host array of contexts).  The
+ * workspace (device, 256-byte aligned) must stay valid for the batch's
+ * life.  FNLS_ERR_STATE if a context is not assembled, FNLS_ERR_INVALID_ARG
+ * for mismatched or unsupported contexts. */
+int fnls_batch_create(fnls_batch **out, fnls_ctx *const *ctxs, int count, void *workspace, size_t bytes);
+void fnls_batch_destroy(fnls_batch *batch);
+
+/* f1 -- Solve A_k x_k = b_k for every instance k (host arrays of device
+ * vectors) with each instance's last precond_setup; same options for all
+ * (fixed_iters not supported); infos (may be NULL) receives one fnls_info per
+ * instance.  Returns FNLS_OK, FNLS_NOT_CONVERGED if any instance did not
+ * converge, or an error. */
+int fnls_batch_solve(fnls_batch *batch, const fnls_c128 *const *b, fnls_c128 *const *x,
+                     const fnls_opts *opts, fnls_info *infos);
+
+/* One three-level step of every instance (precond_setup(u_cur), b, solve),
+ * as fnls_step. */
+int fnls_batch_step(fnls_batch *batch, const fnls_c128 *const *u_prev, const fnls_c128 *const *u_cur,
+                    fnls_c128 *const *u_next, const fnls_opts *opts, fnls_info *infos);
+
+const char *fnls_batch_last_error(const fnls_batch *batch);
+
 /* Per-kernel timing (optional instrumentation, used by the benchmark).
  * fnls_timing(ctx, 1) clears earlier records; every following kernel launch
  * of this context then carries a pair of HIP events that the runtime records

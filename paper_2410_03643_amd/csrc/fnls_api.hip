@@ -1284,3 +1284,649 @@ int fnls_set_pass_config(fnls_ctx* c, int precision, int strided, int rmax, int 
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches: many assembled contexts (any sizes, same d, device and stream)
+// advanced together, one kernel launch per pass / update / decision for all
+// of them.  Every instance's lines use radix 4 and 1024-thread workgroups
+// (G = m / 4 threads per line, 1024 / G lines), so one launch shape serves
+// all line lengths; the workgroups of instance i form one block range of the
+// launch.  Per-launch argument arrays are staged through a pinned ring into
+// the caller's batch workspace with one copy per iteration.
+// ---------------------------------------------------------------------------
+constexpr int kBatchThreads = 1024;
+constexpr int kMaxBatch = 4096;
+constexpr size_t kBatchRingMin = (size_t)16 << 20;
+
+struct fnls_batch {
+    int count = 0;
+    std::vector<fnls_ctx*> ctx;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int d = 0;
+    char* dring = nullptr;       // caller's workspace
+    char* hring = nullptr;       // pinned staging
+    size_t ring_bytes = 0;
+    size_t off = 0;
+    hipEvent_t ev[kEvents] = {};
+    std::string err;
+};
+
+namespace {
+
+int berr(fnls_batch* B, int code, const char* fmt, ...) {
+    if (B) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        B->err = buf;
+    }
+    return code;
+}
+
+#define BHIPCHK(B, expr)                                                                             \
+    do {                                                                                             \
+        hipError_t e_ = (expr);                                                                      \
+        if (e_ != hipSuccess) return berr(B, FNLS_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+size_t batch_ring_bytes(int count) { return std::max(kBatchRingMin, (size_t)count * 64 * 1024); }
+
+// Geometry of a pass in a batched launch: radix 4, G * L = 1024.
+Geo batch_geo(int d, int n, int axis, bool fp64) {
+    Geo g;
+    const int m = n + 1;
+    g.rmax = 4;
+    g.G = std::max(1, m / 4);
+    g.L = std::max(1, kBatchThreads / g.G);
+    const size_t elem = fp64 ? 16 : 8;
+    const size_t perline = (size_t)2 * (m + (m >> 3) + 1) * elem;
+    const int q4 = m >= 4 ? m / 4 : 1;
+    const size_t table = (size_t)(m >= 4 ? (q4 - 1) + ((q4 - 1) >> 3) + 1 : 1) * elem;
+    g.lds = (size_t)g.L * perline + table + (size_t)g.L * (8 + elem / 2);
+    g.stride = ipow(n, d - 1 - axis);
+    g.nlines = ipow(n, d - 1);
+    g.blocks = (int)((g.nlines + g.L - 1) / g.L);
+    return g;
+}
+
+// Host-side image of the argument arrays of one or more launches.
+struct Blob {
+    std::vector<char> data;
+    template <typename T> size_t add(const std::vector<T>& v) {
+        const size_t o = align_up(data.size());
+        data.resize(o + v.size() * sizeof(T));
+        if (!v.empty()) std::memcpy(data.data() + o, v.data(), v.size() * sizeof(T));
+        return o;
+    }
+};
+
+// Copy the blob into the device ring (stream-ordered); returns its device base.
+int stage(fnls_batch* B, const Blob& blob, char** dbase) {
+    const size_t n = align_up(blob.data.size());
+    if (n > B->ring_bytes) return berr(B, FNLS_ERR_WORKSPACE, "argument arrays (%zu B) exceed the batch ring", n);
+    if (B->off + n > B->ring_bytes) {
+        // every earlier copy and launch must be done before the ring is reused
+        BHIPCHK(B, hipStreamSynchronize(B->stream));
+        B->off = 0;
+    }
+    std::memcpy(B->hring + B->off, blob.data.data(), blob.data.size());
+    BHIPCHK(B, hipMemcpyAsync(B->dring + B->off, B->hring + B->off, blob.data.size(), hipMemcpyHostToDevice,
+                              B->stream));
+    *dbase = B->dring + B->off;
+    B->off += n;
+    return FNLS_OK;
+}
+
+// One launch of a batch: per-instance arguments and the block offsets.
+struct PassLaunch {
+    PassVariant v;
+    int fp64;
+    std::vector<PassArgs> args;
+    std::vector<int> offs{0};
+    size_t lds = 0;
+    size_t a_off = 0, o_off = 0;
+    void add(const PassArgs& a, const Geo& g) {
+        args.push_back(a);
+        offs.push_back(offs.back() + g.blocks);
+        lds = std::max(lds, g.lds);
+    }
+};
+struct StreamLaunch {
+    int kind;   // 0 cgs (mode), 1 zupdate, 2 prepare, 3 precond_setup, 4 finish
+    int fp64 = 1, mode = 0;
+    std::vector<StreamArgs> args;
+    std::vector<int> offs{0};
+    size_t a_off = 0, o_off = 0;
+    void add(const StreamArgs& a, int blocks) {
+        args.push_back(a);
+        offs.push_back(offs.back() + blocks);
+    }
+};
+
+struct Step {
+    std::vector<PassLaunch> passes;
+    std::vector<StreamLaunch> streams;
+    std::vector<int> order;   // >= 0: pass index, < 0: -(stream index) - 1
+    void pass(PassLaunch p) {
+        order.push_back((int)passes.size());
+        passes.push_back(std::move(p));
+    }
+    void strm(StreamLaunch s) {
+        order.push_back(-(int)streams.size() - 1);
+        streams.push_back(std::move(s));
+    }
+};
+
+int run_step(fnls_batch* B, Step& st) {
+    Blob blob;
+    for (auto& p : st.passes) {
+        p.a_off = blob.add(p.args);
+        p.o_off = blob.add(p.offs);
+    }
+    for (auto& s : st.streams) {
+        s.a_off = blob.add(s.args);
+        s.o_off = blob.add(s.offs);
+    }
+    char* base = nullptr;
+    int rc = stage(B, blob, &base);
+    if (rc != FNLS_OK) return rc;
+    for (int o : st.order) {
+        hipError_t e;
+        if (o >= 0) {
+            const PassLaunch& p = st.passes[o];
+            const int count = (int)p.args.size();
+            if (count == 0) continue;
+            if (p.lds > B->ctx[0]->max_dyn_lds) return berr(B, FNLS_ERR_INVALID_ARG, "batch pass needs %zu B of LDS", p.lds);
+            e = launch_pass_batch(p.fp64, p.v, reinterpret_cast<const PassArgs*>(base + p.a_off),
+                                  reinterpret_cast<const int*>(base + p.o_off), count, p.offs.back(), p.lds,
+                                  kBatchThreads, B->stream);
+        } else {
+            const StreamLaunch& s = st.streams[-o - 1];
+            const int count = (int)s.args.size();
+            if (count == 0) continue;
+            const StreamArgs* a = reinterpret_cast<const StreamArgs*>(base + s.a_off);
+            const int* offs = reinterpret_cast<const int*>(base + s.o_off);
+            switch (s.kind) {
+                case 0: e = launch_cgs_batch(s.fp64, s.mode, a, offs, count, s.offs.back(), B->stream); break;
+                case 1: e = launch_zupdate_batch(s.fp64, a, offs, count, s.offs.back(), B->stream); break;
+                case 2: e = launch_prepare_batch(a, offs, count, s.offs.back(), B->stream); break;
+                case 3: e = launch_precond_setup_batch(a, offs, count, s.offs.back(), B->stream); break;
+                default: e = launch_finish_batch(a, count, B->stream); break;
+            }
+        }
+        if (e != hipSuccess) return berr(B, FNLS_ERR_HIP, "batched launch failed: %s", hipGetErrorString(e));
+    }
+    return FNLS_OK;
+}
+
+StreamArgs stream_base(fnls_ctx* c) {
+    StreamArgs s;
+    std::memset(&s, 0, sizeof s);
+    s.N = c->N;
+    s.pstride = c->lay.pstride;
+    s.pin_stride = c->lay.pstride;
+    s.st = c->st();
+    s.hs = c->hs_dev;
+    return s;
+}
+
+struct Inst {
+    fnls_ctx* c;
+    const double2* b;   // right-hand side (FP64)
+    double2* x;
+    Bufs bf;
+};
+
+// Toeplitz passes of y = (cD D + i ci I + cT T_d) x (FP64) into `fin` final mode on axis 0.
+void add_matvec(Step& st, std::vector<Inst*>& live, const double2* const* xs, double cD, double ci, double cT,
+                int fin, void* const* final_out, bool ir) {
+    fnls_ctx* c0 = live[0]->c;
+    const int d = c0->d;
+    PassLaunch first;
+    first.fp64 = 1;
+    first.v = PassVariant{IN_PLAIN, P_TOEP, Z_NONE, OUT_ACC_FIRST, FIN_WRITE, 4};
+    for (size_t k = 0; k < live.size(); ++k) {
+        fnls_ctx* c = live[k]->c;
+        Geo g = batch_geo(d, c->n, d - 1, true);
+        PassArgs a = base_args(c, true, d - 1, g);
+        a.in = xs[k];
+        a.cD = cD;
+        a.ci = ci;
+        a.cT = cT;
+        a.out = c->at<char>(c->lay.acc);
+        first.add(a, g);
+    }
+    st.pass(std::move(first));
+    for (int ax = d - 2; ax >= 0; --ax) {
+        const bool last = (ax == 0);
+        PassLaunch p;
+        p.fp64 = 1;
+        p.v = PassVariant{IN_PLAIN, P_TOEP, Z_NONE, OUT_ACC_NEXT, last ? fin : FIN_WRITE, 4};
+        for (size_t k = 0; k < live.size(); ++k) {
+            fnls_ctx* c = live[k]->c;
+            Geo g = batch_geo(d, c->n, ax, true);
+            PassArgs a = base_args(c, true, ax, g);
+            a.in = xs[k];
+            a.acc_in = c->at<char>(c->lay.acc);
+            a.cT = cT;
+            a.out = last ? final_out[k] : (void*)c->at<char>(c->lay.acc);
+            if (last && fin == FIN_RESID) {
+                a.b64 = live[k]->b;
+                a.r64 = c->at<double2>(c->lay.r64);
+                a.r32 = ir ? (void*)c->at<float2>(c->lay.V) : nullptr;
+                a.ir = ir ? 1 : 0;
+                a.pout = c->at<double2>(c->lay.pr);
+                a.out = nullptr;
+            }
+            p.add(a, g);
+        }
+        st.pass(std::move(p));
+    }
+}
+
+// One Arnoldi step j of every live instance (same pass sequence as the
+// single-instance path for d >= 2).
+int batch_arnoldi(fnls_batch* B, std::vector<Inst*>& live, bool fp64, int j) {
+    const int d = B->d;
+    const size_t esz = fp64 ? 16 : 8;
+    Step st;
+    std::vector<void*> cur(live.size());
+    int pp = 0;
+    auto front = [&](int ax, int ops, bool first_pass) {
+        PassLaunch p;
+        p.fp64 = fp64 ? 1 : 0;
+        p.v = PassVariant{first_pass ? IN_BASIS : IN_PLAIN, ops, Z_NONE, OUT_LINE, FIN_WRITE, 4};
+        for (size_t k = 0; k < live.size(); ++k) {
+            fnls_ctx* c = live[k]->c;
+            Bufs& b = live[k]->bf;
+            Geo g = batch_geo(d, c->n, ax, fp64);
+            PassArgs a = base_args(c, fp64, ax, g);
+            void* vj = (j == 0) ? b.v0 : (void*)((char*)b.vbase + (size_t)(j - 1) * c->N * esz);
+            a.in = first_pass ? vj : cur[k];
+            a.v0 = b.v0;
+            a.vbase = b.vbase;
+            a.basis_j = j;
+            a.out = (pp == 0) ? b.t1 : b.t2;
+            a.check_active = 1;
+            cur[k] = a.out;
+            p.add(a, g);
+        }
+        pp ^= 1;
+        st.pass(std::move(p));
+    };
+    bool firstp = true;
+    for (int ax = d - 1; ax >= 1; --ax) {
+        front(ax, P_DST1, firstp);
+        firstp = false;
+    }
+    front(0, P_DST1 | P_DIV | P_DST2, false);
+    for (int ax = 1; ax <= d - 2; ++ax) front(ax, P_DST1, false);
+    // last sine transform + scale (z_j kept) + first Toeplitz axis
+    {
+        PassLaunch p;
+        p.fp64 = fp64 ? 1 : 0;
+        p.v = PassVariant{IN_PLAIN, P_DST1 | P_SCALE | P_TOEP, Z_WRITE, OUT_ACC_FIRST, FIN_WRITE, 4};
+        for (size_t k = 0; k < live.size(); ++k) {
+            fnls_ctx* c = live[k]->c;
+            Bufs& b = live[k]->bf;
+            Geo g = batch_geo(d, c->n, d - 1, fp64);
+            PassArgs a = base_args(c, fp64, d - 1, g);
+            a.in = cur[k];
+            a.zout = (char*)b.zbase + (size_t)j * c->N * esz;
+            a.out = b.acc;
+            a.cD = 1.0;
+            a.ci = 1.0;
+            a.cT = -1.0;
+            a.check_active = 1;
+            p.add(a, g);
+        }
+        st.pass(std::move(p));
+    }
+    for (int ax = d - 2; ax >= 0; --ax) {
+        const bool last = (ax == 0);
+        PassLaunch p;
+        p.fp64 = fp64 ? 1 : 0;
+        p.v = PassVariant{IN_PLAIN, P_TOEP, Z_NONE, OUT_ACC_NEXT, last ? FIN_WDOTS : FIN_WRITE, 4};
+        for (size_t k = 0; k < live.size(); ++k) {
+            fnls_ctx* c = live[k]->c;
+            Bufs& b = live[k]->bf;
+            Geo g = batch_geo(d, c->n, ax, fp64);
+            PassArgs a = base_args(c, fp64, ax, g);
+            a.in = (char*)b.zbase + (size_t)j * c->N * esz;
+            a.acc_in = b.acc;
+            a.cT = -1.0;
+            a.check_active = 1;
+            a.out = last ? (void*)((char*)b.vbase + (size_t)j * c->N * esz) : b.acc;
+            a.v0 = b.v0;
+            a.vbase = b.vbase;
+            a.basis_j = j;
+            p.add(a, g);
+        }
+        st.pass(std::move(p));
+    }
+    // Gram-Schmidt updates and the Givens step
+    StreamLaunch u0, u1, gv;
+    u0.kind = 0;
+    u0.mode = 0;
+    u1.kind = 0;
+    u1.mode = 1;
+    u0.fp64 = u1.fp64 = fp64 ? 1 : 0;
+    gv.kind = 4;
+    for (size_t k = 0; k < live.size(); ++k) {
+        fnls_ctx* c = live[k]->c;
+        Bufs& b = live[k]->bf;
+        StreamArgs s = stream_base(c);
+        s.w = (char*)b.vbase + (size_t)j * c->N * esz;
+        s.v0 = b.v0;
+        s.vbase = b.vbase;
+        s.nv = j + 1;
+        s.check_active = 1;
+        const int sb = stream_blocks(c->N);
+        const int nb0 = batch_geo(d, c->n, 0, fp64).blocks;
+        if (nb0 > kRedundantMax || sb > kRedundantMax)
+            return berr(B, FNLS_ERR_INVALID_ARG, "instance too large for a batch (n = %d)", c->n);
+        s.pin = c->at<double2>(c->lay.p1);
+        s.pin_nb = nb0;
+        s.pout = c->at<double2>(c->lay.p2);
+        u0.add(s, sb);
+        s.pin = c->at<double2>(c->lay.p2);
+        s.pin_nb = sb;
+        s.pout = c->at<double2>(c->lay.p3);
+        u1.add(s, sb);
+        s.pin = c->at<double2>(c->lay.p3);
+        s.pin_nb = sb;
+        s.mode = 1;
+        gv.add(s, 1);
+    }
+    st.strm(std::move(u0));
+    st.strm(std::move(u1));
+    st.strm(std::move(gv));
+    return run_step(B, st);
+}
+
+// End of a cycle: x (+)= sum y_k z_k, FP64 residual and the decision.
+int batch_cycle_final(fnls_batch* B, std::vector<Inst*>& live, bool fp64, int first) {
+    const int d = B->d;
+    Step st;
+    StreamLaunch zu;
+    zu.kind = 1;
+    zu.fp64 = fp64 ? 1 : 0;
+    std::vector<const double2*> xs(live.size());
+    std::vector<void*> nulls(live.size(), nullptr);
+    for (size_t k = 0; k < live.size(); ++k) {
+        fnls_ctx* c = live[k]->c;
+        StreamArgs s = stream_base(c);
+        s.vbase = live[k]->bf.zbase;
+        s.x64 = live[k]->x;
+        s.mode = first;
+        zu.add(s, stream_blocks(c->N));
+        xs[k] = live[k]->x;
+    }
+    st.strm(std::move(zu));
+    add_matvec(st, live, xs.data(), 1.0, 1.0, -1.0, FIN_RESID, nulls.data(), !fp64);
+    StreamLaunch fr;
+    fr.kind = 4;
+    for (size_t k = 0; k < live.size(); ++k) {
+        fnls_ctx* c = live[k]->c;
+        StreamArgs s = stream_base(c);
+        s.pin = c->at<double2>(c->lay.pr);
+        s.pin_nb = batch_geo(d, c->n, 0, true).blocks;
+        s.mode = 2;
+        s.ir = fp64 ? 0 : 1;
+        fr.add(s, 1);
+    }
+    st.strm(std::move(fr));
+    return run_step(B, st);
+}
+
+int batch_solve_impl(fnls_batch* B, std::vector<Inst>& inst, const fnls_opts* o, fnls_info* infos) {
+    const bool fp64 = (o->precision == FNLS_FP64);
+    const int n_inst = (int)inst.size();
+    for (auto& I : inst)
+        if (!I.c->have_D) return berr(B, FNLS_ERR_STATE, "an instance has no preconditioner setup");
+    // configuration, ||b||, initial decision
+    {
+        Step st;
+        StreamLaunch pr, fp;
+        pr.kind = 2;
+        fp.kind = 4;
+        std::vector<StreamArgs> cfg;
+        for (auto& I : inst) {
+            fnls_ctx* c = I.c;
+            StreamArgs s = stream_base(c);
+            cfg.push_back(s);
+            s.b64 = I.b;
+            s.r32 = fp64 ? nullptr : (void*)c->at<float2>(c->lay.V);
+            s.pout = c->at<double2>(c->lay.pr);
+            const int sb = stream_blocks(c->N);
+            if (sb > kRedundantMax) return berr(B, FNLS_ERR_INVALID_ARG, "instance too large for a batch");
+            pr.add(s, sb);
+            StreamArgs f = stream_base(c);
+            f.pin = c->at<double2>(c->lay.pr);
+            f.pin_nb = sb;
+            f.mode = 0;
+            fp.add(f, 1);
+        }
+        Blob blob;
+        const size_t cfg_off = blob.add(cfg);
+        char* base = nullptr;
+        int rc = stage(B, blob, &base);
+        if (rc != FNLS_OK) return rc;
+        hipError_t e = launch_config_batch(reinterpret_cast<const StreamArgs*>(base + cfg_off), n_inst,
+                                           fp64 ? o->tol : o->inner_tol, o->tol, o->restart, o->maxit,
+                                           fp64 ? o->fixed_iters : 0, fp64 ? (1 << 30) : o->max_outer, B->stream);
+        if (e != hipSuccess) return berr(B, FNLS_ERR_HIP, "config launch failed: %s", hipGetErrorString(e));
+        st.strm(std::move(pr));
+        st.strm(std::move(fp));
+        if ((rc = run_step(B, st)) != FNLS_OK) return rc;
+    }
+    BHIPCHK(B, hipStreamSynchronize(B->stream));
+    std::vector<Inst*> live;
+    int worst = FNLS_OK;
+    for (int k = 0; k < n_inst; ++k) {
+        const HostStatus& hs = *inst[k].c->hs;
+        if (hs.done) {
+            if (hs.nonfinite) {
+                fill_info(inst[k].c, infos ? &infos[k] : nullptr, FNLS_ERR_NONFINITE);
+                worst = FNLS_ERR_NONFINITE;
+            } else {
+                BHIPCHK(B, hipMemsetAsync(inst[k].x, 0, (size_t)inst[k].c->N * 16, B->stream));
+                fill_info(inst[k].c, infos ? &infos[k] : nullptr, FNLS_OK);
+                if (infos) infos[k].relres_true = 0.0;
+            }
+        } else {
+            live.push_back(&inst[k]);
+        }
+    }
+    int first = 1;
+    const int lookahead = std::max(0, o->lookahead);
+    while (!live.empty()) {
+        for (Inst* I : live)
+            I->bf = bufs(I->c, fp64, first ? (const void*)I->b : (const void*)I->c->at<double2>(I->c->lay.r64));
+        int issued = 0, waited = 0;
+        while (true) {
+            while (issued < o->restart && issued <= waited + lookahead) {
+                int rc = batch_arnoldi(B, live, fp64, issued);
+                if (rc != FNLS_OK) return rc;
+                BHIPCHK(B, hipEventRecord(B->ev[issued % kEvents], B->stream));
+                ++issued;
+            }
+            BHIPCHK(B, hipEventSynchronize(B->ev[waited % kEvents]));
+            ++waited;
+            bool all = true;
+            for (Inst* I : live) {
+                const HostStatus& hs = *I->c->hs;
+                if (!(hs.stopped || hs.done)) all = false;
+            }
+            if (all || waited >= o->restart) break;
+        }
+        int rc = batch_cycle_final(B, live, fp64, first);
+        if (rc != FNLS_OK) return rc;
+        first = 0;
+        BHIPCHK(B, hipStreamSynchronize(B->stream));
+        std::vector<Inst*> next;
+        for (Inst* I : live) {
+            const HostStatus& hs = *I->c->hs;
+            const int k = (int)(I - inst.data());
+            if (hs.nonfinite) {
+                fill_info(I->c, infos ? &infos[k] : nullptr, FNLS_ERR_NONFINITE);
+                worst = FNLS_ERR_NONFINITE;
+            } else if (hs.done) {
+                const int status = (fp64 && o->fixed_iters > 0) ? FNLS_OK
+                                   : (hs.relres < o->tol ? FNLS_OK : FNLS_NOT_CONVERGED);
+                fill_info(I->c, infos ? &infos[k] : nullptr, status);
+                if (status == FNLS_NOT_CONVERGED && worst == FNLS_OK) worst = FNLS_NOT_CONVERGED;
+            } else {
+                next.push_back(I);
+            }
+        }
+        live.swap(next);
+    }
+    return worst;
+}
+
+int batch_check(fnls_batch* B, const fnls_opts* opts, fnls_opts* o) {
+    for (fnls_ctx* c : B->ctx) {
+        int rc = resolve_opts(c, opts, o);
+        if (rc != FNLS_OK) return berr(B, rc, "instance options: %s", c->err.c_str());
+    }
+    if (o->precision == FNLS_FP64 && o->fixed_iters > 0)
+        return berr(B, FNLS_ERR_INVALID_ARG, "fixed_iters is not supported in batches");
+    BHIPCHK(B, hipSetDevice(B->device));
+    return FNLS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t fnls_batch_workspace_bytes(int count) {
+    if (count < 1 || count > kMaxBatch) return 0;
+    return batch_ring_bytes(count);
+}
+
+int fnls_batch_create(fnls_batch** out, fnls_ctx* const* ctxs, int count, void* workspace, size_t bytes) {
+    if (!out) return FNLS_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!ctxs || count < 1 || count > kMaxBatch) return FNLS_ERR_INVALID_ARG;
+    if (!workspace || bytes < batch_ring_bytes(count) || ((uintptr_t)workspace % kAlign) != 0)
+        return FNLS_ERR_WORKSPACE;
+    for (int i = 0; i < count; ++i) {
+        fnls_ctx* c = ctxs[i];
+        if (!c || !c->assembled) return FNLS_ERR_STATE;
+        if (c->device != ctxs[0]->device || c->stream != ctxs[0]->stream || c->d != ctxs[0]->d)
+            return FNLS_ERR_INVALID_ARG;
+        if (c->d < 2) return FNLS_ERR_INVALID_ARG;
+        for (int a = 0; a < c->d; ++a)
+            for (int p = 0; p < 2; ++p) {
+                const Geo g = batch_geo(c->d, c->n, a, p == 1);
+                if (g.G * g.L != kBatchThreads || g.lds > c->max_dyn_lds) return FNLS_ERR_INVALID_ARG;
+                if (g.blocks > kRedundantMax || stream_blocks(c->N) > kRedundantMax) return FNLS_ERR_INVALID_ARG;
+            }
+        for (int k = 0; k < i; ++k)
+            if (ctxs[k] == c) return FNLS_ERR_INVALID_ARG;
+    }
+    fnls_batch* B = new (std::nothrow) fnls_batch();
+    if (!B) return FNLS_ERR_HIP;
+    B->count = count;
+    B->ctx.assign(ctxs, ctxs + count);
+    B->device = ctxs[0]->device;
+    B->stream = ctxs[0]->stream;
+    B->d = ctxs[0]->d;
+    B->dring = reinterpret_cast<char*>(workspace);
+    B->ring_bytes = batch_ring_bytes(count);
+    if (hipSetDevice(B->device) != hipSuccess ||
+        hipHostMalloc((void**)&B->hring, B->ring_bytes, hipHostMallocDefault) != hipSuccess) {
+        delete B;
+        return FNLS_ERR_HIP;
+    }
+    for (int i = 0; i < kEvents; ++i) {
+        if (hipEventCreateWithFlags(&B->ev[i], hipEventDisableTiming) != hipSuccess) {
+            for (int k = 0; k < i; ++k) (void)hipEventDestroy(B->ev[k]);
+            (void)hipHostFree(B->hring);
+            delete B;
+            return FNLS_ERR_HIP;
+        }
+    }
+    *out = B;
+    return FNLS_OK;
+}
+
+void fnls_batch_destroy(fnls_batch* B) {
+    if (!B) return;
+    (void)hipSetDevice(B->device);
+    (void)hipStreamSynchronize(B->stream);
+    for (int i = 0; i < kEvents; ++i)
+        if (B->ev[i]) (void)hipEventDestroy(B->ev[i]);
+    if (B->hring) (void)hipHostFree(B->hring);
+    delete B;
+}
+
+int fnls_batch_solve(fnls_batch* B, const fnls_c128* const* bs, fnls_c128* const* xs, const fnls_opts* opts,
+                     fnls_info* infos) {
+    if (!B) return FNLS_ERR_INVALID_ARG;
+    if (!bs || !xs) return berr(B, FNLS_ERR_INVALID_ARG, "NULL pointer array");
+    fnls_opts o;
+    int rc = batch_check(B, opts, &o);
+    if (rc != FNLS_OK) return rc;
+    std::vector<Inst> inst(B->count);
+    for (int k = 0; k < B->count; ++k) {
+        if (!bs[k] || !xs[k] || (const void*)bs[k] == (const void*)xs[k])
+            return berr(B, FNLS_ERR_INVALID_ARG, "instance %d: NULL or aliased vectors", k);
+        inst[k].c = B->ctx[k];
+        inst[k].b = reinterpret_cast<const double2*>(bs[k]);
+        inst[k].x = reinterpret_cast<double2*>(xs[k]);
+    }
+    return batch_solve_impl(B, inst, &o, infos);
+}
+
+int fnls_batch_step(fnls_batch* B, const fnls_c128* const* u_prev, const fnls_c128* const* u_cur,
+                    fnls_c128* const* u_next, const fnls_opts* opts, fnls_info* infos) {
+    if (!B) return FNLS_ERR_INVALID_ARG;
+    if (!u_prev || !u_cur || !u_next) return berr(B, FNLS_ERR_INVALID_ARG, "NULL pointer array");
+    fnls_opts o;
+    int rc = batch_check(B, opts, &o);
+    if (rc != FNLS_OK) return rc;
+    std::vector<Inst> inst(B->count);
+    std::vector<Inst*> all;
+    std::vector<const double2*> prev(B->count);
+    std::vector<void*> bout(B->count);
+    Step st;
+    StreamLaunch ps;
+    ps.kind = 3;
+    for (int k = 0; k < B->count; ++k) {
+        fnls_ctx* c = B->ctx[k];
+        if (!u_prev[k] || !u_cur[k] || !u_next[k] || (const void*)u_next[k] == (const void*)u_prev[k] ||
+            (const void*)u_next[k] == (const void*)u_cur[k])
+            return berr(B, FNLS_ERR_INVALID_ARG, "instance %d: NULL or aliased vectors", k);
+        c->tscale = 1.0;
+        c->omega = c->omega > 0 ? c->omega : 1.0;
+        StreamArgs s = stream_base(c);
+        s.u = u_cur[k];
+        s.V = c->Vpot;
+        s.D64 = c->at<double>(c->lay.D64);
+        s.D32 = c->at<float>(c->lay.D32);
+        s.rho = c->rho;
+        s.tau = c->tau;
+        ps.add(s, (int)std::min<long long>(4096, (c->N + 255) / 256));
+        c->have_D = 1;
+        inst[k].c = c;
+        inst[k].b = c->at<double2>(c->lay.bbuf);
+        inst[k].x = reinterpret_cast<double2*>(u_next[k]);
+        all.push_back(&inst[k]);
+        prev[k] = reinterpret_cast<const double2*>(u_prev[k]);
+        bout[k] = c->at<double2>(c->lay.bbuf);
+    }
+    st.strm(std::move(ps));
+    // b = (iI + T_d - D) u_prev
+    add_matvec(st, all, prev.data(), -1.0, 1.0, 1.0, FIN_WRITE, bout.data(), false);
+    if ((rc = run_step(B, st)) != FNLS_OK) return rc;
+    return batch_solve_impl(B, inst, &o, infos);
+}
+
+const char* fnls_batch_last_error(const fnls_batch* B) { return B ? B->err.c_str() : "null batch"; }
+
+}  // extern "C"

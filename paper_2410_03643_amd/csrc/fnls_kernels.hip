@@ -985,6 +985,86 @@ hipError_t launch_pass(int fp64, const PassVariant& v, const PassArgs& a, int bl
     return fp64 ? dispatch_pass<double>(v, a, blocks, lds, s, te) : dispatch_pass<float>(v, a, blocks, lds, s, te);
 }
 
+// ---- batched launches (radix 4, 1024 threads per workgroup, generic line length) ----
+template <typename R, int INM, int OPS, int ZM, int OUTM, int FIN>
+static hipError_t launch_pass_batch_t(const PassArgs* args, const int* offs, int count, int blocks, size_t lds,
+                                      int threads, hipStream_t s) {
+    auto kern = k_pass_batch<R, 4, INM, OPS, ZM, OUTM, FIN>;
+    static size_t granted = 64 * 1024;
+    if (lds > granted) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        granted = lds;
+    }
+    if (threads != PassThreads<4>::v) return hipErrorInvalidConfiguration;
+    return launch_k(kern, dim3(blocks), dim3(threads), lds, s, nullptr, args, offs, count);
+}
+
+#define FNLS_BATCH_CASE(R, INM, OPS, ZM, OUTM, FIN)                                             \
+    if (v.inm == INM && v.ops == (OPS) && v.zm == ZM && v.outm == OUTM && v.fin == FIN)         \
+        return launch_pass_batch_t<R, INM, OPS, ZM, OUTM, FIN>(args, offs, count, blocks, lds, threads, s);
+
+template <typename R>
+static hipError_t dispatch_pass_batch(const PassVariant& v, const PassArgs* args, const int* offs, int count,
+                                      int blocks, size_t lds, int threads, hipStream_t s) {
+    constexpr int DST = OP_DST1;
+    constexpr int DDD = OP_DST1 | OP_DIV | OP_DST2;
+    constexpr int LASTDST_T = OP_DST1 | OP_SCALE | OP_TOEP;
+    constexpr int TOEP = OP_TOEP;
+    FNLS_BATCH_CASE(R, IN_PLAIN, DST, Z_NONE, OUT_LINE, FIN_WRITE)
+    FNLS_BATCH_CASE(R, IN_BASIS, DST, Z_NONE, OUT_LINE, FIN_WRITE)
+    FNLS_BATCH_CASE(R, IN_PLAIN, DDD, Z_NONE, OUT_LINE, FIN_WRITE)
+    FNLS_BATCH_CASE(R, IN_PLAIN, LASTDST_T, Z_WRITE, OUT_ACC_FIRST, FIN_WRITE)
+    FNLS_BATCH_CASE(R, IN_PLAIN, TOEP, Z_NONE, OUT_ACC_FIRST, FIN_WRITE)
+    FNLS_BATCH_CASE(R, IN_PLAIN, TOEP, Z_NONE, OUT_ACC_NEXT, FIN_WRITE)
+    FNLS_BATCH_CASE(R, IN_PLAIN, TOEP, Z_NONE, OUT_ACC_NEXT, FIN_WDOTS)
+    FNLS_BATCH_CASE(R, IN_PLAIN, TOEP, Z_NONE, OUT_ACC_NEXT, FIN_RESID)
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_pass_batch(int fp64, const PassVariant& v, const PassArgs* args, const int* offs, int count,
+                             int blocks, size_t lds, int threads, hipStream_t s) {
+    return fp64 ? dispatch_pass_batch<double>(v, args, offs, count, blocks, lds, threads, s)
+                : dispatch_pass_batch<float>(v, args, offs, count, blocks, lds, threads, s);
+}
+
+hipError_t launch_cgs_batch(int fp64, int mode, const StreamArgs* args, const int* offs, int count, int blocks,
+                            hipStream_t s) {
+    const dim3 g(blocks), b(kStreamThreads);
+    if (fp64)
+        return mode == 0 ? launch_k(k_cgs_batch<double, 0>, g, b, 0, s, nullptr, args, offs, count)
+                         : launch_k(k_cgs_batch<double, 1>, g, b, 0, s, nullptr, args, offs, count);
+    return mode == 0 ? launch_k(k_cgs_batch<float, 0>, g, b, 0, s, nullptr, args, offs, count)
+                     : launch_k(k_cgs_batch<float, 1>, g, b, 0, s, nullptr, args, offs, count);
+}
+
+hipError_t launch_zupdate_batch(int fp64, const StreamArgs* args, const int* offs, int count, int blocks,
+                                hipStream_t s) {
+    const dim3 g(blocks), b(kStreamThreads);
+    return fp64 ? launch_k(k_zupdate_batch<double>, g, b, 0, s, nullptr, args, offs, count)
+                : launch_k(k_zupdate_batch<float>, g, b, 0, s, nullptr, args, offs, count);
+}
+
+hipError_t launch_prepare_batch(const StreamArgs* args, const int* offs, int count, int blocks, hipStream_t s) {
+    return launch_k(k_prepare_batch, dim3(blocks), dim3(kStreamThreads), 0, s, nullptr, args, offs, count);
+}
+
+hipError_t launch_precond_setup_batch(const StreamArgs* args, const int* offs, int count, int blocks,
+                                      hipStream_t s) {
+    return launch_k(k_precond_setup_batch, dim3(blocks), dim3(256), 0, s, nullptr, args, offs, count);
+}
+
+hipError_t launch_finish_batch(const StreamArgs* args, int count, hipStream_t s) {
+    return launch_k(k_finish_batch, dim3(count), dim3(kStreamThreads), 0, s, nullptr, args);
+}
+
+hipError_t launch_config_batch(const StreamArgs* args, int count, double tol, double outer_tol, int restart,
+                               int maxit, int fixed_iters, int max_outer, hipStream_t s) {
+    return launch_k(k_config_batch, dim3((count + 255) / 256), dim3(256), 0, s, nullptr, args, count, tol,
+                    outer_tol, restart, maxit, fixed_iters, max_outer);
+}
+
 hipError_t launch_precond_setup(const StreamArgs& a, int blocks, hipStream_t s, const LaunchEvents* te) {
     return launch_k(k_precond_setup, dim3(blocks), dim3(kStreamThreads), 0, s, te, a);
 }

@@ -35,6 +35,19 @@ hipError_t launch_adjoint(const AdjointArgs& a, hipStream_t s, const LaunchEvent
 // x (+)= sum_k y_k z_k over the stored preconditioned basis (vbase, st->k vectors)
 hipError_t launch_zupdate(int fp64, const StreamArgs& a, int blocks, hipStream_t s,
                           const LaunchEvents* te = nullptr);
+// batched launches: instance i owns the blocks [offs[i], offs[i+1]); args / offs in device memory
+hipError_t launch_pass_batch(int fp64, const PassVariant& v, const PassArgs* args, const int* offs, int count,
+                             int blocks, size_t lds, int threads, hipStream_t s);
+hipError_t launch_cgs_batch(int fp64, int mode, const StreamArgs* args, const int* offs, int count, int blocks,
+                            hipStream_t s);
+hipError_t launch_zupdate_batch(int fp64, const StreamArgs* args, const int* offs, int count, int blocks,
+                                hipStream_t s);
+hipError_t launch_prepare_batch(const StreamArgs* args, const int* offs, int count, int blocks, hipStream_t s);
+hipError_t launch_precond_setup_batch(const StreamArgs* args, const int* offs, int count, int blocks,
+                                      hipStream_t s);
+hipError_t launch_finish_batch(const StreamArgs* args, int count, hipStream_t s);   // one workgroup per instance
+hipError_t launch_config_batch(const StreamArgs* args, int count, double tol, double outer_tol, int restart,
+                               int maxit, int fixed_iters, int max_outer, hipStream_t s);
 hipError_t launch_config(GmresState* st, double tol, double outer_tol, int restart, int maxit, int fixed_iters,
                          int max_outer, hipStream_t s);
 

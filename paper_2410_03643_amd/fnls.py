@@ -112,6 +112,20 @@ def lib() -> ctypes.CDLL:
     L.fnls_step_backward.restype = ci
     L.fnls_first_step_backward.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(Opts), ctypes.POINTER(Info)]
     L.fnls_first_step_backward.restype = ci
+    L.fnls_batch_workspace_bytes.argtypes = [ci]
+    L.fnls_batch_workspace_bytes.restype = sz
+    L.fnls_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ci, vp, sz]
+    L.fnls_batch_create.restype = ci
+    L.fnls_batch_destroy.argtypes = [vp]
+    L.fnls_batch_destroy.restype = None
+    L.fnls_batch_solve.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(Opts),
+                                   ctypes.POINTER(Info)]
+    L.fnls_batch_solve.restype = ci
+    L.fnls_batch_step.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                  ctypes.POINTER(Opts), ctypes.POINTER(Info)]
+    L.fnls_batch_step.restype = ci
+    L.fnls_batch_last_error.argtypes = [vp]
+    L.fnls_batch_last_error.restype = ctypes.c_char_p
     _lib = L
     return L
 
@@ -312,6 +326,72 @@ class Solver:
         if getattr(self, "_ctx", None):
             lib().fnls_destroy(self._ctx)
             self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many Solver instances (uneven sizes, same d, device and stream)
+    advanced together: one kernel launch per pass / update / decision for all
+    of them.  The solvers must outlive the batch."""
+
+    def __init__(self, solvers):
+        import torch
+        self.torch = torch
+        self.solvers = list(solvers)
+        if not self.solvers:
+            raise ValueError("empty batch")
+        L = lib()
+        n = len(self.solvers)
+        ctxs = (ctypes.c_void_p * n)(*[s._ctx for s in self.solvers])
+        nbytes = L.fnls_batch_workspace_bytes(n)
+        if nbytes == 0:
+            raise FnlsError(ERR_INVALID_ARG, "unsupported batch size %d" % n)
+        dev = self.solvers[0].device
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        ptr = (self._ws.data_ptr() + 255) // 256 * 256
+        self._b = ctypes.c_void_p()
+        rc = L.fnls_batch_create(ctypes.byref(self._b), ctxs, n, ctypes.c_void_p(ptr), nbytes)
+        if rc != OK:
+            raise FnlsError(rc, L.fnls_status_string(rc).decode())
+
+    def _check(self, rc):
+        if rc < 0:
+            raise FnlsError(rc, lib().fnls_batch_last_error(self._b).decode())
+        return rc
+
+    def _ptrs(self, ts, name):
+        n = len(self.solvers)
+        if len(ts) != n:
+            raise ValueError("%s: expected %d tensors" % (name, n))
+        return (ctypes.c_void_p * n)(*[s._vec(t, name) for s, t in zip(self.solvers, ts)])
+
+    def solve(self, bs, outs=None, *, tol=1e-10, restart=30, maxit=2000, precision="fp64", inner_tol=1e-5,
+              max_outer=20, lookahead=1):
+        xs = [s._out() for s in self.solvers] if outs is None else outs
+        o = Solver._opts(tol, restart, maxit, precision, inner_tol, max_outer, 0, lookahead)
+        infos = (Info * len(self.solvers))()
+        self._check(lib().fnls_batch_solve(self._b, self._ptrs(bs, "b"), self._ptrs(xs, "x"), ctypes.byref(o),
+                                           infos))
+        return xs, [Solver._info(i) for i in infos]
+
+    def step(self, u_prev, u_cur, outs=None, *, tol=1e-10, restart=30, maxit=2000, precision="fp64",
+             inner_tol=1e-5, max_outer=20, lookahead=1):
+        un = [s._out() for s in self.solvers] if outs is None else outs
+        o = Solver._opts(tol, restart, maxit, precision, inner_tol, max_outer, 0, lookahead)
+        infos = (Info * len(self.solvers))()
+        self._check(lib().fnls_batch_step(self._b, self._ptrs(u_prev, "u_prev"), self._ptrs(u_cur, "u_cur"),
+                                          self._ptrs(un, "u_next"), ctypes.byref(o), infos))
+        return un, [Solver._info(i) for i in infos]
+
+    def close(self):
+        if getattr(self, "_b", None) and self._b.value:
+            lib().fnls_batch_destroy(self._b)
+            self._b = ctypes.c_void_p()
 
     def __del__(self):
         try:

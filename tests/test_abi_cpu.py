@@ -70,6 +70,13 @@ def test_null_context_is_rejected(L):
     assert L.fnls_set_potential(None, None) == fnls.ERR_INVALID_ARG
     assert L.fnls_step_backward(None, None, None, None, None, None, None, None, None, None) == fnls.ERR_INVALID_ARG
     assert L.fnls_first_step_backward(None, None, None, None, None, None, None, None) == fnls.ERR_INVALID_ARG
+    assert L.fnls_batch_create(None, None, 0, None, 0) == fnls.ERR_INVALID_ARG
+    assert L.fnls_batch_solve(None, None, None, None, None) == fnls.ERR_INVALID_ARG
+    assert L.fnls_batch_step(None, None, None, None, None, None) == fnls.ERR_INVALID_ARG
+    assert L.fnls_batch_last_error(None) == b"null batch"
+    assert L.fnls_batch_workspace_bytes(0) == 0 and L.fnls_batch_workspace_bytes(4097) == 0
+    assert L.fnls_batch_workspace_bytes(64) >= 16 << 20
+    L.fnls_batch_destroy(None)
     L.fnls_destroy(None)
     assert L.fnls_last_error(None) == b"null context"
 

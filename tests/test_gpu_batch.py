@@ -1,0 +1,142 @@
+"""Batched solves through the C ABI (fnls_batch_*): many instances of uneven
+sizes advanced together with one launch per pass for all of them.
+
+* A mixed batch (d = 2, n in {31, 63, 127, 255}, different alpha, rho, and
+  one zero right-hand side) against the single-instance path and the oracle:
+  each instance's iteration count within 1 of the oracle's, x within 1e-10 of
+  the oracle's solution at the same iteration count, oracle residual < tol;
+  FP64 and FP32-IR.
+* The batched workload at full size: 64 instances on [-10, 10]^2 with n
+  drawn from {127, 255, 511, 1023}, alpha ~ U[1.1, 1.9], rho ~ U[0.5, 3],
+  dt 0.01, soliton data with random centre and phase (seed 0); one
+  three-level step of every instance in FP32-IR to 1e-10; every instance's
+  FP64 residual below 1e-10, a sample checked by the oracle's operator; the
+  batch timed against the same steps taken one instance at a time.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2410_03643_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch, torch.device("cuda", 0)
+
+
+def to_np(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+MIXED = [(31, 1.2, 0.5), (63, 1.5, 2.0), (127, 1.8, 1.0), (255, 1.4, 3.0), (63, 1.9, 2.5), (127, 1.1, 0.7),
+         (31, 1.6, 2.0)]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_mixed_batch_matches_single_and_oracle(torch_dev, precision):
+    from paper_2410_03643_amd.fnls import Batch, Solver
+    torch, dev = torch_dev
+    lo, hi, dt = -10.0, 10.0, 0.01
+    solvers, us, bs, probs = [], [], [], []
+    for k, (n, alpha, rho) in enumerate(MIXED):
+        h = (hi - lo) / (n + 1)
+        u = inputs.soliton(2, n, lo, hi, center=[0.5 * k - 1.0, 0.3], phase=0.4 * k, noise=1e-3, seed=k)
+        s = Solver(alpha, rho, 2, n, h, dt, device=dev)
+        ut = torch.from_numpy(u).to(dev)
+        s.precond_setup(ut)
+        b = s.rhs(ut)
+        if k == len(MIXED) - 1:
+            b.zero_()                       # a zero right-hand side: x = 0, IT = 0
+        solvers.append(s)
+        us.append(u)
+        bs.append(b)
+        probs.append((n, alpha, rho, h))
+    batch = Batch(solvers)
+    xs, infos = batch.solve(bs, tol=TOL, precision=precision)
+    for k, (s, b, x, info) in enumerate(zip(solvers, bs, xs, infos)):
+        n, alpha, rho, h = probs[k]
+        xn, bn = to_np(x), to_np(b)
+        if k == len(MIXED) - 1:
+            assert info.status == 0 and info.iters == 0 and np.abs(xn).max() == 0.0
+            continue
+        # the single-instance path on the same system
+        x1, i1 = s.solve(b, tol=TOL, precision=precision)
+        o = oracle.OracleSolver(alpha, rho, 2, n, h, dt)
+        o.precond_setup(us[k])
+        res = np.linalg.norm(bn - o.apply_A(xn)) / np.linalg.norm(bn)
+        e1 = np.linalg.norm(xn - to_np(x1)) / np.linalg.norm(to_np(x1))
+        msg = "instance %d n=%d: IT batch %d single %d outer %d, relres %.2e, |x - x_single| %.1e" % (
+            k, n, info.iters, i1.iters, info.outer_iters, res, e1)
+        if precision == "fp64":
+            xo, io = o.solve(bn, tol=TOL)
+            if io.iters != info.iters:
+                xo, _ = o.solve(bn, fixed_iters=info.iters)
+            eo = np.linalg.norm(xn - xo) / np.linalg.norm(xo)
+            msg += ", oracle IT %d, |x - x_oracle| %.1e" % (io.iters, eo)
+            assert abs(info.iters - io.iters) <= 1 and eo <= 1e-10
+        print(msg, flush=True)
+        assert info.status == 0 and res < TOL
+        assert abs(info.iters - i1.iters) <= 1
+        assert e1 <= 1e-8
+    batch.close()
+
+
+def test_batched_workload_64_instances(torch_dev):
+    from paper_2410_03643_amd.fnls import Batch, Solver
+    torch, dev = torch_dev
+    cases = inputs.batched_cases(64)
+    sizes = sorted(set(p.n for p in cases))
+    print("64 instances, n counts %s" % {n: sum(p.n == n for p in cases) for n in sizes}, flush=True)
+    solvers = [Solver(p.alpha, p.rho, p.d, p.n, p.h, p.tau, device=dev) for p in cases]
+    us = [torch.from_numpy(p.u).to(dev) for p in cases]
+    batch = Batch(solvers)
+    outs = [torch.empty_like(u) for u in us]
+    for _ in range(3):
+        batch.step(us, us, outs, tol=TOL, precision="fp32_ir")
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        _, infos = batch.step(us, us, outs, tol=TOL, precision="fp32_ir")
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / reps
+    # the same steps one instance at a time
+    single = [torch.empty_like(u) for u in us]
+    for s, u, o in zip(solvers, us, single):
+        s.step(u, u, o, tol=TOL, precision="fp32_ir")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sinfos = [s.step(u, u, o, tol=TOL, precision="fp32_ir")[1] for s, u, o in zip(solvers, us, single)]
+    torch.cuda.synchronize()
+    ts = (time.perf_counter() - t0) / reps
+    its = [i.iters for i in infos]
+    print("batch: %.2f ms per step of all 64 (%.0f instance-steps/s); one at a time: %.2f ms (%.0f/s); "
+          "speed-up %.2f; IT %d-%d, max relres %.2e"
+          % (1e3 * tb, 64 / tb, 1e3 * ts, 64 / ts, ts / tb, min(its), max(its), max(i.relres_true for i in infos)),
+          flush=True)
+    assert all(i.status == 0 and i.relres_true < TOL for i in infos)
+    assert all(abs(a.iters - b.iters) <= 1 for a, b in zip(infos, sinfos))
+    # the oracle's residual for a sample of instances, and agreement with the single path
+    for k in range(0, 64, 9):
+        p = cases[k]
+        o = oracle.OracleSolver(p.alpha, p.rho, p.d, p.n, p.h, p.tau)
+        o.precond_setup(p.u)
+        b = o.rhs(p.u)
+        x = to_np(outs[k])
+        res = np.linalg.norm(b - o.apply_A(x)) / np.linalg.norm(b)
+        e1 = np.linalg.norm(x - to_np(single[k])) / np.linalg.norm(to_np(single[k]))
+        print("instance %d (n=%d): oracle residual %.2e, |x_batch - x_single| %.1e" % (k, p.n, res, e1), flush=True)
+        assert res < TOL and e1 <= 1e-8
+    batch.close()
