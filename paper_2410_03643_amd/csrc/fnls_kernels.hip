@@ -403,6 +403,27 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk) {
     // ---- element phase 1: preconditioner scale, z / x outputs, Toeplitz operand
     if (kPhase1) {
         const double om = a.omega;
+        // every global operand of this phase is loaded before the first
+        // global store (a store could alias a later load, which would
+        // serialise one memory round trip per element)
+        constexpr bool kNeedD = (OPS & OP_SCALE) != 0;
+        constexpr bool kNeedX = (ZM == Z_XADD);
+        R dpre[kNeedD ? kMaxEptLine : 1];
+        double2 xpre[kNeedX ? kMaxEptLine : 1];
+#pragma unroll
+        for (int q = 0; q < kMaxEptLine; ++q) {
+            const int e = tid + q * T;
+            if (kNeedD) dpre[q] = R(0);
+            if (kNeedX) xpre[q] = dmk(0.0, 0.0);
+            if (e >= E) continue;
+            int l, j;
+            emap(e, l, j);
+            const long long base = s_base[l];
+            if (base < 0) continue;
+            const long long gi = base + (long long)j * stride;
+            if (kNeedD) dpre[q] = Dv[gi];
+            if (kNeedX && !a.first_cycle) xpre[q] = a.x64[gi];
+        }
 #pragma unroll
         for (int q = 0; q < kMaxEptLine; ++q) {
             const int e = tid + q * T;
@@ -414,7 +435,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk) {
             if (base >= 0) {
                 const long long gi = base + (long long)j * stride;
                 if (OPS & OP_SCALE) {
-                    const R Dj = Dv[gi];
+                    const R Dj = dpre[kNeedD ? q : 0];
                     // -2 i om / ((om+1) - i D) = (2 om D - 2 i om (om+1)) / ((om+1)^2 + D^2)
                     const R op1 = static_cast<R>(om + 1.0);
                     const R den = op1 * op1 + Dj * Dj;
@@ -426,7 +447,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk) {
                 if (ZM == Z_XSET || ZM == Z_XADD) {
                     double2 xn = dmk((double)z.x, (double)z.y);
                     if (ZM == Z_XADD && !a.first_cycle) {
-                        const double2 xo = a.x64[gi];
+                        const double2 xo = xpre[kNeedX ? q : 0];
                         xn.x += xo.x;
                         xn.y += xo.y;
                     }
@@ -446,6 +467,28 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk) {
         line_toeplitz<R, RMAX, LGM>(A, B, lgm, lt, G, tw, twl, reinterpret_cast<const R*>(a.sym_e),
                          reinterpret_cast<const R*>(a.sym_o), tscale);
         const R cT = static_cast<R>(a.cT);
+        // operands first (see element phase 1)
+        constexpr bool kFirst = (OUTM == OUT_ACC_FIRST);
+        constexpr bool kResid = (FIN == FIN_RESID);
+        R dq[kFirst ? kMaxEptLine : 1];
+        C accq[kFirst ? 1 : kMaxEptLine];
+        double2 bq[kResid ? kMaxEptLine : 1];
+#pragma unroll
+        for (int q = 0; q < kMaxEptLine; ++q) {
+            const int e = tid + q * T;
+            if (kFirst) dq[q] = R(0);
+            else accq[q] = czero<C>();
+            if (kResid) bq[q] = dmk(0.0, 0.0);
+            if (e >= E) continue;
+            int l, j;
+            emap(e, l, j);
+            const long long base = s_base[l];
+            if (base < 0) continue;
+            const long long gi = base + (long long)j * stride;
+            if (kFirst) dq[q] = Dv[gi];
+            else accq[q] = ld<R>(a.acc_in, gi);
+            if (kResid) bq[q] = a.b64[gi];
+        }
 #pragma unroll
         for (int q = 0; q < kMaxEptLine; ++q) {
             const int e = tid + q * T;
@@ -461,12 +504,12 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk) {
             const C tz = cadd(Al[pad(s)], cmulc(Al[PA + pad(s)], tw[s]));
             C o;
             if (OUTM == OUT_ACC_FIRST) {
-                const R Dj = Dv[gi];
+                const R Dj = dq[kFirst ? q : 0];
                 const R cD = static_cast<R>(a.cD) * Dj, ci = static_cast<R>(a.ci);
                 const C z = zreg[kKeepZ ? q : 0];
                 o = cm<R>(cD * z.x - ci * z.y + cT * tz.x, cD * z.y + ci * z.x + cT * tz.y);
             } else {
-                const C acc = ld<R>(a.acc_in, gi);
+                const C acc = accq[kFirst ? 0 : q];
                 o = cm<R>(acc.x + cT * tz.x, acc.y + cT * tz.y);
             }
             if (FIN == FIN_WRITE) {
@@ -476,7 +519,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk) {
                 oreg[q] = o;
                 nrm += (double)o.x * o.x + (double)o.y * o.y;
             } else {
-                const double2 b = a.b64[gi];
+                const double2 b = bq[kResid ? q : 0];
                 const double2 r = dmk(b.x - (double)o.x, b.y - (double)o.y);
                 a.r64[gi] = r;
                 if (a.r32) reinterpret_cast<float2*>(a.r32)[gi] = make_float2((float)r.x, (float)r.y);
@@ -497,25 +540,47 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk) {
     if (FIN == FIN_WDOTS) {
         const int nb = a.basis_j + 1;
         nv = nb + 1;
-        for (int i = 0; i < nb; ++i) {
+        // global index of each element (-1: none) and double-buffered basis
+        // loads: vector i + 1 is in flight while vector i is reduced
+        long long gq[kMaxEptLine];
+#pragma unroll
+        for (int q = 0; q < kMaxEptLine; ++q) {
+            const int e = tid + q * T;
+            gq[q] = -1;
+            if (e >= E) continue;
+            int l, j;
+            emap(e, l, j);
+            const long long base = s_base[l];
+            if (base >= 0) gq[q] = base + (long long)j * stride;
+        }
+        auto load_vec = [&](int i, C* v) {
+            const C* src = (i == 0) ? reinterpret_cast<const C*>(a.v0)
+                                    : reinterpret_cast<const C*>(a.vbase) + (long long)(i - 1) * a.N;
+#pragma unroll
+            for (int q = 0; q < kMaxEptLine; ++q) v[q] = gq[q] >= 0 ? src[gq[q]] : czero<C>();
+        };
+        auto reduce_vec = [&](int i, const C* v) {
             double sx = 0.0, sy = 0.0;
 #pragma unroll
             for (int q = 0; q < kMaxEptLine; ++q) {
-                const int e = tid + q * T;
-                if (e >= E) continue;
-                int l, j;
-                emap(e, l, j);
-                const long long base = s_base[l];
-                if (base < 0) continue;
-                const long long gi = base + (long long)j * stride;
-                const C v = (i == 0) ? ld<R>(a.v0, gi) : ld<R>(a.vbase, (long long)(i - 1) * a.N + gi);
                 const C w = oreg[FIN == FIN_WDOTS ? q : 0];
-                sx += (double)v.x * w.x + (double)v.y * w.y;
-                sy += (double)v.x * w.y - (double)v.y * w.x;
+                sx += (double)v[q].x * w.x + (double)v[q].y * w.y;
+                sy += (double)v[q].x * w.y - (double)v[q].y * w.x;
             }
             sx = wave_sum(sx);
             sy = wave_sum(sy);
             if (lane == 0) s_red[i * nwv + wave] = dmk(sx, sy);
+        };
+        // two register buffers with compile-time indices (no scratch)
+        C va[kMaxEptLine], vb[kMaxEptLine];
+        load_vec(0, va);
+        for (int i = 0; i < nb; i += 2) {
+            if (i + 1 < nb) load_vec(i + 1, vb);
+            reduce_vec(i, va);
+            if (i + 1 < nb) {
+                if (i + 2 < nb) load_vec(i + 2, va);
+                reduce_vec(i + 1, vb);
+            }
         }
         nrm = wave_sum(nrm);
         if (lane == 0) s_red[nb * nwv + wave] = dmk(nrm, 0.0);
