@@ -270,6 +270,16 @@ int fnls_timing_report(fnls_ctx *ctx, fnls_kernel_stat *out, int max_entries);
  * Waits for the context's stream. */
 int fnls_set_pass_config(fnls_ctx *ctx, int precision, int strided, int rmax, int lines);
 
+/* Autotuner of the transform-pass schedule above, for this context's
+ * operator and one precision: times `reps` solves (after one warm-up solve)
+ * of the device vector b with the current preconditioner setup and default
+ * options, for each candidate rmax in {4, 8, 16} and lines in {1, 2, 4}, by
+ * coordinate descent (strided axes first, then the contiguous axis), and
+ * keeps the fastest schedule.  best (may be NULL) receives {rmax, lines} of
+ * the contiguous and then of the strided axes; *best_ms (may be NULL) its
+ * time per solve.  Uses the context's stream and workspace; returns when done. */
+int fnls_autotune(fnls_ctx *ctx, const fnls_c128 *b, int precision, int reps, int best[4], double *best_ms);
+
 /* Last error message of this context ("" if none); valid until the next call. */
 const char *fnls_last_error(const fnls_ctx *ctx);
 

@@ -65,8 +65,8 @@ PassConfig default_pass_config() {
     p.lines[0][1] = 4;
     p.rmax[1][0] = 4;
     p.lines[1][0] = 2;
-    p.rmax[1][1] = 8;
-    p.lines[1][1] = 4;
+    p.rmax[1][1] = 4;
+    p.lines[1][1] = 2;
     return p;
 }
 
@@ -1265,6 +1265,80 @@ int fnls_timing_report(fnls_ctx* c, fnls_kernel_stat* out, int max_entries) {
     for (int i = 0; i < ncls && k < max_entries; ++i)
         if (agg[i].launches > 0) out[k++] = agg[i];
     return k;
+}
+
+int fnls_autotune(fnls_ctx* c, const fnls_c128* b, int precision, int reps, int best[4], double* best_ms) {
+    int rc = check_solve_ready(c);
+    if (rc != FNLS_OK) return rc;
+    if (!b) return set_err(c, FNLS_ERR_INVALID_ARG, "NULL vector");
+    if (precision != FNLS_FP64 && precision != FNLS_FP32_IR)
+        return set_err(c, FNLS_ERR_INVALID_ARG, "unknown precision");
+    if (reps < 1 || reps > 1000) return set_err(c, FNLS_ERR_INVALID_ARG, "reps must lie in [1, 1000]");
+    HIPCHK(c, hipSetDevice(c->device));
+    fnls_opts o;
+    fnls_default_opts(&o);
+    o.precision = precision;
+    o.restart = std::min(o.restart, c->restart_cap);
+    fnls_c128* x = c->at<fnls_c128>(c->lay.adj);
+    const int f = precision == FNLS_FP64 ? 1 : 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(c, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return set_err(c, FNLS_ERR_HIP, "hipEventCreate failed");
+    }
+    // time per solve of the current schedule (one untimed warm-up solve)
+    auto measure = [&](double* ms) -> int {
+        int r = solve_impl(c, b, x, &o, nullptr);
+        if (r < 0) return r;
+        if (hipEventRecord(e0, c->stream) != hipSuccess) return set_err(c, FNLS_ERR_HIP, "hipEventRecord");
+        for (int k = 0; k < reps; ++k) {
+            r = solve_impl(c, b, x, &o, nullptr);
+            if (r < 0) return r;
+        }
+        if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+            return set_err(c, FNLS_ERR_HIP, "event timing failed");
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, e0, e1) != hipSuccess) return set_err(c, FNLS_ERR_HIP, "hipEventElapsedTime");
+        *ms = (double)t / reps;
+        return FNLS_OK;
+    };
+    static const int kRmax[3] = {4, 8, 16};
+    static const int kLines[3] = {1, 2, 4};
+    double cur = 0.0;
+    rc = measure(&cur);
+    // coordinate descent: strided axes, then the contiguous axis
+    for (int strided = 1; strided >= 0 && rc == FNLS_OK; --strided) {
+        int br = c->pcfg.rmax[f][strided], bl = c->pcfg.lines[f][strided];
+        for (int ir = 0; ir < 3 && rc == FNLS_OK; ++ir)
+            for (int il = 0; il < 3 && rc == FNLS_OK; ++il) {
+                const int rm = kRmax[ir], li = kLines[il];
+                if (rm == br && li == bl) continue;
+                if ((1024 / rm) * li > pass_threads_max(rm)) continue;
+                c->pcfg.rmax[f][strided] = rm;
+                c->pcfg.lines[f][strided] = li;
+                double t = 0.0;
+                rc = measure(&t);
+                if (rc == FNLS_OK && t < cur) {
+                    cur = t;
+                    br = rm;
+                    bl = li;
+                }
+            }
+        c->pcfg.rmax[f][strided] = br;
+        c->pcfg.lines[f][strided] = bl;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != FNLS_OK) return rc;
+    if (best) {
+        best[0] = c->pcfg.rmax[f][0];
+        best[1] = c->pcfg.lines[f][0];
+        best[2] = c->pcfg.rmax[f][1];
+        best[3] = c->pcfg.lines[f][1];
+    }
+    if (best_ms) *best_ms = cur;
+    return FNLS_OK;
 }
 
 int fnls_set_pass_config(fnls_ctx* c, int precision, int strided, int rmax, int lines) {

@@ -112,6 +112,8 @@ def lib() -> ctypes.CDLL:
     L.fnls_step_backward.restype = ci
     L.fnls_first_step_backward.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(Opts), ctypes.POINTER(Info)]
     L.fnls_first_step_backward.restype = ci
+    L.fnls_autotune.argtypes = [vp, vp, ci, ci, ctypes.POINTER(ci), ctypes.POINTER(cd)]
+    L.fnls_autotune.restype = ci
     L.fnls_batch_workspace_bytes.argtypes = [ci]
     L.fnls_batch_workspace_bytes.restype = sz
     L.fnls_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ci, vp, sz]
@@ -305,6 +307,15 @@ class Solver:
             self._ctx, self._vec(u0, "u0"), self._vec(u1, "u1"), self._vec(g1, "g1"), self._vec(g0, "g0"),
             self._real(g_V, "g_V"), ctypes.byref(o), ctypes.byref(info)))
         return self._info(info)
+
+    def autotune(self, b, precision="fp64", reps: int = 5):
+        """Time solves of b over the transform-pass schedules and keep the
+        fastest; returns ({axis kind: (rmax, lines)}, ms per solve)."""
+        p = {"fp64": FP64, "fp32_ir": FP32_IR}[precision] if isinstance(precision, str) else precision
+        best = (ctypes.c_int * 4)()
+        ms = ctypes.c_double()
+        self._check(lib().fnls_autotune(self._ctx, self._vec(b, "b"), p, reps, best, ctypes.byref(ms)))
+        return {"contiguous": (best[0], best[1]), "strided": (best[2], best[3])}, ms.value
 
     def set_pass_config(self, precision, strided: bool, rmax: int, lines: int):
         """Transform-pass tuning: largest radix and lines per workgroup."""

@@ -70,6 +70,7 @@ def test_null_context_is_rejected(L):
     assert L.fnls_set_potential(None, None) == fnls.ERR_INVALID_ARG
     assert L.fnls_step_backward(None, None, None, None, None, None, None, None, None, None) == fnls.ERR_INVALID_ARG
     assert L.fnls_first_step_backward(None, None, None, None, None, None, None, None) == fnls.ERR_INVALID_ARG
+    assert L.fnls_autotune(None, None, 0, 1, None, None) == fnls.ERR_INVALID_ARG
     assert L.fnls_batch_create(None, None, 0, None, 0) == fnls.ERR_INVALID_ARG
     assert L.fnls_batch_solve(None, None, None, None, None) == fnls.ERR_INVALID_ARG
     assert L.fnls_batch_step(None, None, None, None, None, None) == fnls.ERR_INVALID_ARG

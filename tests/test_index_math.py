@@ -20,7 +20,8 @@ STREAM_THREADS = 256
 
 DEFAULT_CFG = {"rmax": (4, 4), "lines": (1, 4)}   # (contiguous axis, strided axes)
 CONFIGS = [DEFAULT_CFG,
-           {"rmax": (4, 8), "lines": (2, 4)},       # FP64 default
+           {"rmax": (4, 8), "lines": (2, 4)},
+           {"rmax": (4, 4), "lines": (2, 2)},       # FP64 default
            {"rmax": (4, 8), "lines": (1, 4)},       # FP32 default
            {"rmax": (8, 8), "lines": (1, 4)},
            {"rmax": (16, 16), "lines": (1, 4)},
