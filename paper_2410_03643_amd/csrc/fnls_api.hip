@@ -178,6 +178,9 @@ struct fnls_ctx {
     HostStatus* hs = nullptr;       // pinned, device-written
     HostStatus* hs_dev = nullptr;
     hipEvent_t ev[kEvents] = {};
+    hipEvent_t evp[kEvents] = {};   // after the first pass of an Arnoldi iteration
+    int fuse = 0;                   // Givens step of iteration j in the first pass of j + 1
+    int restart_cur = 0;            // restart length of the running cycle
     // optional per-launch timing (fnls_timing / fnls_timing_report)
     struct TimingRec {
         int cls;
@@ -331,10 +334,23 @@ double pass_bytes(fnls_ctx* c, bool fp64, const PassVariant& v, const PassArgs& 
     return b;
 }
 
+// Dynamic LDS of a pass: passes without the Toeplitz product keep one
+// buffer per line (the sine transform needs one FFT buffer); at least 4 KB
+// (the fused Givens workgroup stages its column there).
+size_t pass_lds(const Geo& g, int m, bool fp64, bool two_buffers) {
+    const size_t elem = fp64 ? 16 : 8;
+    const size_t pa = (size_t)(m + (m >> 3) + 1) * elem;
+    const int q4 = m >= 4 ? m / 4 : 1;
+    const size_t table = (size_t)(m >= 4 ? (q4 - 1) + ((q4 - 1) >> 3) + 1 : 1) * elem;
+    const size_t lds = (size_t)g.L * (two_buffers ? 2 : 1) * pa + table + (size_t)g.L * (8 + elem / 2);
+    return std::max<size_t>(lds, 4096);
+}
+
 int run_pass(fnls_ctx* c, bool fp64, int axis, PassVariant v, PassArgs& a, const Geo& g) {
     v.rmax = g.rmax;
+    const size_t lds = pass_lds(g, c->m, fp64, (v.ops & P_TOEP) != 0);
     const LaunchEvents* te = c->timing ? timing_begin(c, pass_name(fp64, v, axis), pass_bytes(c, fp64, v, a)) : nullptr;
-    hipError_t e = launch_pass(fp64 ? 1 : 0, v, a, g.blocks, g.lds, c->stream, te);
+    hipError_t e = launch_pass(fp64 ? 1 : 0, v, a, g.blocks + (a.gfuse ? 1 : 0), lds, c->stream, te);
     if (e != hipSuccess) timing_failed(c, te);
     if (e != hipSuccess)
         return set_err(c, FNLS_ERR_HIP, "pass launch (axis %d, ops %d) failed: %s", axis, v.ops, hipGetErrorString(e));
@@ -371,13 +387,19 @@ Bufs bufs(fnls_ctx* c, bool fp64, const void* v0_fp64) {
 // Sine-transform passes that precede the last one: axes d-1 .. 1 forward,
 // axis 0 transform-divide-transform, axes 1 .. d-2 back.  The first pass reads
 // `src` with input mode `inm`; returns the buffer holding the result.
+// scale_second (Arnoldi step, d >= 2): the first pass transforms the raw
+// basis vector, the second applies the basis scale sigma_j, and an event
+// marks the end of the first pass; givens: the first pass also carries the
+// previous iteration's Givens step in an extra workgroup.
 int precond_front(fnls_ctx* c, bool fp64, int inm, const void* src, int basis_j, Bufs& b, void** result,
-                  int check_active) {
+                  int check_active, bool scale_second = false, bool givens = false) {
+    const bool fused = scale_second;
     const int d = c->d;
     void* cur_in = const_cast<void*>(src);
-    int cur_mode = inm;
+    int cur_mode = fused ? IN_PLAIN : inm;
     void* pingpong[2] = {b.t1, b.t2};
     int pp = 0;
+    int npass = 0;
     auto step = [&](int axis, int ops) -> int {
         Geo g = pass_geo(d, c->n, axis, fp64, c->max_dyn_lds, c->pcfg);
         PassArgs a = base_args(c, fp64, axis, g);
@@ -387,11 +409,22 @@ int precond_front(fnls_ctx* c, bool fp64, int inm, const void* src, int basis_j,
         a.basis_j = basis_j;
         a.out = pingpong[pp];
         a.check_active = check_active;
+        if (npass == 0 && givens) {
+            a.gfuse = 1;
+            a.gpin = c->at<double2>(c->lay.p3);
+            a.gpin_nb = stream_blocks(c->N);
+            a.gpin_stride = c->lay.pstride;
+        }
         PassVariant v{cur_mode, ops, Z_NONE, OUT_LINE, FIN_WRITE};
         int rc = run_pass(c, fp64, axis, v, a, g);
+        if (rc == FNLS_OK && npass == 0 && fused) {
+            hipError_t e = hipEventRecord(c->evp[basis_j % kEvents], c->stream);
+            if (e != hipSuccess) rc = set_err(c, FNLS_ERR_HIP, "hipEventRecord: %s", hipGetErrorString(e));
+        }
         cur_in = pingpong[pp];
         pp ^= 1;
-        cur_mode = IN_PLAIN;
+        cur_mode = (fused && npass == 0) ? inm : IN_PLAIN;
+        ++npass;
         return rc;
     };
     int rc;
@@ -512,7 +545,8 @@ int arnoldi_step(fnls_ctx* c, bool fp64, Bufs& b, int j) {
         if ((rc = run_pass(c, fp64, 0, v, a, g)) != FNLS_OK) return rc;
     } else {
         void* t;
-        if ((rc = precond_front(c, fp64, IN_BASIS, vj, j, b, &t, 1)) != FNLS_OK) return rc;
+        if ((rc = precond_front(c, fp64, IN_BASIS, vj, j, b, &t, 1, true, c->fuse != 0 && j >= 1)) != FNLS_OK)
+            return rc;
         Geo g = pass_geo(d, c->n, d - 1, fp64, c->max_dyn_lds, c->pcfg);
         PassArgs a = base_args(c, fp64, d - 1, g);
         a.in = t;
@@ -567,7 +601,8 @@ int arnoldi_step(fnls_ctx* c, bool fp64, Bufs& b, int j) {
     e = launch_cgs(fp64 ? 1 : 0, 1, s, blocks, c->stream, te);
     if (e != hipSuccess) timing_failed(c, te);
     if (e != hipSuccess) return set_err(c, FNLS_ERR_HIP, "cgs launch failed: %s", hipGetErrorString(e));
-    // Givens step and stopping decision
+    // Givens step and stopping decision (fused: in the next iteration's first pass)
+    if (c->fuse && d >= 2 && j + 1 < c->restart_cur) return FNLS_OK;
     s.pin = c->at<double2>(c->lay.p3);
     s.pin_nb = blocks;
     s.pin_stride = c->lay.pstride;
@@ -714,6 +749,10 @@ int run_cycle(fnls_ctx* c, bool fp64, Bufs& b, int restart, int lookahead, int t
         for (int i = std::max(0, active); i < issued; ++i)
             for (size_t r = rec_first[i]; r < c->recs.size(); ++r) c->recs[r].bytes = 0.0;
     };
+    // fused Givens: the status of iteration j is written by the first pass of
+    // iteration j + 1, which the lookahead has issued before the wait
+    c->fuse = (lookahead >= 1 && c->d >= 2 && stream_blocks(c->N) <= kRedundantMax) ? 1 : 0;
+    c->restart_cur = restart;
     while (true) {
         while (issued < restart && issued <= waited + lookahead) {
             rec_first.push_back(c->recs.size());
@@ -722,7 +761,8 @@ int run_cycle(fnls_ctx* c, bool fp64, Bufs& b, int restart, int lookahead, int t
             HIPCHK(c, hipEventRecord(c->ev[issued % kEvents], c->stream));
             ++issued;
         }
-        int rc = wait_status(c, c->ev[waited % kEvents], &hs);
+        const bool via_next = c->fuse && waited + 1 < restart;
+        int rc = wait_status(c, via_next ? c->evp[(waited + 1) % kEvents] : c->ev[waited % kEvents], &hs);
         if (rc != FNLS_OK) return rc;
         ++waited;
         if (hs.done) {
@@ -886,8 +926,12 @@ int fnls_create(fnls_ctx** out, int device, void* hip_stream) {
         return FNLS_ERR_HIP;
     }
     for (int i = 0; i < kEvents; ++i) {
-        if (hipEventCreateWithFlags(&c->ev[i], hipEventDisableTiming) != hipSuccess) {
-            for (int k = 0; k < i; ++k) (void)hipEventDestroy(c->ev[k]);
+        if (hipEventCreateWithFlags(&c->ev[i], hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&c->evp[i], hipEventDisableTiming) != hipSuccess) {
+            for (int k = 0; k <= i; ++k) {
+                if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
+                if (c->evp[k]) (void)hipEventDestroy(c->evp[k]);
+            }
             (void)hipHostFree(c->hs);
             delete c;
             return FNLS_ERR_HIP;
@@ -901,8 +945,10 @@ void fnls_destroy(fnls_ctx* c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
-    for (int i = 0; i < kEvents; ++i)
+    for (int i = 0; i < kEvents; ++i) {
         if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+        if (c->evp[i]) (void)hipEventDestroy(c->evp[i]);
+    }
     if (c->hs) (void)hipHostFree(c->hs);
     for (auto e : c->evpool) (void)hipEventDestroy(e);
     delete c;
@@ -1465,7 +1511,7 @@ struct PassLaunch {
     void add(const PassArgs& a, const Geo& g) {
         args.push_back(a);
         offs.push_back(offs.back() + g.blocks);
-        lds = std::max(lds, g.lds);
+        lds = std::max(lds, pass_lds(g, a.m, fp64 != 0, (v.ops & P_TOEP) != 0));
     }
 };
 struct StreamLaunch {

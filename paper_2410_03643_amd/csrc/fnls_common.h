@@ -10,8 +10,8 @@ namespace fnls {
 // Largest restart length supported by the fixed-size Hessenberg state.
 constexpr int kMaxRestart = 64;
 // Elements per thread in the streaming (CGS update / setup) kernels.
-constexpr int kEpt = 16;
-constexpr int kStreamThreads = 256;
+constexpr int kEpt = 8;
+constexpr int kStreamThreads = 512;
 
 // GMRES state kept in device memory (inside the caller's workspace).  Only
 // the last workgroup of a reduction kernel (and single-workgroup kernels)
@@ -115,6 +115,11 @@ struct PassArgs {
     int check_active;     // return at once if st->active == 0
     int first_cycle;      // Z_XADD: 1 = set x (first correction), 0 = accumulate
     int ir;               // FIN_RESID: 1 = refinement step of FP32-IR
+    // Givens step of the previous Arnoldi iteration in one extra workgroup
+    // (logical block 0) of this launch: partials of ||w||^2 in gpin
+    int gfuse;
+    const double2* gpin;
+    int gpin_nb, gpin_stride;
 };
 
 struct StreamArgs {

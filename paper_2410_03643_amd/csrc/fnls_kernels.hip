@@ -27,7 +27,7 @@
 namespace fnls {
 
 enum OpBits { OP_DST1 = 1, OP_DIV = 2, OP_DST2 = 4, OP_SCALE = 8, OP_TOEP = 16 };
-constexpr int kMaxWaves = 4;     // streaming and finish kernels run 256 threads (4 wavefronts)
+constexpr int kMaxWaves = kStreamThreads / 64;   // wavefronts of the streaming and finish kernels
 
 // ---------------------------------------------------------------------------
 // status reporting
@@ -261,11 +261,33 @@ template <> struct PassThreads<16> { static constexpr int v = 256; };
 // LGM > 0: the line length m = 2^LGM is a compile-time constant (the host
 // launches this specialisation only when a.lgm == LGM); 0: generic.
 template <typename R, int RMAX, int LGM, int INM, int OPS, int ZM, int OUTM, int FIN>
-__device__ __forceinline__ void pass_body(const PassArgs& a, int blk) {
+__device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
     using C = cplx<R>;
     constexpr int kMaxEptLine = RMAX;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     if (a.check_active && a.st->active == 0) return;
+    // with a fused Givens step, logical block 0 (dispatched first, so it runs
+    // beside the first round of line blocks) does it; line blocks follow
+    const int blk = a.gfuse ? blk_in - 1 : blk_in;
+    if (a.gfuse && blk_in == 0) {
+        // the previous iteration's Givens step, beside this pass's line work
+        double2* s_red = reinterpret_cast<double2*>(smem_raw);   // waves
+        double2* s_tot = s_red + 32;
+        double2* s_col = s_tot + 2;                                // kMaxRestart + 1
+        double2* s_sn = s_col + (kMaxRestart + 1);                 // kMaxRestart
+        double* s_cs = reinterpret_cast<double*>(s_sn + kMaxRestart);
+        reduce_partials(a.gpin, a.gpin_stride, a.gpin_nb, 1, s_tot, s_red);
+        GmresState* st = a.st;
+        const int j = st->j;
+        for (int i = threadIdx.x; i <= j; i += blockDim.x) s_col[i] = st->hcol[i];
+        for (int i = threadIdx.x; i < j; i += blockDim.x) {
+            s_cs[i] = st->cs[i];
+            s_sn[i] = st->sn[i];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) arnoldi_finish(st, a.hs, s_tot[0].x, j, s_col, s_cs, s_sn);
+        return;
+    }
 
     const int lgm = LGM ? LGM : a.lgm;
     const int m = 1 << lgm;
@@ -280,7 +302,9 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk) {
     const long long stride = a.stride;
     const bool contiguous = (stride == 1);
     const int PA = padded_len(m);   // padded slots of one line buffer
-    const int LS = 2 * PA;          // line stride: buffers A and B
+    // line stride: buffers A and B for the Toeplitz product, A alone otherwise
+    constexpr bool kTwoBuf = (OPS & OP_TOEP) != 0;
+    const int LS = kTwoBuf ? 2 * PA : PA;
     // dynamic LDS: L lines | quarter twiddle table | per-line base offsets | per-line Lambda
     C* lds = reinterpret_cast<C*>(smem_raw);
     C* twl = lds + (size_t)L * LS;                    // W_m^q at pad(q), q < max(1, m/4)
@@ -375,7 +399,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk) {
     __syncthreads();
 
     C* A = lds + (size_t)line * LS;
-    C* B = A + PA;
+    C* B = kTwoBuf ? A + PA : A;   // B exists only for the Toeplitz product
 
     // ---- transform stages
     if (OPS & OP_DST1) line_dst<R, RMAX, LGM>(A, B, lgm, lt, G, tw, twl);
@@ -922,34 +946,34 @@ __global__ void k_precond_setup_batch(const StreamArgs* args, const int* offs, i
     precond_setup_body(args[i], g - offs[i], offs[i + 1] - offs[i]);
 }
 
-__global__ __launch_bounds__(256) void k_prepare(StreamArgs a) { prepare_body(a, (int)blockIdx.x); }
-__global__ __launch_bounds__(256) void k_prepare_batch(const StreamArgs* args, const int* offs, int count) {
+__global__ __launch_bounds__(kStreamThreads) void k_prepare(StreamArgs a) { prepare_body(a, (int)blockIdx.x); }
+__global__ __launch_bounds__(kStreamThreads) void k_prepare_batch(const StreamArgs* args, const int* offs, int count) {
     const int g = (int)blockIdx.x;
     const int i = batch_find(offs, count, g);
     prepare_body(args[i], g - offs[i]);
 }
 
 template <typename R>
-__global__ __launch_bounds__(256) void k_zupdate(StreamArgs a) { zupdate_body<R>(a, (int)blockIdx.x); }
+__global__ __launch_bounds__(kStreamThreads) void k_zupdate(StreamArgs a) { zupdate_body<R>(a, (int)blockIdx.x); }
 template <typename R>
-__global__ __launch_bounds__(256) void k_zupdate_batch(const StreamArgs* args, const int* offs, int count) {
+__global__ __launch_bounds__(kStreamThreads) void k_zupdate_batch(const StreamArgs* args, const int* offs, int count) {
     const int g = (int)blockIdx.x;
     const int i = batch_find(offs, count, g);
     zupdate_body<R>(args[i], g - offs[i]);
 }
 
 template <typename R, int MODE>
-__global__ __launch_bounds__(256) void k_cgs(StreamArgs a) { cgs_body<R, MODE>(a, (int)blockIdx.x); }
+__global__ __launch_bounds__(kStreamThreads) void k_cgs(StreamArgs a) { cgs_body<R, MODE>(a, (int)blockIdx.x); }
 template <typename R, int MODE>
-__global__ __launch_bounds__(256) void k_cgs_batch(const StreamArgs* args, const int* offs, int count) {
+__global__ __launch_bounds__(kStreamThreads) void k_cgs_batch(const StreamArgs* args, const int* offs, int count) {
     const int g = (int)blockIdx.x;
     const int i = batch_find(offs, count, g);
     cgs_body<R, MODE>(args[i], g - offs[i]);
 }
 
-__global__ __launch_bounds__(256) void k_finish(StreamArgs a) { finish_body(a); }
+__global__ __launch_bounds__(kStreamThreads) void k_finish(StreamArgs a) { finish_body(a); }
 // one workgroup per instance
-__global__ __launch_bounds__(256) void k_finish_batch(const StreamArgs* args) { finish_body(args[blockIdx.x]); }
+__global__ __launch_bounds__(kStreamThreads) void k_finish_batch(const StreamArgs* args) { finish_body(args[blockIdx.x]); }
 
 // ---------------------------------------------------------------------------
 // host-side launchers (declared in fnls_launch.h)
@@ -1028,6 +1052,7 @@ static hipError_t dispatch_pass(const PassVariant& v, const PassArgs& a, int blo
     FNLS_PASS_CASE(R, IN_PLAIN, DST, Z_NONE, OUT_LINE, FIN_WRITE)
     FNLS_PASS_CASE(R, IN_BASIS, DST, Z_NONE, OUT_LINE, FIN_WRITE)
     FNLS_PASS_CASE(R, IN_PLAIN, DDD, Z_NONE, OUT_LINE, FIN_WRITE)
+    FNLS_PASS_CASE(R, IN_BASIS, DDD, Z_NONE, OUT_LINE, FIN_WRITE)
     // last sine transform of the preconditioner (d >= 2)
     FNLS_PASS_CASE(R, IN_PLAIN, LASTDST, Z_NONE, OUT_LINE, FIN_WRITE)
     FNLS_PASS_CASE(R, IN_PLAIN, LASTDST_T, Z_WRITE, OUT_ACC_FIRST, FIN_WRITE)
