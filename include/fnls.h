@@ -94,7 +94,11 @@ typedef struct {
     int fixed_iters;   /* > 0: run exactly this many iterations, no tolerance test (FP64) */
     int lookahead;     /* iterations enqueued ahead of the host's convergence check
                           (0 = synchronise every iteration; default 1)                   */
-    int reserved[4];
+    int graph;         /* batches (fnls_batch_solve / fnls_batch_step): 1 = enqueue every
+                          Arnoldi iteration of all instances as one replay of a captured
+                          hipGraph (see fnls_batch_create); 0 = direct launches (default).
+                          Single-instance calls ignore it                                */
+    int reserved[3];
 } fnls_opts;
 
 /* Result of a solve.  relres_hist[k] is the GMRES estimate |g_{k+1}|/||b||
@@ -215,15 +219,32 @@ int fnls_first_step_backward(fnls_ctx *ctx, const fnls_c128 *u0, const fnls_c128
 typedef struct fnls_batch fnls_batch;
 
 /* Bytes of caller-owned device workspace for a batch of `count` instances
- * (argument staging); 0 for count outside [1, 4096]. */
+ * (a ring for argument staging, then the argument tables of up to 4 cached
+ * iteration graphs); 0 for count outside [1, 4096]. */
 size_t fnls_batch_workspace_bytes(int count);
 
 /* Create a batch over ctxs[0..count-1] (host array of contexts).  The
  * workspace (device, 256-byte aligned) must stay valid for the batch's
  * life.  FNLS_ERR_STATE if a context is not assembled, FNLS_ERR_INVALID_ARG
- * for mismatched or unsupported contexts. */
+ * for mismatched or unsupported contexts.
+ *
+ * The launches of one Arnoldi iteration read the iteration index from each
+ * instance's GMRES state, so one argument table serves every iteration of a
+ * GMRES cycle.  With opts->graph = 1 those launches are captured (on a
+ * stream of the batch's own that executes nothing) into a hipGraph, which is
+ * then launched once per iteration on the contexts' stream.  Up to 4 graphs
+ * stay cached, keyed by the argument table and the launch shapes, so that
+ * repeated steps with the same vectors replay them without a new capture; a
+ * different vector set, a converged instance dropping out or a changed
+ * omega captures a new one (least recently used slot).  The graphs hold
+ * kernel nodes only. */
 int fnls_batch_create(fnls_batch **out, fnls_ctx *const *ctxs, int count, void *workspace, size_t bytes);
+/* Waits for the stream, then releases the graphs, events and staging memory. */
 void fnls_batch_destroy(fnls_batch *batch);
+
+/* Counters of graph mode since the batch was created: graphs captured and
+ * graph launches (one per Arnoldi iteration of the batch). */
+int fnls_batch_graph_stats(const fnls_batch *batch, long long *captures, long long *replays);
 
 /* f1 -- Solve A_k x_k = b_k for every instance k (host arrays of device
  * vectors) with each instance's last precond_setup; same options for all

@@ -1136,6 +1136,7 @@ static int resolve_opts(fnls_ctx* c, const fnls_opts* in, fnls_opts* o) {
     }
     if (o->fixed_iters < 0) return set_err(c, FNLS_ERR_INVALID_ARG, "fixed_iters must be >= 0");
     if (o->lookahead < 0 || o->lookahead > kEvents - 2) return set_err(c, FNLS_ERR_INVALID_ARG, "lookahead out of range");
+    if (o->graph != 0 && o->graph != 1) return set_err(c, FNLS_ERR_INVALID_ARG, "graph must be 0 or 1");
     return FNLS_OK;
 }
 
@@ -1412,11 +1413,24 @@ int fnls_set_pass_config(fnls_ctx* c, int precision, int strided, int rmax, int 
 // (G = m / 4 threads per line, 1024 / G lines), so one launch shape serves
 // all line lengths; the workgroups of instance i form one block range of the
 // launch.  Per-launch argument arrays are staged through a pinned ring into
-// the caller's batch workspace with one copy per iteration.
+// the caller's batch workspace.  The launches of one Arnoldi iteration take
+// the iteration index from each instance's GMRES state, so one argument
+// table serves a whole cycle; in graph mode those launches are captured once
+// into a hipGraph that is replayed for every iteration (and every later
+// cycle or call with the same arguments).
 // ---------------------------------------------------------------------------
 constexpr int kBatchThreads = 1024;
 constexpr int kMaxBatch = 4096;
 constexpr size_t kBatchRingMin = (size_t)16 << 20;
+constexpr int kGraphSlots = 4;        // cached iteration graphs per batch
+constexpr int kMaxIterLaunches = 12;  // launches of one Arnoldi iteration (d <= 3)
+
+struct GraphSlot {
+    std::vector<char> key;            // argument table + launch shapes it was captured with
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ex = nullptr;
+    unsigned long long used = 0;      // last use (LRU replacement)
+};
 
 struct fnls_batch {
     int count = 0;
@@ -1429,6 +1443,14 @@ struct fnls_batch {
     size_t ring_bytes = 0;
     size_t off = 0;
     hipEvent_t ev[kEvents] = {};
+    // graph mode: argument tables of the cached graphs (caller's workspace,
+    // after the ring), a stream used only for capturing, the cache
+    char* dgraph = nullptr;
+    size_t slot_bytes = 0;
+    hipStream_t cap = nullptr;
+    GraphSlot gs[kGraphSlots];
+    unsigned long long tick = 0;
+    long long captures = 0, replays = 0;
     std::string err;
 };
 
@@ -1453,6 +1475,13 @@ int berr(fnls_batch* B, int code, const char* fmt, ...) {
     } while (0)
 
 size_t batch_ring_bytes(int count) { return std::max(kBatchRingMin, (size_t)count * 64 * 1024); }
+// Upper bound of one iteration's argument table (every launch: count argument
+// blocks and count + 1 block offsets, each array 256-byte aligned).
+size_t batch_slot_bytes(int count) {
+    const size_t args = std::max(sizeof(PassArgs), sizeof(StreamArgs));
+    return (size_t)kMaxIterLaunches * (align_up((size_t)count * args) + align_up((size_t)(count + 1) * sizeof(int)));
+}
+size_t batch_total_bytes(int count) { return batch_ring_bytes(count) + (size_t)kGraphSlots * batch_slot_bytes(count); }
 
 // Geometry of a pass in a batched launch: radix 4, G * L = 1024.
 Geo batch_geo(int d, int n, int axis, bool fp64) {
@@ -1540,8 +1569,8 @@ struct Step {
     }
 };
 
-int run_step(fnls_batch* B, Step& st) {
-    Blob blob;
+// Lay out the argument arrays of every launch of `st` in one blob.
+void build_blob(Step& st, Blob& blob) {
     for (auto& p : st.passes) {
         p.a_off = blob.add(p.args);
         p.o_off = blob.add(p.offs);
@@ -1550,36 +1579,150 @@ int run_step(fnls_batch* B, Step& st) {
         s.a_off = blob.add(s.args);
         s.o_off = blob.add(s.offs);
     }
-    char* base = nullptr;
-    int rc = stage(B, blob, &base);
-    if (rc != FNLS_OK) return rc;
+}
+
+// Enqueue the launches of `st` on stream `s`, argument arrays at device
+// address `base` (laid out by build_blob).  attr_only: only raise the dynamic
+// LDS limits of the pass kernels (no launch), as a graph capture needs.
+int launch_step(fnls_batch* B, const Step& st, char* base, hipStream_t s_, bool attr_only = false) {
     for (int o : st.order) {
-        hipError_t e;
+        hipError_t e = hipSuccess;
         if (o >= 0) {
             const PassLaunch& p = st.passes[o];
             const int count = (int)p.args.size();
             if (count == 0) continue;
             if (p.lds > B->ctx[0]->max_dyn_lds) return berr(B, FNLS_ERR_INVALID_ARG, "batch pass needs %zu B of LDS", p.lds);
-            e = launch_pass_batch(p.fp64, p.v, reinterpret_cast<const PassArgs*>(base + p.a_off),
+            e = launch_pass_batch(p.fp64, p.v, attr_only ? nullptr : reinterpret_cast<const PassArgs*>(base + p.a_off),
                                   reinterpret_cast<const int*>(base + p.o_off), count, p.offs.back(), p.lds,
-                                  kBatchThreads, B->stream);
-        } else {
+                                  kBatchThreads, s_);
+        } else if (!attr_only) {
             const StreamLaunch& s = st.streams[-o - 1];
             const int count = (int)s.args.size();
             if (count == 0) continue;
             const StreamArgs* a = reinterpret_cast<const StreamArgs*>(base + s.a_off);
             const int* offs = reinterpret_cast<const int*>(base + s.o_off);
             switch (s.kind) {
-                case 0: e = launch_cgs_batch(s.fp64, s.mode, a, offs, count, s.offs.back(), B->stream); break;
-                case 1: e = launch_zupdate_batch(s.fp64, a, offs, count, s.offs.back(), B->stream); break;
-                case 2: e = launch_prepare_batch(a, offs, count, s.offs.back(), B->stream); break;
-                case 3: e = launch_precond_setup_batch(a, offs, count, s.offs.back(), B->stream); break;
-                default: e = launch_finish_batch(a, count, B->stream); break;
+                case 0: e = launch_cgs_batch(s.fp64, s.mode, a, offs, count, s.offs.back(), s_); break;
+                case 1: e = launch_zupdate_batch(s.fp64, a, offs, count, s.offs.back(), s_); break;
+                case 2: e = launch_prepare_batch(a, offs, count, s.offs.back(), s_); break;
+                case 3: e = launch_precond_setup_batch(a, offs, count, s.offs.back(), s_); break;
+                default: e = launch_finish_batch(a, count, s_); break;
             }
         }
         if (e != hipSuccess) return berr(B, FNLS_ERR_HIP, "batched launch failed: %s", hipGetErrorString(e));
     }
     return FNLS_OK;
+}
+
+// Stage and enqueue the launches of `st` on the batch stream.
+int run_step(fnls_batch* B, Step& st) {
+    Blob blob;
+    build_blob(st, blob);
+    char* base = nullptr;
+    int rc = stage(B, blob, &base);
+    if (rc != FNLS_OK) return rc;
+    return launch_step(B, st, base, B->stream);
+}
+
+// The launches of one Arnoldi iteration, ready to be enqueued once per
+// iteration: either a staged argument table (eager launches) or a graph.
+struct IterLaunch {
+    Step st;
+    char* base = nullptr;
+    hipGraphExec_t ex = nullptr;
+};
+
+// Cache key of an iteration graph: the argument table and every launch shape.
+std::vector<char> graph_key(const Step& st, const Blob& blob) {
+    std::vector<int> sig;
+    for (int o : st.order) {
+        sig.push_back(o);
+        if (o >= 0) {
+            const PassLaunch& p = st.passes[o];
+            sig.insert(sig.end(), {p.v.inm, p.v.ops, p.v.zm, p.v.outm, p.v.fin, p.v.rmax, p.fp64,
+                                   (int)p.args.size(), p.offs.back(), (int)p.lds});
+        } else {
+            const StreamLaunch& s = st.streams[-o - 1];
+            sig.insert(sig.end(), {s.kind, s.fp64, s.mode, (int)s.args.size(), s.offs.back()});
+        }
+    }
+    std::vector<char> key(blob.data);
+    const char* sp = reinterpret_cast<const char*>(sig.data());
+    key.insert(key.end(), sp, sp + sig.size() * sizeof(int));
+    return key;
+}
+
+void drop_graph(GraphSlot& g) {
+    if (g.ex) (void)hipGraphExecDestroy(g.ex);
+    if (g.g) (void)hipGraphDestroy(g.g);
+    g.ex = nullptr;
+    g.g = nullptr;
+    g.key.clear();
+    g.used = 0;
+}
+
+// Prepare `it` (built by batch_arnoldi) for enqueueing.  Eager: stage its
+// argument table in the ring.  Graph: find the cached graph of the same
+// table and shapes, or copy the table into the least recently used slot and
+// capture the launches (on the capture stream, which runs nothing) into a
+// new graph.
+int prepare_iteration(fnls_batch* B, IterLaunch& it, bool graph) {
+    Blob blob;
+    build_blob(it.st, blob);
+    if (!graph) return stage(B, blob, &it.base);
+    const size_t nbytes = align_up(blob.data.size());
+    if (nbytes > B->slot_bytes)
+        return berr(B, FNLS_ERR_WORKSPACE, "iteration argument table (%zu B) exceeds a graph slot", nbytes);
+    std::vector<char> key = graph_key(it.st, blob);
+    int slot = 0;
+    for (int i = 0; i < kGraphSlots; ++i) {
+        if (B->gs[i].ex && B->gs[i].key == key) {
+            B->gs[i].used = ++B->tick;
+            it.ex = B->gs[i].ex;
+            return FNLS_OK;
+        }
+        if (B->gs[i].used < B->gs[slot].used) slot = i;
+    }
+    GraphSlot& g = B->gs[slot];
+    drop_graph(g);
+    char* dslot = B->dgraph + (size_t)slot * B->slot_bytes;
+    // the table goes through the ring (stream-ordered after every earlier
+    // launch, so no graph still reading this slot is overwritten)
+    char* staged = nullptr;
+    int rc = stage(B, blob, &staged);
+    if (rc != FNLS_OK) return rc;
+    BHIPCHK(B, hipMemcpyAsync(dslot, staged, blob.data.size(), hipMemcpyDeviceToDevice, B->stream));
+    if ((rc = launch_step(B, it.st, dslot, B->cap, true)) != FNLS_OK) return rc;
+    BHIPCHK(B, hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
+    rc = launch_step(B, it.st, dslot, B->cap);
+    hipGraph_t graph_ = nullptr;
+    const hipError_t e = hipStreamEndCapture(B->cap, &graph_);
+    if (rc != FNLS_OK || e != hipSuccess) {
+        if (graph_) (void)hipGraphDestroy(graph_);
+        return rc != FNLS_OK ? rc : berr(B, FNLS_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
+    }
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&ex, graph_, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+        (void)hipGraphDestroy(graph_);
+        return berr(B, FNLS_ERR_HIP, "graph instantiation failed: %s", hipGetErrorString(ei));
+    }
+    g.g = graph_;
+    g.ex = ex;
+    g.key.swap(key);
+    g.used = ++B->tick;
+    ++B->captures;
+    it.ex = ex;
+    return FNLS_OK;
+}
+
+int launch_iteration(fnls_batch* B, IterLaunch& it) {
+    if (it.ex) {
+        BHIPCHK(B, hipGraphLaunch(it.ex, B->stream));
+        ++B->replays;
+        return FNLS_OK;
+    }
+    return launch_step(B, it.st, it.base, B->stream);
 }
 
 StreamArgs stream_base(fnls_ctx* c) {
@@ -1647,12 +1790,12 @@ void add_matvec(Step& st, std::vector<Inst*>& live, const double2* const* xs, do
     }
 }
 
-// One Arnoldi step j of every live instance (same pass sequence as the
-// single-instance path for d >= 2).
-int batch_arnoldi(fnls_batch* B, std::vector<Inst*>& live, bool fp64, int j) {
+// The launches of one Arnoldi step of every live instance (the pass sequence
+// of the single-instance path for d >= 2, with the basis scale in the first
+// pass and a standalone Givens step).  The kernels read the iteration index j
+// from each instance's state, so `st` serves every iteration of a cycle.
+int batch_arnoldi(fnls_batch* B, std::vector<Inst*>& live, bool fp64, Step& st) {
     const int d = B->d;
-    const size_t esz = fp64 ? 16 : 8;
-    Step st;
     std::vector<void*> cur(live.size());
     int pp = 0;
     auto front = [&](int ax, int ops, bool first_pass) {
@@ -1664,11 +1807,10 @@ int batch_arnoldi(fnls_batch* B, std::vector<Inst*>& live, bool fp64, int j) {
             Bufs& b = live[k]->bf;
             Geo g = batch_geo(d, c->n, ax, fp64);
             PassArgs a = base_args(c, fp64, ax, g);
-            void* vj = (j == 0) ? b.v0 : (void*)((char*)b.vbase + (size_t)(j - 1) * c->N * esz);
-            a.in = first_pass ? vj : cur[k];
+            a.in = first_pass ? nullptr : cur[k];   // IN_BASIS: basis vector j
             a.v0 = b.v0;
             a.vbase = b.vbase;
-            a.basis_j = j;
+            a.dev_j = 1;
             a.out = (pp == 0) ? b.t1 : b.t2;
             a.check_active = 1;
             cur[k] = a.out;
@@ -1695,7 +1837,9 @@ int batch_arnoldi(fnls_batch* B, std::vector<Inst*>& live, bool fp64, int j) {
             Geo g = batch_geo(d, c->n, d - 1, fp64);
             PassArgs a = base_args(c, fp64, d - 1, g);
             a.in = cur[k];
-            a.zout = (char*)b.zbase + (size_t)j * c->N * esz;
+            a.zout = b.zbase;   // + j N
+            a.jz = c->N;
+            a.dev_j = 1;
             a.out = b.acc;
             a.cD = 1.0;
             a.ci = 1.0;
@@ -1715,14 +1859,16 @@ int batch_arnoldi(fnls_batch* B, std::vector<Inst*>& live, bool fp64, int j) {
             Bufs& b = live[k]->bf;
             Geo g = batch_geo(d, c->n, ax, fp64);
             PassArgs a = base_args(c, fp64, ax, g);
-            a.in = (char*)b.zbase + (size_t)j * c->N * esz;
+            a.in = b.zbase;   // z_j
+            a.jin = c->N;
             a.acc_in = b.acc;
             a.cT = -1.0;
             a.check_active = 1;
-            a.out = last ? (void*)((char*)b.vbase + (size_t)j * c->N * esz) : b.acc;
+            a.out = last ? b.vbase : b.acc;   // w = basis vector j + 1 at vbase + j N
+            a.jout = last ? c->N : 0;
             a.v0 = b.v0;
             a.vbase = b.vbase;
-            a.basis_j = j;
+            a.dev_j = 1;
             p.add(a, g);
         }
         st.pass(std::move(p));
@@ -1739,10 +1885,11 @@ int batch_arnoldi(fnls_batch* B, std::vector<Inst*>& live, bool fp64, int j) {
         fnls_ctx* c = live[k]->c;
         Bufs& b = live[k]->bf;
         StreamArgs s = stream_base(c);
-        s.w = (char*)b.vbase + (size_t)j * c->N * esz;
+        s.w = b.vbase;   // + j N
+        s.jw = c->N;
+        s.dev_j = 1;
         s.v0 = b.v0;
         s.vbase = b.vbase;
-        s.nv = j + 1;
         s.check_active = 1;
         const int sb = stream_blocks(c->N);
         const int nb0 = batch_geo(d, c->n, 0, fp64).blocks;
@@ -1756,15 +1903,17 @@ int batch_arnoldi(fnls_batch* B, std::vector<Inst*>& live, bool fp64, int j) {
         s.pin_nb = sb;
         s.pout = c->at<double2>(c->lay.p3);
         u1.add(s, sb);
-        s.pin = c->at<double2>(c->lay.p3);
-        s.pin_nb = sb;
-        s.mode = 1;
-        gv.add(s, 1);
+        StreamArgs f = stream_base(c);
+        f.pin = c->at<double2>(c->lay.p3);
+        f.pin_nb = sb;
+        f.check_active = 1;
+        f.mode = 1;
+        gv.add(f, 1);
     }
     st.strm(std::move(u0));
     st.strm(std::move(u1));
     st.strm(std::move(gv));
-    return run_step(B, st);
+    return FNLS_OK;
 }
 
 // End of a cycle: x (+)= sum y_k z_k, FP64 residual and the decision.
@@ -1866,10 +2015,14 @@ int batch_solve_impl(fnls_batch* B, std::vector<Inst>& inst, const fnls_opts* o,
     while (!live.empty()) {
         for (Inst* I : live)
             I->bf = bufs(I->c, fp64, first ? (const void*)I->b : (const void*)I->c->at<double2>(I->c->lay.r64));
+        IterLaunch it;
+        int rc = batch_arnoldi(B, live, fp64, it.st);
+        if (rc == FNLS_OK) rc = prepare_iteration(B, it, o->graph != 0);
+        if (rc != FNLS_OK) return rc;
         int issued = 0, waited = 0;
         while (true) {
             while (issued < o->restart && issued <= waited + lookahead) {
-                int rc = batch_arnoldi(B, live, fp64, issued);
+                rc = launch_iteration(B, it);
                 if (rc != FNLS_OK) return rc;
                 BHIPCHK(B, hipEventRecord(B->ev[issued % kEvents], B->stream));
                 ++issued;
@@ -1883,7 +2036,7 @@ int batch_solve_impl(fnls_batch* B, std::vector<Inst>& inst, const fnls_opts* o,
             }
             if (all || waited >= o->restart) break;
         }
-        int rc = batch_cycle_final(B, live, fp64, first);
+        rc = batch_cycle_final(B, live, fp64, first);
         if (rc != FNLS_OK) return rc;
         first = 0;
         BHIPCHK(B, hipStreamSynchronize(B->stream));
@@ -1925,14 +2078,14 @@ extern "C" {
 
 size_t fnls_batch_workspace_bytes(int count) {
     if (count < 1 || count > kMaxBatch) return 0;
-    return batch_ring_bytes(count);
+    return batch_total_bytes(count);
 }
 
 int fnls_batch_create(fnls_batch** out, fnls_ctx* const* ctxs, int count, void* workspace, size_t bytes) {
     if (!out) return FNLS_ERR_INVALID_ARG;
     *out = nullptr;
     if (!ctxs || count < 1 || count > kMaxBatch) return FNLS_ERR_INVALID_ARG;
-    if (!workspace || bytes < batch_ring_bytes(count) || ((uintptr_t)workspace % kAlign) != 0)
+    if (!workspace || bytes < batch_total_bytes(count) || ((uintptr_t)workspace % kAlign) != 0)
         return FNLS_ERR_WORKSPACE;
     for (int i = 0; i < count; ++i) {
         fnls_ctx* c = ctxs[i];
@@ -1958,14 +2111,22 @@ int fnls_batch_create(fnls_batch** out, fnls_ctx* const* ctxs, int count, void* 
     B->d = ctxs[0]->d;
     B->dring = reinterpret_cast<char*>(workspace);
     B->ring_bytes = batch_ring_bytes(count);
+    B->dgraph = B->dring + B->ring_bytes;
+    B->slot_bytes = batch_slot_bytes(count);
     if (hipSetDevice(B->device) != hipSuccess ||
         hipHostMalloc((void**)&B->hring, B->ring_bytes, hipHostMallocDefault) != hipSuccess) {
+        delete B;
+        return FNLS_ERR_HIP;
+    }
+    if (hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipHostFree(B->hring);
         delete B;
         return FNLS_ERR_HIP;
     }
     for (int i = 0; i < kEvents; ++i) {
         if (hipEventCreateWithFlags(&B->ev[i], hipEventDisableTiming) != hipSuccess) {
             for (int k = 0; k < i; ++k) (void)hipEventDestroy(B->ev[k]);
+            (void)hipStreamDestroy(B->cap);
             (void)hipHostFree(B->hring);
             delete B;
             return FNLS_ERR_HIP;
@@ -1981,8 +2142,17 @@ void fnls_batch_destroy(fnls_batch* B) {
     (void)hipStreamSynchronize(B->stream);
     for (int i = 0; i < kEvents; ++i)
         if (B->ev[i]) (void)hipEventDestroy(B->ev[i]);
+    for (int i = 0; i < kGraphSlots; ++i) drop_graph(B->gs[i]);
+    if (B->cap) (void)hipStreamDestroy(B->cap);
     if (B->hring) (void)hipHostFree(B->hring);
     delete B;
+}
+
+int fnls_batch_graph_stats(const fnls_batch* B, long long* captures, long long* replays) {
+    if (!B) return FNLS_ERR_INVALID_ARG;
+    if (captures) *captures = B->captures;
+    if (replays) *replays = B->replays;
+    return FNLS_OK;
 }
 
 int fnls_batch_solve(fnls_batch* B, const fnls_c128* const* bs, fnls_c128* const* xs, const fnls_opts* opts,

@@ -120,6 +120,12 @@ struct PassArgs {
     int gfuse;
     const double2* gpin;
     int gpin_nb, gpin_stride;
+    // batched launches: with dev_j set the iteration index j is read from
+    // st->j when the kernel starts (one argument table serves every Arnoldi
+    // iteration of a cycle).  Then basis_j = j; IN_BASIS reads basis vector j;
+    // in / out / zout are bases advanced by j * jin / jout / jz elements.
+    int dev_j;
+    long long jin, jout, jz;
 };
 
 struct StreamArgs {
@@ -148,6 +154,10 @@ struct StreamArgs {
     int mode;             // k_finish: FinishKind; k_zupdate: 1 = first correction (x = 0 before)
     int ir;               // k_finish residual decision: 1 = refinement step of FP32-IR
     double2* x64;         // k_zupdate: the iterate
+    // batched CGS launches: with dev_j set, j = st->j when the kernel starts,
+    // nv = j + 1 and w is advanced by j * jw elements
+    int dev_j;
+    long long jw;
 };
 
 // Reverse mode of one step: gradient accumulation after the adjoint solve.

@@ -260,7 +260,8 @@ template <> struct PassThreads<16> { static constexpr int v = 256; };
 
 // LGM > 0: the line length m = 2^LGM is a compile-time constant (the host
 // launches this specialisation only when a.lgm == LGM); 0: generic.
-template <typename R, int RMAX, int LGM, int INM, int OPS, int ZM, int OUTM, int FIN>
+// BJ: the launch may take its iteration index from the GMRES state (a.dev_j).
+template <typename R, int RMAX, int LGM, int INM, int OPS, int ZM, int OUTM, int FIN, bool BJ = false>
 __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
     using C = cplx<R>;
     constexpr int kMaxEptLine = RMAX;
@@ -287,6 +288,22 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
         __syncthreads();
         if (threadIdx.x == 0) arnoldi_finish(st, a.hs, s_tot[0].x, j, s_col, s_cs, s_sn);
         return;
+    }
+
+    // operands that depend on the Arnoldi iteration index
+    const void* in_p = a.in;
+    void* out_p = a.out;
+    void* zout_p = a.zout;
+    int basis_j = a.basis_j;
+    if (BJ && a.dev_j) {
+        const int j = a.st->j;
+        basis_j = j;
+        if (INM == IN_BASIS)
+            in_p = (j == 0) ? a.v0 : (const void*)(reinterpret_cast<const C*>(a.vbase) + (long long)(j - 1) * a.N);
+        else if (in_p)
+            in_p = reinterpret_cast<const C*>(in_p) + (long long)j * a.jin;
+        if (out_p) out_p = reinterpret_cast<C*>(out_p) + (long long)j * a.jout;
+        if (zout_p) zout_p = reinterpret_cast<C*>(zout_p) + (long long)j * a.jz;
     }
 
     const int lgm = LGM ? LGM : a.lgm;
@@ -363,7 +380,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
     // ---- load phase
     {
         double sig = 1.0;
-        if (INM == IN_BASIS) sig = a.st->sigma[a.basis_j];
+        if (INM == IN_BASIS) sig = a.st->sigma[basis_j];
         int nvc = 0;
         if (INM == IN_COMBO) nvc = a.st->k;
 #pragma unroll
@@ -377,9 +394,9 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
                 if (base >= 0) {
                     const long long gi = base + (long long)j * stride;
                     if (INM == IN_PLAIN) {
-                        v = ld<R>(a.in, gi);
+                        v = ld<R>(in_p, gi);
                     } else if (INM == IN_BASIS) {
-                        const C t = ld<R>(a.in, gi);
+                        const C t = ld<R>(in_p, gi);
                         v = cm<R>(static_cast<R>(t.x * sig), static_cast<R>(t.y * sig));
                     } else {
                         double sx = 0.0, sy = 0.0;
@@ -467,7 +484,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
                     const R fi = -static_cast<R>(2.0 * om) * op1 / den;
                     z = cm<R>(z.x * fr - z.y * fi, z.x * fi + z.y * fr);
                 }
-                if (ZM == Z_WRITE) stc<R>(a.zout, gi, z);
+                if (ZM == Z_WRITE) stc<R>(zout_p, gi, z);
                 if (ZM == Z_XSET || ZM == Z_XADD) {
                     double2 xn = dmk((double)z.x, (double)z.y);
                     if (ZM == Z_XADD && !a.first_cycle) {
@@ -478,7 +495,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
                     a.x64[gi] = xn;
                     z = cm<R>(static_cast<R>(xn.x), static_cast<R>(xn.y));
                 }
-                if (!kToep && FIN == FIN_WRITE && a.out) stc<R>(a.out, gi, z);
+                if (!kToep && FIN == FIN_WRITE && out_p) stc<R>(out_p, gi, z);
             }
             if (kKeepZ) zreg[q] = z;
             if (kToep) lds[(size_t)l * LS + pad(j + 1)] = z;
@@ -537,9 +554,9 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
                 o = cm<R>(acc.x + cT * tz.x, acc.y + cT * tz.y);
             }
             if (FIN == FIN_WRITE) {
-                if (a.out) stc<R>(a.out, gi, o);
+                if (out_p) stc<R>(out_p, gi, o);
             } else if (FIN == FIN_WDOTS) {
-                stc<R>(a.out, gi, o);
+                stc<R>(out_p, gi, o);
                 oreg[q] = o;
                 nrm += (double)o.x * o.x + (double)o.y * o.y;
             } else {
@@ -562,7 +579,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
     const int lane = tid & 63, wave = tid >> 6;
     int nv = 1;
     if (FIN == FIN_WDOTS) {
-        const int nb = a.basis_j + 1;
+        const int nb = basis_j + 1;
         nv = nb + 1;
         // global index of each element (-1: none) and double-buffered basis
         // loads: vector i + 1 is in flight while vector i is reduced
@@ -627,7 +644,7 @@ __global__ __launch_bounds__(PassThreads<RMAX>::v) void k_pass_batch(const PassA
                                                                       int count) {
     const int g = xcd_block((int)blockIdx.x, (int)gridDim.x);
     const int i = batch_find(offs, count, g);
-    pass_body<R, RMAX, 0, INM, OPS, ZM, OUTM, FIN>(args[i], g - offs[i]);
+    pass_body<R, RMAX, 0, INM, OPS, ZM, OUTM, FIN, true>(args[i], g - offs[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -757,7 +774,7 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs a) {
 // are complex<R>; arithmetic in FP64.  Each thread owns kEpt elements
 // (stride = workgroup size: every load instruction of a wavefront is
 // contiguous) and issues all kEpt loads of a vector at once.
-template <typename R, int MODE>
+template <typename R, int MODE, bool BJ = false>
 __device__ __forceinline__ void cgs_body(const StreamArgs& a, int blk) {
     using C = cplx<R>;
     __shared__ double2 s_red[(kMaxRestart + 2) * kMaxWaves];
@@ -765,7 +782,13 @@ __device__ __forceinline__ void cgs_body(const StreamArgs& a, int blk) {
     __shared__ double2 s_coef[kMaxRestart + 1];
     if (a.check_active && a.st->active == 0) return;
     const long long N = a.N;
-    const int nv = a.nv;
+    int nv = a.nv;
+    void* wp = a.w;
+    if (BJ && a.dev_j) {
+        const int j = a.st->j;
+        nv = j + 1;
+        wp = reinterpret_cast<C*>(wp) + (long long)j * a.jw;
+    }
     GmresState* st = a.st;
     reduce_partials(a.pin, a.pin_stride, a.pin_nb, MODE == 0 ? nv + 1 : nv, s_tot, s_red);
     if (threadIdx.x < nv) {
@@ -790,7 +813,7 @@ __device__ __forceinline__ void cgs_body(const StreamArgs& a, int blk) {
 #pragma unroll
     for (int q = 0; q < kEpt; ++q) {
         const long long i = base + (long long)q * kStreamThreads;
-        const C w = i < N ? ld<R>(a.w, i) : czero<C>();
+        const C w = i < N ? ld<R>(wp, i) : czero<C>();
         wx[q] = w.x;
         wy[q] = w.y;
     }
@@ -816,7 +839,7 @@ __device__ __forceinline__ void cgs_body(const StreamArgs& a, int blk) {
     for (int q = 0; q < kEpt; ++q) {
         const long long i = base + (long long)q * kStreamThreads;
         wr[q] = cm<R>(static_cast<R>(wx[q]), static_cast<R>(wy[q]));
-        if (i < N) stc<R>(a.w, i, wr[q]);
+        if (i < N) stc<R>(wp, i, wr[q]);
         else wr[q] = czero<C>();
         nrm += (double)wr[q].x * wr[q].x + (double)wr[q].y * wr[q].y;
     }
@@ -968,7 +991,7 @@ template <typename R, int MODE>
 __global__ __launch_bounds__(kStreamThreads) void k_cgs_batch(const StreamArgs* args, const int* offs, int count) {
     const int g = (int)blockIdx.x;
     const int i = batch_find(offs, count, g);
-    cgs_body<R, MODE>(args[i], g - offs[i]);
+    cgs_body<R, MODE, true>(args[i], g - offs[i]);
 }
 
 __global__ __launch_bounds__(kStreamThreads) void k_finish(StreamArgs a) { finish_body(a); }
@@ -1087,6 +1110,7 @@ static hipError_t launch_pass_batch_t(const PassArgs* args, const int* offs, int
         if (e != hipSuccess) return e;
         granted = lds;
     }
+    if (!args) return hipSuccess;   // attribute only (before a graph capture)
     if (threads != PassThreads<4>::v) return hipErrorInvalidConfiguration;
     return launch_k(kern, dim3(blocks), dim3(threads), lds, s, nullptr, args, offs, count);
 }

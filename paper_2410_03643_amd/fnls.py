@@ -39,7 +39,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("maxit", ctypes.c_int),
                 ("precision", ctypes.c_int), ("inner_tol", ctypes.c_double),
                 ("max_outer", ctypes.c_int), ("fixed_iters", ctypes.c_int),
-                ("lookahead", ctypes.c_int), ("reserved", ctypes.c_int * 4)]
+                ("lookahead", ctypes.c_int), ("graph", ctypes.c_int), ("reserved", ctypes.c_int * 3)]
 
 
 class Info(ctypes.Structure):
@@ -128,6 +128,8 @@ def lib() -> ctypes.CDLL:
     L.fnls_batch_step.restype = ci
     L.fnls_batch_last_error.argtypes = [vp]
     L.fnls_batch_last_error.restype = ctypes.c_char_p
+    L.fnls_batch_graph_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)]
+    L.fnls_batch_graph_stats.restype = ci
     _lib = L
     return L
 
@@ -382,22 +384,30 @@ class Batch:
         return (ctypes.c_void_p * n)(*[s._vec(t, name) for s, t in zip(self.solvers, ts)])
 
     def solve(self, bs, outs=None, *, tol=1e-10, restart=30, maxit=2000, precision="fp64", inner_tol=1e-5,
-              max_outer=20, lookahead=1):
+              max_outer=20, lookahead=1, graph=False):
         xs = [s._out() for s in self.solvers] if outs is None else outs
         o = Solver._opts(tol, restart, maxit, precision, inner_tol, max_outer, 0, lookahead)
+        o.graph = 1 if graph else 0
         infos = (Info * len(self.solvers))()
         self._check(lib().fnls_batch_solve(self._b, self._ptrs(bs, "b"), self._ptrs(xs, "x"), ctypes.byref(o),
                                            infos))
         return xs, [Solver._info(i) for i in infos]
 
     def step(self, u_prev, u_cur, outs=None, *, tol=1e-10, restart=30, maxit=2000, precision="fp64",
-             inner_tol=1e-5, max_outer=20, lookahead=1):
+             inner_tol=1e-5, max_outer=20, lookahead=1, graph=False):
         un = [s._out() for s in self.solvers] if outs is None else outs
         o = Solver._opts(tol, restart, maxit, precision, inner_tol, max_outer, 0, lookahead)
+        o.graph = 1 if graph else 0
         infos = (Info * len(self.solvers))()
         self._check(lib().fnls_batch_step(self._b, self._ptrs(u_prev, "u_prev"), self._ptrs(u_cur, "u_cur"),
                                           self._ptrs(un, "u_next"), ctypes.byref(o), infos))
         return un, [Solver._info(i) for i in infos]
+
+    def graph_stats(self):
+        """(graphs captured, graph launches) since the batch was created."""
+        cap, rep = ctypes.c_longlong(), ctypes.c_longlong()
+        self._check(lib().fnls_batch_graph_stats(self._b, ctypes.byref(cap), ctypes.byref(rep)))
+        return cap.value, rep.value
 
     def close(self):
         if getattr(self, "_b", None) and self._b.value:

@@ -12,6 +12,11 @@ sizes advanced together with one launch per pass for all of them.
   three-level step of every instance in FP32-IR to 1e-10; every instance's
   FP64 residual below 1e-10, a sample checked by the oracle's operator; the
   batch timed against the same steps taken one instance at a time.
+* Graph mode (opts.graph = 1): each Arnoldi iteration of all instances is one
+  replay of a captured hipGraph.  Replays are checked bitwise against the
+  direct launches of the same kernels, several times over with other GPU
+  work and synchronisations in between; repeated calls with the same vectors
+  replay cached graphs without capturing again.
 """
 import time
 
@@ -139,4 +144,80 @@ def test_batched_workload_64_instances(torch_dev):
         e1 = np.linalg.norm(x - to_np(single[k])) / np.linalg.norm(to_np(single[k]))
         print("instance %d (n=%d): oracle residual %.2e, |x_batch - x_single| %.1e" % (k, p.n, res, e1), flush=True)
         assert res < TOL and e1 <= 1e-8
+    batch.close()
+
+
+def bitwise_equal(a, b):
+    import torch
+    return bool(torch.equal(torch.view_as_real(a), torch.view_as_real(b)))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_graph_mode_replays_match_direct_launches(torch_dev, precision):
+    from paper_2410_03643_amd.fnls import Batch, Solver
+    torch, dev = torch_dev
+    lo, hi, dt = -10.0, 10.0, 0.01
+    solvers, bs = [], []
+    for k, (n, alpha, rho) in enumerate(MIXED[:-1]):
+        h = (hi - lo) / (n + 1)
+        u = inputs.soliton(2, n, lo, hi, center=[0.5 * k - 1.0, 0.3], phase=0.4 * k, noise=1e-3, seed=k)
+        s = Solver(alpha, rho, 2, n, h, dt, device=dev)
+        ut = torch.from_numpy(u).to(dev)
+        s.precond_setup(ut)
+        solvers.append(s)
+        bs.append(s.rhs(ut))
+    batch = Batch(solvers)
+    ref, rinfo = batch.solve(bs, tol=TOL, precision=precision)
+    ref = [x.clone() for x in ref]
+    outs = [torch.empty_like(x) for x in ref]
+    counts = []
+    for rep in range(4):
+        for x in outs:
+            x.fill_(float("nan"))
+        _, ginfo = batch.solve(bs, outs, tol=TOL, precision=precision, graph=True)
+        torch.cuda.synchronize()
+        same = [bitwise_equal(x, r) for x, r in zip(outs, ref)]
+        its = [(a.iters, b.iters) for a, b in zip(ginfo, rinfo)]
+        counts.append(batch.graph_stats())
+        print("replay round %d: bitwise equal %s, IT (graph, direct) %s, graphs (captured, launched) %s"
+              % (rep, same, its, counts[-1]), flush=True)
+        assert all(same)
+        assert all(a.iters == b.iters and a.status == b.status for a, b in zip(ginfo, rinfo))
+        # other GPU work and a direct-launch solve between the replays
+        junk = torch.randn(1 << 20, device=dev).cumsum(0)
+        _, dinfo = batch.solve(bs, [torch.empty_like(x) for x in ref], tol=TOL, precision=precision)
+        torch.cuda.synchronize()
+        del junk
+    assert counts[0][0] >= 1 and counts[0][1] >= sum(i.iters for i in rinfo) // len(rinfo)
+    assert all(c[0] == counts[0][0] for c in counts), "repeated calls captured new graphs"
+    assert all(b[1] > a[1] for a, b in zip(counts, counts[1:]))
+    batch.close()
+
+
+def test_batched_workload_graph_mode(torch_dev):
+    from paper_2410_03643_amd.fnls import Batch, Solver
+    torch, dev = torch_dev
+    cases = inputs.batched_cases(64)
+    solvers = [Solver(p.alpha, p.rho, p.d, p.n, p.h, p.tau, device=dev) for p in cases]
+    us = [torch.from_numpy(p.u).to(dev) for p in cases]
+    batch = Batch(solvers)
+    direct = [torch.empty_like(u) for u in us]
+    graph = [torch.empty_like(u) for u in us]
+    times = {}
+    for name, outs, g in (("direct", direct, False), ("graph", graph, True), ("direct", direct, False),
+                          ("graph", graph, True)):
+        batch.step(us, us, outs, tol=TOL, precision="fp32_ir", graph=g)
+        torch.cuda.synchronize()
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            _, infos = batch.step(us, us, outs, tol=TOL, precision="fp32_ir", graph=g)
+        torch.cuda.synchronize()
+        times[name] = (time.perf_counter() - t0) / reps
+        assert all(i.status == 0 and i.relres_true < TOL for i in infos)
+    same = [bitwise_equal(a, b) for a, b in zip(direct, graph)]
+    print("64 instances, one FP32-IR step of all: direct launches %.2f ms, graph replays %.2f ms; "
+          "graphs (captured, launched) %s; bitwise equal %d / 64"
+          % (1e3 * times["direct"], 1e3 * times["graph"], batch.graph_stats(), sum(same)), flush=True)
+    assert all(same)
     batch.close()
