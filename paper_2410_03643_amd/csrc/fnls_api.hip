@@ -72,6 +72,29 @@ PassConfig default_pass_config() {
 
 int pass_threads_max(int rmax) { return rmax == 16 ? 256 : 4096 / rmax; }
 
+// LDS line layout of a pass kernel: a line buffer holds pa >= m slots and
+// consecutive lines are ls slots apart (2 pa with the Toeplitz buffer).  On
+// strided axes the lanes of a wavefront spread over L interleaved lines; the
+// element writes of one LDS write cycle (8 lanes of 16-byte values, 16 of
+// 8-byte ones, on a 128-byte bank row) stay apart when
+// ls * size = 128 / L modulo 256 / L bytes.  pa is the smallest length >= m
+// that gives that stride (m itself for a single line or when none does).
+void line_layout(int m, int L, bool fp64, bool two, int* pa, int* ls) {
+    const int elem = fp64 ? 16 : 8;
+    const int k = two ? 2 : 1;
+    int best = m;
+    if (L >= 2 && 128 / L >= elem) {
+        const int target = 128 / L / elem, mod = 256 / L / elem;   // in slots
+        for (int d = 0; d < mod; ++d)
+            if ((k * (m + d)) % mod == target) {
+                best = m + d;
+                break;
+            }
+    }
+    *pa = best;
+    *ls = k * best;
+}
+
 Geo pass_geo(int d, int n, int axis, bool fp64, size_t max_dyn_lds, const PassConfig& cfg) {
     Geo g;
     const int m = n + 1;
@@ -80,19 +103,21 @@ Geo pass_geo(int d, int n, int axis, bool fp64, size_t max_dyn_lds, const PassCo
     g.rmax = cfg.rmax[fp64 ? 1 : 0][col];
     g.G = std::max(1, m / g.rmax);
     const int tmax = pass_threads_max(g.rmax);
-    const size_t elem = fp64 ? 16 : 8;
-    // per line: buffers A and B of padded_len(m) slots; per workgroup: the W_m table
-    const size_t perline = (size_t)2 * (m + (m >> 3) + 1) * elem;
-    // quarter twiddle table (padded) + per-line base offset (8 B) and Lambda (elem/2 B)
-    const int q4 = m >= 4 ? m / 4 : 1;
-    const size_t table = (size_t)(m >= 4 ? (q4 - 1) + ((q4 - 1) >> 3) + 1 : 1) * elem;
+    // LDS of L lines with buffers A and B (line_layout), the quarter twiddle
+    // table, per-line base offset (8 B) and Lambda (elem/2 B)
+    auto lds_of = [&](int L) {
+        int pa = 0, ls = 0;
+        line_layout(m, L, fp64, true, &pa, &ls);
+        const size_t elem = fp64 ? 16 : 8;
+        return (size_t)L * ls * elem + (size_t)(m >= 4 ? m / 4 : 1) * elem + (size_t)L * (8 + elem / 2);
+    };
     const int gref = 1024 / g.rmax;
     int L = cfg.lines[fp64 ? 1 : 0][col] * std::max(1, gref / g.G);
     L = std::max(1, std::min(L, tmax / g.G));
-    while (L > 1 && (size_t)L * (perline + 8 + elem / 2) + table > max_dyn_lds) L /= 2;
+    while (L > 1 && lds_of(L) > max_dyn_lds) L /= 2;
     while (g.G * L < 64) L *= 2;   // whole wavefronts
     g.L = L;
-    g.lds = (size_t)L * perline + table + (size_t)L * (8 + elem / 2);
+    g.lds = lds_of(L);
     g.stride = ipow(n, d - 1 - axis);
     g.nlines = ipow(n, d - 1);
     g.blocks = (int)((g.nlines + L - 1) / L);
@@ -339,16 +364,20 @@ double pass_bytes(fnls_ctx* c, bool fp64, const PassVariant& v, const PassArgs& 
 // (the fused Givens workgroup stages its column there).
 size_t pass_lds(const Geo& g, int m, bool fp64, bool two_buffers) {
     const size_t elem = fp64 ? 16 : 8;
-    const size_t pa = (size_t)(m + (m >> 3) + 1) * elem;
-    const int q4 = m >= 4 ? m / 4 : 1;
-    const size_t table = (size_t)(m >= 4 ? (q4 - 1) + ((q4 - 1) >> 3) + 1 : 1) * elem;
-    const size_t lds = (size_t)g.L * (two_buffers ? 2 : 1) * pa + table + (size_t)g.L * (8 + elem / 2);
-    return std::max<size_t>(lds, 4096);
+    int pa = 0, ls = 0;
+    line_layout(m, g.L, fp64, two_buffers, &pa, &ls);
+    const size_t table = (size_t)(m >= 4 ? m / 4 : 1) * elem;
+    const size_t lds = (size_t)g.L * ls * elem + table + (size_t)g.L * (8 + elem / 2);
+    // the line buffers also hold the reduction sums at the end of the pass:
+    // (kMaxRestart + 2) complex values per wavefront
+    const size_t red = (size_t)(kMaxRestart + 2) * ((g.G * g.L + 63) / 64) * 16;
+    return std::max<size_t>(std::max(lds, red), 4096);
 }
 
 int run_pass(fnls_ctx* c, bool fp64, int axis, PassVariant v, PassArgs& a, const Geo& g) {
     v.rmax = g.rmax;
     const size_t lds = pass_lds(g, c->m, fp64, (v.ops & P_TOEP) != 0);
+    line_layout(c->m, g.L, fp64, (v.ops & P_TOEP) != 0, &a.pa, &a.ls);
     const LaunchEvents* te = c->timing ? timing_begin(c, pass_name(fp64, v, axis), pass_bytes(c, fp64, v, a)) : nullptr;
     hipError_t e = launch_pass(fp64 ? 1 : 0, v, a, g.blocks + (a.gfuse ? 1 : 0), lds, c->stream, te);
     if (e != hipSuccess) timing_failed(c, te);
@@ -1491,10 +1520,9 @@ Geo batch_geo(int d, int n, int axis, bool fp64) {
     g.G = std::max(1, m / 4);
     g.L = std::max(1, kBatchThreads / g.G);
     const size_t elem = fp64 ? 16 : 8;
-    const size_t perline = (size_t)2 * (m + (m >> 3) + 1) * elem;
-    const int q4 = m >= 4 ? m / 4 : 1;
-    const size_t table = (size_t)(m >= 4 ? (q4 - 1) + ((q4 - 1) >> 3) + 1 : 1) * elem;
-    g.lds = (size_t)g.L * perline + table + (size_t)g.L * (8 + elem / 2);
+    int pa = 0, ls = 0;
+    line_layout(m, g.L, fp64, true, &pa, &ls);   // the larger (Toeplitz) layout
+    g.lds = (size_t)g.L * ls * elem + (size_t)(m >= 4 ? m / 4 : 1) * elem + (size_t)g.L * (8 + elem / 2);
     g.stride = ipow(n, d - 1 - axis);
     g.nlines = ipow(n, d - 1);
     g.blocks = (int)((g.nlines + g.L - 1) / g.L);
@@ -1537,7 +1565,8 @@ struct PassLaunch {
     std::vector<int> offs{0};
     size_t lds = 0;
     size_t a_off = 0, o_off = 0;
-    void add(const PassArgs& a, const Geo& g) {
+    void add(PassArgs a, const Geo& g) {
+        line_layout(a.m, g.L, fp64 != 0, (v.ops & P_TOEP) != 0, &a.pa, &a.ls);
         args.push_back(a);
         offs.push_back(offs.back() + g.blocks);
         lds = std::max(lds, pass_lds(g, a.m, fp64 != 0, (v.ops & P_TOEP) != 0));

@@ -80,6 +80,7 @@ struct PassArgs {
     int G;            // threads per line in the transform phases (power of two)
     int L;            // lines per workgroup (power of two)
     int lgG, lgL;     // log2 of G and L
+    int pa, ls;       // LDS: slots of a line buffer (>= m) and line stride in slots
     unsigned magic_n; // ceil(2^32 / n) (n >= 2): e / n == umulhi(e, magic_n) for e < 2^16
     long long stride; // element stride along the axis
     long long nlines; // n^(d-1)

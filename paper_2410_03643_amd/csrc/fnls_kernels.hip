@@ -318,14 +318,15 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
     const int lt = tid & (G - 1);
     const long long stride = a.stride;
     const bool contiguous = (stride == 1);
-    const int PA = padded_len(m);   // padded slots of one line buffer
-    // line stride: buffers A and B for the Toeplitz product, A alone otherwise
+    // slots of one line buffer (>= m) and line stride (buffers A and B for
+    // the Toeplitz product, A alone otherwise), both chosen by the host
     constexpr bool kTwoBuf = (OPS & OP_TOEP) != 0;
-    const int LS = kTwoBuf ? 2 * PA : PA;
+    const int PA = a.pa;
+    const int LS = a.ls;
     // dynamic LDS: L lines | quarter twiddle table | per-line base offsets | per-line Lambda
     C* lds = reinterpret_cast<C*>(smem_raw);
-    C* twl = lds + (size_t)L * LS;                    // W_m^q at pad(q), q < max(1, m/4)
-    const int nq = m >= 4 ? pad((m >> 2) - 1) + 1 : 1;
+    C* twl = lds + (size_t)L * LS;                    // W_m^q at tw_slot(q), q < max(1, m/4)
+    const int nq = m >= 4 ? (m >> 2) : 1;
     long long* s_base = reinterpret_cast<long long*>(twl + nq);
     R* s_lamo = reinterpret_cast<R*>(s_base + L);
 
@@ -334,6 +335,12 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
     const R* Dv = reinterpret_cast<const R*>(a.D);
     const R tscale = static_cast<R>(a.tscale);
     const int E = L * n;
+    // per-thread twiddles of the compile-time plan, read while the line
+    // data loads are in flight
+    // (the passes that keep z across the Toeplitz product are short of
+    // registers: no wl there)
+    LineTw<R, RMAX, LGM, !((OPS & OP_TOEP) && OUTM == OUT_ACC_FIRST)> ltw;
+    ltw.init(tw, lt);
 
     // coalescing element map: e -> (line l, unknown j); rows are contiguous on
     // the last axis, lines are interleaved on strided axes
@@ -374,7 +381,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
         s_lamo[l] = lamo;
         lds[(size_t)l * LS] = czero<C>();   // slot 0: the Dirichlet zero
     }
-    for (int q = tid; q < (m >= 4 ? (m >> 2) : 1); q += T) twl[pad(q)] = tw[2 * q];
+    for (int q = tid; q < nq; q += T) twl[tw_slot<R>(q)] = tw[2 * q];
     __syncthreads();
 
     // ---- load phase
@@ -409,7 +416,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
                         v = cm<R>(static_cast<R>(sx), static_cast<R>(sy));
                     }
                 }
-                lds[(size_t)l * LS + pad(j + 1)] = v;
+                lds[(size_t)l * LS + j + 1] = v;
             }
         }
     }
@@ -419,20 +426,20 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
     C* B = kTwoBuf ? A + PA : A;   // B exists only for the Toeplitz product
 
     // ---- transform stages
-    if (OPS & OP_DST1) line_dst<R, RMAX, LGM>(A, B, lgm, lt, G, tw, twl);
+    if (OPS & OP_DST1) line_dst<R, RMAX, LGM>(A, B, lgm, lt, G, tw, twl, ltw);
     if (OPS & OP_DIV) {
         const R om = static_cast<R>(a.omega);
         const R lo = s_lamo[line];
         for (int k = lt + 1; k < m; k += G) {
             const R mu = lo + tscale * lam[k];
             const R den = om * om + mu * mu;
-            const C v = A[pad(k)];
+            const C v = A[k];
             // v / (om + i mu) = v (om - i mu) / den
-            A[pad(k)] = cm<R>((v.x * om + v.y * mu) / den, (v.y * om - v.x * mu) / den);
+            A[k] = cm<R>((v.x * om + v.y * mu) / den, (v.y * om - v.x * mu) / den);
         }
         __syncthreads();
     }
-    if (OPS & OP_DST2) line_dst<R, RMAX, LGM>(A, B, lgm, lt, G, tw, twl);
+    if (OPS & OP_DST2) line_dst<R, RMAX, LGM>(A, B, lgm, lt, G, tw, twl, ltw);
 
     constexpr bool kToep = (OPS & OP_TOEP) != 0;
     constexpr bool kKeepZ = kToep && (OUTM == OUT_ACC_FIRST);
@@ -472,7 +479,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
             int l, j;
             emap(e, l, j);
             const long long base = s_base[l];
-            C z = lds[(size_t)l * LS + pad(j + 1)];
+            C z = lds[(size_t)l * LS + j + 1];
             if (base >= 0) {
                 const long long gi = base + (long long)j * stride;
                 if (OPS & OP_SCALE) {
@@ -498,7 +505,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
                 if (!kToep && FIN == FIN_WRITE && out_p) stc<R>(out_p, gi, z);
             }
             if (kKeepZ) zreg[q] = z;
-            if (kToep) lds[(size_t)l * LS + pad(j + 1)] = z;
+            if (kToep) lds[(size_t)l * LS + j + 1] = z;
         }
         if (kToep) __syncthreads();
     }
@@ -506,7 +513,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
     // ---- Toeplitz product and element phase 2
     if (kToep) {
         line_toeplitz<R, RMAX, LGM>(A, B, lgm, lt, G, tw, twl, reinterpret_cast<const R*>(a.sym_e),
-                         reinterpret_cast<const R*>(a.sym_o), tscale);
+                         reinterpret_cast<const R*>(a.sym_o), tscale, ltw);
         const R cT = static_cast<R>(a.cT);
         // operands first (see element phase 1)
         constexpr bool kFirst = (OUTM == OUT_ACC_FIRST);
@@ -542,7 +549,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
             const long long gi = base + (long long)j * stride;
             const int s = j + 1;
             const C* Al = lds + (size_t)l * LS;
-            const C tz = cadd(Al[pad(s)], cmulc(Al[PA + pad(s)], tw[s]));
+            const C tz = cadd(Al[s], cmulc(Al[PA + s], tw[s]));
             C o;
             if (OUTM == OUT_ACC_FIRST) {
                 const R Dj = dq[kFirst ? q : 0];
