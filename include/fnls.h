@@ -292,11 +292,12 @@ int fnls_timing_report(fnls_ctx *ctx, fnls_kernel_stat *out, int max_entries);
 int fnls_set_pass_config(fnls_ctx *ctx, int precision, int strided, int rmax, int lines);
 
 /* Autotuner of the transform-pass schedule above, for this context's
- * operator and one precision: times `reps` solves (after one warm-up solve)
- * of the device vector b with the current preconditioner setup and default
- * options, for each candidate rmax in {4, 8, 16} and lines in {1, 2, 4}, by
- * coordinate descent (strided axes first, then the contiguous axis), and
- * keeps the fastest schedule.  best (may be NULL) receives {rmax, lines} of
+ * operator and one precision: times solves of the device vector b with the
+ * current preconditioner setup and default options (per schedule: one
+ * warm-up solve, then the fastest of three runs of `reps` solves), for each
+ * candidate rmax in {4, 8, 16} and lines in {1, 2, 4}, by coordinate descent
+ * (strided axes first, then the contiguous axis).  A candidate replaces the
+ * current schedule only when it is more than 1 % faster.  best (may be NULL) receives {rmax, lines} of
  * the contiguous and then of the strided axes; *best_ms (may be NULL) its
  * time per solve.  Uses the context's stream and workspace; returns when done. */
 int fnls_autotune(fnls_ctx *ctx, const fnls_c128 *b, int precision, int reps, int best[4], double *best_ms);

@@ -19,7 +19,7 @@ STREAM_THREADS = 512
 
 
 DEFAULT_CFG = {"rmax": (4, 4), "lines": (1, 4)}   # (contiguous axis, strided axes)
-CONFIGS = [DEFAULT_CFG,
+PASS_CONFIGS = [DEFAULT_CFG,
            {"rmax": (4, 8), "lines": (2, 4)},
            {"rmax": (4, 4), "lines": (2, 2)},       # FP64 default
            {"rmax": (4, 8), "lines": (1, 4)},       # FP32 default
@@ -134,7 +134,7 @@ SIZES = [(d, n) for d in (1, 2, 3) for n in (1, 3, 7, 15, 31, 63, 127, 255, 511,
          if n ** d <= 1023 ** 2 or (d == 3 and n <= 255)]
 
 
-@pytest.mark.parametrize("cfg", range(len(CONFIGS)))
+@pytest.mark.parametrize("cfg", range(len(PASS_CONFIGS)))
 @pytest.mark.parametrize("max_dyn", [MAX_LDS_BLOCK - STATIC_LDS, 64 * 1024 - STATIC_LDS])
 @pytest.mark.parametrize("d,n", SIZES)
 def test_pass_addresses(d, n, max_dyn, cfg):
@@ -142,7 +142,7 @@ def test_pass_addresses(d, n, max_dyn, cfg):
     m = n + 1
     for axis in range(d):
         for fp64 in (True, False):
-            g = pass_geo(d, n, axis, fp64, max_dyn, CONFIGS[cfg])
+            g = pass_geo(d, n, axis, fp64, max_dyn, PASS_CONFIGS[cfg])
             G, L, stride = g["G"], g["L"], g["stride"]
             T = G * L
             assert 64 <= T <= g["tmax"] and T % 64 == 0
@@ -299,7 +299,7 @@ MAX_RESTART = 64
 REDUNDANT_MAX = 1024
 
 
-@pytest.mark.parametrize("cfg", range(len(CONFIGS)))
+@pytest.mark.parametrize("cfg", range(len(PASS_CONFIGS)))
 @pytest.mark.parametrize("d,n", SIZES)
 def test_partial_buffers(d, n, cfg):
     """Every per-workgroup partial written, and every one read back, lies in
@@ -312,7 +312,7 @@ def test_partial_buffers(d, n, cfg):
     size = {"p1": (MAX_RESTART + 2) * pstride, "p2": (MAX_RESTART + 2) * pstride,
             "p3": pstride, "pr": pstride, "px": MAX_RESTART + 2}
     for fp64 in (True, False):
-        nb0 = pass_geo(d, n, 0, fp64, MAX_LDS_BLOCK - STATIC_LDS, CONFIGS[cfg])["blocks"]
+        nb0 = pass_geo(d, n, 0, fp64, MAX_LDS_BLOCK - STATIC_LDS, PASS_CONFIGS[cfg])["blocks"]
         for restart in (1, 30, MAX_RESTART):
             for j in range(restart):
                 # producer -> buffer, number of values, producer workgroups
@@ -337,7 +337,7 @@ def test_stream_kernels_and_partials(d, n):
     pmax = blocks
     for axis in range(d):
         for fp64 in (True, False):
-            for cfg in CONFIGS:
+            for cfg in PASS_CONFIGS:
                 assert pass_geo(d, n, axis, fp64, MAX_LDS_BLOCK - STATIC_LDS, cfg)["blocks"] <= n ** (d - 1)
     pmax = max(blocks, n ** (d - 1))
     # reductions use at most pstride workgroups
