@@ -202,6 +202,12 @@ __device__ __forceinline__ int out_rot() {
     return sizeof(R) == 8 ? (((lane >> 2) & 1) | (((lane >> 1) & 1) << 1))    // 16-byte values
                           : (((lane >> 2) & 1) | (((lane >> 3) & 1) << 1));   // 8-byte values
 }
+// Radix-8 stage (Ns = 1) stores: three lane bits select the output order.
+template <typename R>
+__device__ __forceinline__ int out_rot8() {
+    const int lane = threadIdx.x & 63;
+    return sizeof(R) == 8 ? (lane & 7) : ((lane >> 1) & 7);
+}
 template <typename R>
 __device__ __forceinline__ int scan_rot() {
     const int lane = threadIdx.x & 63;
@@ -353,8 +359,10 @@ __device__ __forceinline__ void stage_store(const StageRegs<R, RAD, RMAX>& g, cp
     constexpr int PER = RMAX / RAD;
     const int nb = (1 << lgm) >> Lg<RAD>::v;
     const int Ns = 1 << lgNs;
-    // stages with Ns >= 16 store contiguous runs already; only Ns < 16 rotates
-    const int rot = (Ns < 16) ? (out_rot<R>() & (RAD <= 4 ? RAD - 1 : 0)) : 0;
+    // stages with Ns >= 16 (radix 8: Ns >= 8) store contiguous runs already;
+    // only the earlier ones rotate
+    const int rot = (RAD == 8) ? (Ns < 8 ? out_rot8<R>() : 0)
+                               : ((Ns < 16) ? (out_rot<R>() & (RAD <= 4 ? RAD - 1 : 0)) : 0);
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
         const int b = lt + q * G;
@@ -368,6 +376,23 @@ __device__ __forceinline__ void stage_store(const StageRegs<R, RAD, RMAX>& g, cp
                 X[base + (1 ^ rot) * Ns] = u1;
                 X[base + (2 ^ rot) * Ns] = u2;
                 X[base + (3 ^ rot) * Ns] = u3;
+            } else if constexpr (RAD == 8) {
+                // u_i = v_{i ^ rot} by three rounds of conditional pair swaps
+                C u[8];
+#pragma unroll
+                for (int r = 0; r < 8; ++r) u[r] = g.v[q][r];
+#pragma unroll
+                for (int bit = 1; bit < 8; bit <<= 1) {
+                    const bool sw = (rot & bit) != 0;
+#pragma unroll
+                    for (int r = 0; r < 8; ++r)
+                        if ((r & bit) == 0) {
+                            C a0 = u[r], a1 = u[r | bit];
+                            csel2(a0, a1, sw, u[r], u[r | bit]);
+                        }
+                }
+#pragma unroll
+                for (int i = 0; i < 8; ++i) X[base + (i ^ rot) * Ns] = u[i];
             } else if constexpr (RAD == 2) {
                 const C a0 = g.v[q][0], a1 = g.v[q][1];
                 C u0, u1;

@@ -245,7 +245,10 @@ def test_line_fft_and_line_ops_indices(m, rmax):
                 k = b & (Ns - 1)
                 step = k * ((2 * m) // (Ns * R))
                 tsh = lgm - (Ns.bit_length() - 1) - (R.bit_length() - 1)
-                rot = out_rot(lt & 63) & (R - 1 if R <= 4 else 0) if Ns < 16 else 0
+                if R == 8:
+                    rot = (lt & 63) & 7 if Ns < 8 else 0
+                else:
+                    rot = out_rot(lt & 63) & (R - 1 if R <= 4 else 0) if Ns < 16 else 0
                 # store i writes output i ^ rot: still every output once
                 assert sorted(i ^ rot for i in range(R)) == list(range(R))
                 for r in range(R):
