@@ -347,7 +347,7 @@ std::string pass_name(bool fp64, const PassVariant& v, int axis) {
 // write once (line data, D, accumulators, basis vectors of the dot products).
 double pass_bytes(fnls_ctx* c, bool fp64, const PassVariant& v, const PassArgs& a) {
     const double N = (double)c->N, e = fp64 ? 16.0 : 8.0, dsz = fp64 ? 8.0 : 4.0;
-    double b = (v.inm == IN_COMBO) ? c->cur_k * e * N : e * N;
+    double b = (v.inm == IN_COMBO) ? c->cur_k * (a.zsum ? (a.z32 ? 8.0 : 16.0) : e) * N : e * N;
     if ((v.ops & P_SCALE) || v.outm == OUT_ACC_FIRST) b += dsz * N;
     if (v.zm == Z_WRITE) b += e * N;
     if (v.zm == Z_XSET) b += 16.0 * N;
@@ -687,26 +687,6 @@ int cycle_final_passes(fnls_ctx* c, bool fp64, Bufs& b, const void* b64, void* x
         }
         PassVariant v{IN_COMBO, P_DST1 | P_DIV | P_DST2 | P_SCALE, Z_XADD, OUT_LINE, FIN_WRITE};
         if ((rc = run_pass(c, false, 0, v, a, g)) != FNLS_OK) return rc;
-    } else {
-        // x (+)= sum_k y_k z_k over the preconditioned basis stored by the Arnoldi passes
-        // (equal to Ptilde^{-1} (V y) by linearity)
-        StreamArgs s;
-        std::memset(&s, 0, sizeof s);
-        s.N = c->N;
-        s.vbase = b.zbase;
-        s.x64 = (double2*)x;
-        s.mode = first;
-        s.st = c->st();
-        const double e = fp64 ? 16.0 : 8.0;
-        const LaunchEvents* te =
-            c->timing ? timing_begin(c, fp64 ? "zupdate64" : "zupdate32",
-                                     (c->cur_k * e + (first ? 16.0 : 32.0)) * (double)c->N)
-                      : nullptr;
-        hipError_t e2 = launch_zupdate(fp64 ? 1 : 0, s, stream_blocks(c->N), c->stream, te);
-        if (e2 != hipSuccess) {
-            timing_failed(c, te);
-            return set_err(c, FNLS_ERR_HIP, "zupdate launch failed: %s", hipGetErrorString(e2));
-        }
     }
     // FP64 residual r = b - A x (IR: with its complex64 copy as the next basis vector 0)
     Geo g = pass_geo(d, c->n, d - 1, true, c->max_dyn_lds, c->pcfg);
@@ -725,9 +705,19 @@ int cycle_final_passes(fnls_ctx* c, bool fp64, Bufs& b, const void* b64, void* x
         PassVariant v{IN_PLAIN, P_TOEP, Z_NONE, OUT_ACC_FIRST, FIN_RESID};
         return run_pass(c, true, 0, v, a, g);
     }
+    // d >= 2: the first axis pass of the residual also forms the update
+    // x (+)= sum_k y_k z_k over the preconditioned basis stored by the Arnoldi
+    // passes (equal to Ptilde^{-1} (V y) by linearity), in FP64, and takes the
+    // new x as its Toeplitz operand
     void* acc64 = c->at<char>(c->lay.acc);
     a.out = acc64;
-    PassVariant v{IN_PLAIN, P_TOEP, Z_NONE, OUT_ACC_FIRST, FIN_WRITE};
+    a.in = nullptr;
+    a.zsum = 1;
+    a.z32 = fp64 ? 0 : 1;
+    a.vbase = b.zbase;
+    a.x64 = (double2*)x;
+    a.first_cycle = first;
+    PassVariant v{IN_COMBO, P_TOEP, Z_XADD, OUT_ACC_FIRST, FIN_WRITE};
     if ((rc = run_pass(c, true, d - 1, v, a, g)) != FNLS_OK) return rc;
     PassArgs tmpl;
     std::memset(&tmpl, 0, sizeof tmpl);

@@ -115,6 +115,7 @@ struct PassArgs {
     HostStatus* hs;
     int check_active;     // return at once if st->active == 0
     int first_cycle;      // Z_XADD: 1 = set x (first correction), 0 = accumulate
+    int zsum, z32;        // IN_COMBO: 1 = sum_k y_k z_k with z_k at vbase + k N (z32: complex64)
     int ir;               // FIN_RESID: 1 = refinement step of FP32-IR
     // Givens step of the previous Arnoldi iteration in one extra workgroup
     // (logical block 0) of this launch: partials of ||w||^2 in gpin

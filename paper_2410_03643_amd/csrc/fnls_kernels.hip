@@ -405,6 +405,27 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
                     } else if (INM == IN_BASIS) {
                         const C t = ld<R>(in_p, gi);
                         v = cm<R>(static_cast<R>(t.x * sig), static_cast<R>(t.y * sig));
+                    } else if (a.zsum) {
+                        // sum_k y_k z_k over the stored preconditioned basis
+                        // (complex64 when z32), accumulated in FP64
+                        double sx = 0.0, sy = 0.0;
+                        for (int i = 0; i < nvc; ++i) {
+                            const long long zi = (long long)i * a.N + gi;
+                            double tx, ty;
+                            if (a.z32) {
+                                const float2 t = reinterpret_cast<const float2*>(a.vbase)[zi];
+                                tx = t.x;
+                                ty = t.y;
+                            } else {
+                                const double2 t = reinterpret_cast<const double2*>(a.vbase)[zi];
+                                tx = t.x;
+                                ty = t.y;
+                            }
+                            const double2 c = a.st->y[i];
+                            sx += c.x * tx - c.y * ty;
+                            sy += c.x * ty + c.y * tx;
+                        }
+                        v = cm<R>(static_cast<R>(sx), static_cast<R>(sy));
                     } else {
                         double sx = 0.0, sy = 0.0;
                         for (int i = 0; i < nvc; ++i) {
@@ -984,8 +1005,6 @@ __global__ __launch_bounds__(kStreamThreads) void k_prepare_batch(const StreamAr
 }
 
 template <typename R>
-__global__ __launch_bounds__(kStreamThreads) void k_zupdate(StreamArgs a) { zupdate_body<R>(a, (int)blockIdx.x); }
-template <typename R>
 __global__ __launch_bounds__(kStreamThreads) void k_zupdate_batch(const StreamArgs* args, const int* offs, int count) {
     const int g = (int)blockIdx.x;
     const int i = batch_find(offs, count, g);
@@ -1093,6 +1112,8 @@ static hipError_t dispatch_pass(const PassVariant& v, const PassArgs& a, int blo
     FNLS_PASS_CASE(R, IN_COMBO, FULL1, Z_XADD, OUT_LINE, FIN_WRITE)
     // Toeplitz passes
     FNLS_PASS_CASE(R, IN_PLAIN, TOEP, Z_NONE, OUT_ACC_FIRST, FIN_WRITE)
+    // end of a cycle (d >= 2): x (+)= sum_k y_k z_k, then the residual's first axis
+    FNLS_PASS_CASE(R, IN_COMBO, TOEP, Z_XADD, OUT_ACC_FIRST, FIN_WRITE)
     FNLS_PASS_CASE(R, IN_PLAIN, TOEP, Z_NONE, OUT_ACC_FIRST, FIN_RESID)
     FNLS_PASS_CASE(R, IN_PLAIN, TOEP, Z_NONE, OUT_ACC_NEXT, FIN_WRITE)
     FNLS_PASS_CASE(R, IN_PLAIN, TOEP, Z_NONE, OUT_ACC_NEXT, FIN_WDOTS)
@@ -1203,11 +1224,6 @@ hipError_t launch_cgs(int fp64, int mode, const StreamArgs& a, int blocks, hipSt
     if (fp64)
         return mode == 0 ? launch_k(k_cgs<double, 0>, g, b, 0, s, te, a) : launch_k(k_cgs<double, 1>, g, b, 0, s, te, a);
     return mode == 0 ? launch_k(k_cgs<float, 0>, g, b, 0, s, te, a) : launch_k(k_cgs<float, 1>, g, b, 0, s, te, a);
-}
-
-hipError_t launch_zupdate(int fp64, const StreamArgs& a, int blocks, hipStream_t s, const LaunchEvents* te) {
-    const dim3 g(blocks), b(kStreamThreads);
-    return fp64 ? launch_k(k_zupdate<double>, g, b, 0, s, te, a) : launch_k(k_zupdate<float>, g, b, 0, s, te, a);
 }
 
 hipError_t launch_conj(const double2* in, double2* out, long long N, hipStream_t s) {

@@ -32,9 +32,6 @@ hipError_t launch_cgs(int fp64, int mode, const StreamArgs& a, int blocks, hipSt
 hipError_t launch_conj(const double2* in, double2* out, long long N, hipStream_t s);
 // gradient accumulation of one step's reverse mode
 hipError_t launch_adjoint(const AdjointArgs& a, hipStream_t s, const LaunchEvents* te = nullptr);
-// x (+)= sum_k y_k z_k over the stored preconditioned basis (vbase, st->k vectors)
-hipError_t launch_zupdate(int fp64, const StreamArgs& a, int blocks, hipStream_t s,
-                          const LaunchEvents* te = nullptr);
 // batched launches: instance i owns the blocks [offs[i], offs[i+1]); args / offs in device memory
 hipError_t launch_pass_batch(int fp64, const PassVariant& v, const PassArgs* args, const int* offs, int count,
                              int blocks, size_t lds, int threads, hipStream_t s);
