@@ -420,8 +420,9 @@ Bufs bufs(fnls_ctx* c, bool fp64, const void* v0_fp64) {
 // basis vector, the second applies the basis scale sigma_j, and an event
 // marks the end of the first pass; givens: the first pass also carries the
 // previous iteration's Givens step in an extra workgroup.
+// part: 0 all passes, 1 the first pass only, 2 all passes after the first.
 int precond_front(fnls_ctx* c, bool fp64, int inm, const void* src, int basis_j, Bufs& b, void** result,
-                  int check_active, bool scale_second = false, bool givens = false) {
+                  int check_active, bool scale_second = false, bool givens = false, int part = 0) {
     const bool fused = scale_second;
     const int d = c->d;
     void* cur_in = const_cast<void*>(src);
@@ -445,8 +446,9 @@ int precond_front(fnls_ctx* c, bool fp64, int inm, const void* src, int basis_j,
             a.gpin_stride = c->lay.pstride;
         }
         PassVariant v{cur_mode, ops, Z_NONE, OUT_LINE, FIN_WRITE};
-        int rc = run_pass(c, fp64, axis, v, a, g);
-        if (rc == FNLS_OK && npass == 0 && fused) {
+        const bool launch = (part == 0) || (part == 1 ? npass == 0 : npass >= 1);
+        int rc = launch ? run_pass(c, fp64, axis, v, a, g) : FNLS_OK;
+        if (rc == FNLS_OK && launch && npass == 0 && fused) {
             hipError_t e = hipEventRecord(c->evp[basis_j % kEvents], c->stream);
             if (e != hipSuccess) rc = set_err(c, FNLS_ERR_HIP, "hipEventRecord: %s", hipGetErrorString(e));
         }
@@ -552,7 +554,9 @@ int reduce_if_wide(fnls_ctx* c, StreamArgs& s, int nv) {
 
 // One Arnoldi step j: w = A Ptilde^{-1} v_j into basis slot j+1, first-round
 // dot products, then the two Gram-Schmidt update kernels.
-int arnoldi_step(fnls_ctx* c, bool fp64, Bufs& b, int j) {
+// part: 0 the whole step; for d >= 2, 1 = its first pass only (which
+// carries the previous step's Givens step when fused), 2 = the rest.
+int arnoldi_step(fnls_ctx* c, bool fp64, Bufs& b, int j, int part = 0) {
     const int d = c->d;
     const size_t esz = fp64 ? 16 : 8;
     void* vj = (j == 0) ? b.v0 : (void*)((char*)b.vbase + (size_t)(j - 1) * c->N * esz);
@@ -574,8 +578,9 @@ int arnoldi_step(fnls_ctx* c, bool fp64, Bufs& b, int j) {
         if ((rc = run_pass(c, fp64, 0, v, a, g)) != FNLS_OK) return rc;
     } else {
         void* t;
-        if ((rc = precond_front(c, fp64, IN_BASIS, vj, j, b, &t, 1, true, c->fuse != 0 && j >= 1)) != FNLS_OK)
+        if ((rc = precond_front(c, fp64, IN_BASIS, vj, j, b, &t, 1, true, c->fuse != 0 && j >= 1, part)) != FNLS_OK)
             return rc;
+        if (part == 1) return FNLS_OK;
         Geo g = pass_geo(d, c->n, d - 1, fp64, c->max_dyn_lds, c->pcfg);
         PassArgs a = base_args(c, fp64, d - 1, g);
         a.in = t;
@@ -772,12 +777,30 @@ int run_cycle(fnls_ctx* c, bool fp64, Bufs& b, int restart, int lookahead, int t
     // iteration j + 1, which the lookahead has issued before the wait
     c->fuse = (lookahead >= 1 && c->d >= 2 && stream_blocks(c->N) <= kRedundantMax) ? 1 : 0;
     c->restart_cur = restart;
+    // With the fused Givens step, iteration J's first pass decides whether
+    // iteration J - 1 stopped the cycle.  When the estimates of the finished
+    // iterations, extrapolated at their last rate, predict that stop, only
+    // that first pass is issued ahead; the rest of iteration J follows once
+    // the status shows that the cycle goes on (a short host round trip).
+    std::vector<char> partial((size_t)restart + 1, 0);
+    double est_last = 1.0, est_prev = 1.0, tol_last = 0.0;
     while (true) {
         while (issued < restart && issued <= waited + lookahead) {
             rec_first.push_back(c->recs.size());
-            int rc = arnoldi_step(c, fp64, b, issued);
+            bool first_only = false;
+            if (c->fuse && issued >= 1 && waited >= 1 && est_prev > 0.0 && tol_last > 0.0) {
+                const double rate = est_last / est_prev;
+                double pred = est_last;
+                for (int k = waited; k < issued; ++k) pred *= rate;   // estimate of iteration issued - 1
+                first_only = rate < 1.0 && pred < tol_last;
+            }
+            int rc = arnoldi_step(c, fp64, b, issued, first_only ? 1 : 0);
             if (rc != FNLS_OK) return rc;
-            HIPCHK(c, hipEventRecord(c->ev[issued % kEvents], c->stream));
+            if (first_only) {
+                partial[issued] = 1;
+            } else {
+                HIPCHK(c, hipEventRecord(c->ev[issued % kEvents], c->stream));
+            }
             ++issued;
         }
         const bool via_next = c->fuse && waited + 1 < restart;
@@ -790,6 +813,15 @@ int run_cycle(fnls_ctx* c, bool fp64, Bufs& b, int restart, int lookahead, int t
             return FNLS_OK;
         }
         if (hs.stopped || waited >= restart) break;
+        est_prev = est_last;
+        est_last = hs.est;
+        tol_last = hs.tol;
+        // the cycle goes on: complete an iteration that was issued up to its first pass
+        if (partial[waited]) {
+            partial[waited] = 0;
+            if ((rc = arnoldi_step(c, fp64, b, waited, 2)) != FNLS_OK) return rc;
+            HIPCHK(c, hipEventRecord(c->ev[waited % kEvents], c->stream));
+        }
     }
     *total_after = hs.total;
     c->cur_k = hs.total - total_before;   // iterations of this cycle

@@ -62,6 +62,7 @@ struct HostStatus {
     double est;
     double relres;
     double bnorm;
+    double tol;      // the tolerance est is compared with (inner one in FP32-IR)
     double hist[64];
 };
 

@@ -42,6 +42,7 @@ __device__ void report(GmresState* st, HostStatus* hs, int stopped) {
         hs->nonfinite = st->nonfinite;
         hs->outer = st->outer;
         hs->est = st->est;
+        hs->tol = st->tol;
         hs->relres = st->relres;
         hs->bnorm = st->bnorm;
         if (st->total >= 1 && st->total <= 64) hs->hist[st->total - 1] = st->hist[st->total - 1];
