@@ -1076,6 +1076,9 @@ static hipError_t launch_pass_r(int rmax, const PassArgs& a, int blocks, size_t 
         if (rmax == 4) return launch_pass_t<R, 4, 10, INM, OPS, ZM, OUTM, FIN>(a, blocks, lds, s, te);
         if (rmax == 8) return launch_pass_t<R, 8, 10, INM, OPS, ZM, OUTM, FIN>(a, blocks, lds, s, te);
     }
+    // m = 512 and 256 (d = 2, n = 511; d = 3, n = 255): compile-time radix-4 plans
+    if (a.lgm == 9 && rmax == 4) return launch_pass_t<R, 4, 9, INM, OPS, ZM, OUTM, FIN>(a, blocks, lds, s, te);
+    if (a.lgm == 8 && rmax == 4) return launch_pass_t<R, 4, 8, INM, OPS, ZM, OUTM, FIN>(a, blocks, lds, s, te);
     switch (rmax) {
         case 4: return launch_pass_t<R, 4, 0, INM, OPS, ZM, OUTM, FIN>(a, blocks, lds, s, te);
         case 8: return launch_pass_t<R, 8, 0, INM, OPS, ZM, OUTM, FIN>(a, blocks, lds, s, te);
