@@ -212,7 +212,8 @@ int fnls_first_step_backward(fnls_ctx *ctx, const fnls_c128 *u0, const fnls_c128
 /* Batches: many independent systems of uneven sizes (each an assembled
  * context with its own operator, workspace and preconditioner setup)
  * advanced together.  Every GMRES iteration issues one launch per transform
- * pass, Gram-Schmidt update and Givens step for all instances together;
+ * pass (per line-length class: 1024, 512, 256, other), Gram-Schmidt update
+ * and Givens step for all instances together;
  * each instance keeps its own convergence state, and instances that have
  * converged drop out.  All contexts must share device, stream and d (d >= 2),
  * with n >= 31 and n^(d-1) <= 262144.  The batch does not own the contexts. */

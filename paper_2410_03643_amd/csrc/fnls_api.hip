@@ -1482,7 +1482,7 @@ constexpr int kBatchThreads = 1024;
 constexpr int kMaxBatch = 4096;
 constexpr size_t kBatchRingMin = (size_t)16 << 20;
 constexpr int kGraphSlots = 4;        // cached iteration graphs per batch
-constexpr int kMaxIterLaunches = 12;  // launches of one Arnoldi iteration (d <= 3)
+constexpr int kMaxIterLaunches = 36;  // launches of one Arnoldi iteration (d <= 3, 4 line-length classes)
 
 struct GraphSlot {
     std::vector<char> key;            // argument table + launch shapes it was captured with
@@ -1588,18 +1588,24 @@ int stage(fnls_batch* B, const Blob& blob, char** dbase) {
 }
 
 // One launch of a batch: per-instance arguments and the block offsets.
+// Line lengths with a compile-time plan in the batched pass kernel.
+int batch_lgm_class(int lgm) { return (lgm == 8 || lgm == 9 || lgm == 10) ? lgm : 0; }
+
 struct PassLaunch {
     PassVariant v;
     int fp64;
+    int lgm = 0;                      // line-length class of every instance (batch_lgm_class)
     std::vector<PassArgs> args;
     std::vector<int> offs{0};
+    std::vector<size_t> ilds;         // LDS of each instance
     size_t lds = 0;
     size_t a_off = 0, o_off = 0;
     void add(PassArgs a, const Geo& g) {
         line_layout(a.m, g.L, fp64 != 0, (v.ops & P_TOEP) != 0, &a.pa, &a.ls);
         args.push_back(a);
         offs.push_back(offs.back() + g.blocks);
-        lds = std::max(lds, pass_lds(g, a.m, fp64 != 0, (v.ops & P_TOEP) != 0));
+        ilds.push_back(pass_lds(g, a.m, fp64 != 0, (v.ops & P_TOEP) != 0));
+        lds = std::max(lds, ilds.back());
     }
 };
 struct StreamLaunch {
@@ -1618,9 +1624,28 @@ struct Step {
     std::vector<PassLaunch> passes;
     std::vector<StreamLaunch> streams;
     std::vector<int> order;   // >= 0: pass index, < 0: -(stream index) - 1
+    // one launch per line-length class (compile-time plans for 2^8 .. 2^10)
     void pass(PassLaunch p) {
-        order.push_back((int)passes.size());
-        passes.push_back(std::move(p));
+        std::vector<int> classes;
+        for (const PassArgs& a : p.args) {
+            const int cl = batch_lgm_class(a.lgm);
+            if (std::find(classes.begin(), classes.end(), cl) == classes.end()) classes.push_back(cl);
+        }
+        for (int cl : classes) {
+            PassLaunch q;
+            q.v = p.v;
+            q.fp64 = p.fp64;
+            q.lgm = cl;
+            for (size_t i = 0; i < p.args.size(); ++i) {
+                if (batch_lgm_class(p.args[i].lgm) != cl) continue;
+                q.args.push_back(p.args[i]);
+                q.offs.push_back(q.offs.back() + (p.offs[i + 1] - p.offs[i]));
+                q.ilds.push_back(p.ilds[i]);
+                q.lds = std::max(q.lds, p.ilds[i]);
+            }
+            order.push_back((int)passes.size());
+            passes.push_back(std::move(q));
+        }
     }
     void strm(StreamLaunch s) {
         order.push_back(-(int)streams.size() - 1);
@@ -1651,7 +1676,7 @@ int launch_step(fnls_batch* B, const Step& st, char* base, hipStream_t s_, bool 
             const int count = (int)p.args.size();
             if (count == 0) continue;
             if (p.lds > B->ctx[0]->max_dyn_lds) return berr(B, FNLS_ERR_INVALID_ARG, "batch pass needs %zu B of LDS", p.lds);
-            e = launch_pass_batch(p.fp64, p.v, attr_only ? nullptr : reinterpret_cast<const PassArgs*>(base + p.a_off),
+            e = launch_pass_batch(p.fp64, p.v, p.lgm, attr_only ? nullptr : reinterpret_cast<const PassArgs*>(base + p.a_off),
                                   reinterpret_cast<const int*>(base + p.o_off), count, p.offs.back(), p.lds,
                                   kBatchThreads, s_);
         } else if (!attr_only) {
@@ -1698,7 +1723,7 @@ std::vector<char> graph_key(const Step& st, const Blob& blob) {
         sig.push_back(o);
         if (o >= 0) {
             const PassLaunch& p = st.passes[o];
-            sig.insert(sig.end(), {p.v.inm, p.v.ops, p.v.zm, p.v.outm, p.v.fin, p.v.rmax, p.fp64,
+            sig.insert(sig.end(), {p.v.inm, p.v.ops, p.v.zm, p.v.outm, p.v.fin, p.v.rmax, p.fp64, p.lgm,
                                    (int)p.args.size(), p.offs.back(), (int)p.lds});
         } else {
             const StreamLaunch& s = st.streams[-o - 1];

@@ -667,13 +667,14 @@ __global__ __launch_bounds__(PassThreads<RMAX>::v) void k_pass(PassArgs a) {
     pass_body<R, RMAX, LGM, INM, OPS, ZM, OUTM, FIN>(a, xcd_block((int)blockIdx.x, (int)gridDim.x));
 }
 
-// One launch over the lines of many instances (each with its own PassArgs).
-template <typename R, int RMAX, int INM, int OPS, int ZM, int OUTM, int FIN>
+// One launch over the lines of many instances (each with its own PassArgs);
+// LGM > 0: every instance has lines of length 2^LGM (compile-time plan).
+template <typename R, int RMAX, int LGM, int INM, int OPS, int ZM, int OUTM, int FIN>
 __global__ __launch_bounds__(PassThreads<RMAX>::v) void k_pass_batch(const PassArgs* args, const int* offs,
                                                                       int count) {
     const int g = xcd_block((int)blockIdx.x, (int)gridDim.x);
     const int i = batch_find(offs, count, g);
-    pass_body<R, RMAX, 0, INM, OPS, ZM, OUTM, FIN, true>(args[i], g - offs[i]);
+    pass_body<R, RMAX, LGM, INM, OPS, ZM, OUTM, FIN, true>(args[i], g - offs[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1130,11 +1131,12 @@ hipError_t launch_pass(int fp64, const PassVariant& v, const PassArgs& a, int bl
     return fp64 ? dispatch_pass<double>(v, a, blocks, lds, s, te) : dispatch_pass<float>(v, a, blocks, lds, s, te);
 }
 
-// ---- batched launches (radix 4, 1024 threads per workgroup, generic line length) ----
-template <typename R, int INM, int OPS, int ZM, int OUTM, int FIN>
-static hipError_t launch_pass_batch_t(const PassArgs* args, const int* offs, int count, int blocks, size_t lds,
+// ---- batched launches (radix 4, 1024 threads per workgroup; line length
+// 2^LGM for every instance of the launch, or generic with LGM = 0) ----
+template <typename R, int LGM, int INM, int OPS, int ZM, int OUTM, int FIN>
+static hipError_t launch_pass_batch_l(const PassArgs* args, const int* offs, int count, int blocks, size_t lds,
                                       int threads, hipStream_t s) {
-    auto kern = k_pass_batch<R, 4, INM, OPS, ZM, OUTM, FIN>;
+    auto kern = k_pass_batch<R, 4, LGM, INM, OPS, ZM, OUTM, FIN>;
     static size_t granted = 64 * 1024;
     if (lds > granted) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
@@ -1147,13 +1149,24 @@ static hipError_t launch_pass_batch_t(const PassArgs* args, const int* offs, int
     return launch_k(kern, dim3(blocks), dim3(threads), lds, s, nullptr, args, offs, count);
 }
 
+template <typename R, int INM, int OPS, int ZM, int OUTM, int FIN>
+static hipError_t launch_pass_batch_t(int lgm, const PassArgs* args, const int* offs, int count, int blocks,
+                                      size_t lds, int threads, hipStream_t s) {
+    switch (lgm) {
+        case 10: return launch_pass_batch_l<R, 10, INM, OPS, ZM, OUTM, FIN>(args, offs, count, blocks, lds, threads, s);
+        case 9: return launch_pass_batch_l<R, 9, INM, OPS, ZM, OUTM, FIN>(args, offs, count, blocks, lds, threads, s);
+        case 8: return launch_pass_batch_l<R, 8, INM, OPS, ZM, OUTM, FIN>(args, offs, count, blocks, lds, threads, s);
+        default: return launch_pass_batch_l<R, 0, INM, OPS, ZM, OUTM, FIN>(args, offs, count, blocks, lds, threads, s);
+    }
+}
+
 #define FNLS_BATCH_CASE(R, INM, OPS, ZM, OUTM, FIN)                                             \
     if (v.inm == INM && v.ops == (OPS) && v.zm == ZM && v.outm == OUTM && v.fin == FIN)         \
-        return launch_pass_batch_t<R, INM, OPS, ZM, OUTM, FIN>(args, offs, count, blocks, lds, threads, s);
+        return launch_pass_batch_t<R, INM, OPS, ZM, OUTM, FIN>(lgm, args, offs, count, blocks, lds, threads, s);
 
 template <typename R>
-static hipError_t dispatch_pass_batch(const PassVariant& v, const PassArgs* args, const int* offs, int count,
-                                      int blocks, size_t lds, int threads, hipStream_t s) {
+static hipError_t dispatch_pass_batch(const PassVariant& v, int lgm, const PassArgs* args, const int* offs,
+                                      int count, int blocks, size_t lds, int threads, hipStream_t s) {
     constexpr int DST = OP_DST1;
     constexpr int DDD = OP_DST1 | OP_DIV | OP_DST2;
     constexpr int LASTDST_T = OP_DST1 | OP_SCALE | OP_TOEP;
@@ -1169,10 +1182,10 @@ static hipError_t dispatch_pass_batch(const PassVariant& v, const PassArgs* args
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_pass_batch(int fp64, const PassVariant& v, const PassArgs* args, const int* offs, int count,
-                             int blocks, size_t lds, int threads, hipStream_t s) {
-    return fp64 ? dispatch_pass_batch<double>(v, args, offs, count, blocks, lds, threads, s)
-                : dispatch_pass_batch<float>(v, args, offs, count, blocks, lds, threads, s);
+hipError_t launch_pass_batch(int fp64, const PassVariant& v, int lgm, const PassArgs* args, const int* offs,
+                             int count, int blocks, size_t lds, int threads, hipStream_t s) {
+    return fp64 ? dispatch_pass_batch<double>(v, lgm, args, offs, count, blocks, lds, threads, s)
+                : dispatch_pass_batch<float>(v, lgm, args, offs, count, blocks, lds, threads, s);
 }
 
 hipError_t launch_cgs_batch(int fp64, int mode, const StreamArgs* args, const int* offs, int count, int blocks,

@@ -32,9 +32,11 @@ hipError_t launch_cgs(int fp64, int mode, const StreamArgs& a, int blocks, hipSt
 hipError_t launch_conj(const double2* in, double2* out, long long N, hipStream_t s);
 // gradient accumulation of one step's reverse mode
 hipError_t launch_adjoint(const AdjointArgs& a, hipStream_t s, const LaunchEvents* te = nullptr);
-// batched launches: instance i owns the blocks [offs[i], offs[i+1]); args / offs in device memory
-hipError_t launch_pass_batch(int fp64, const PassVariant& v, const PassArgs* args, const int* offs, int count,
-                             int blocks, size_t lds, int threads, hipStream_t s);
+// batched launches: instance i owns the blocks [offs[i], offs[i+1]); args / offs in device memory.
+// lgm in {8, 9, 10}: every instance of the pass launch has lines of length 2^lgm (compile-time
+// plan); anything else: the generic plan.  args == nullptr: only raise the kernel's LDS limit.
+hipError_t launch_pass_batch(int fp64, const PassVariant& v, int lgm, const PassArgs* args, const int* offs,
+                             int count, int blocks, size_t lds, int threads, hipStream_t s);
 hipError_t launch_cgs_batch(int fp64, int mode, const StreamArgs* args, const int* offs, int count, int blocks,
                             hipStream_t s);
 hipError_t launch_zupdate_batch(int fp64, const StreamArgs* args, const int* offs, int count, int blocks,
