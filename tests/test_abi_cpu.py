@@ -28,7 +28,7 @@ def test_default_opts(L):
 
 
 def test_struct_sizes_match_header():
-    # double + 3 int + pad + double + 3 int + int[4] -> 64 bytes; info 24 + 512
+    # double + 3 int + pad + double + 4 int (lookahead, graph) + int[3] -> 64 bytes; info 24 + 512
     assert ctypes.sizeof(fnls.Opts) == 64
     assert ctypes.sizeof(fnls.Info) == 24 + 64 * 8
 
@@ -77,6 +77,11 @@ def test_null_context_is_rejected(L):
     assert L.fnls_batch_last_error(None) == b"null batch"
     assert L.fnls_batch_workspace_bytes(0) == 0 and L.fnls_batch_workspace_bytes(4097) == 0
     assert L.fnls_batch_workspace_bytes(64) >= 16 << 20
+    # the workspace grows with the count (argument tables of the cached graphs)
+    assert L.fnls_batch_workspace_bytes(4096) > L.fnls_batch_workspace_bytes(64)
+    cap, rep = ctypes.c_longlong(-1), ctypes.c_longlong(-1)
+    assert L.fnls_batch_graph_stats(None, ctypes.byref(cap), ctypes.byref(rep)) == fnls.ERR_INVALID_ARG
+    assert cap.value == -1 and rep.value == -1
     L.fnls_batch_destroy(None)
     L.fnls_destroy(None)
     assert L.fnls_last_error(None) == b"null context"
