@@ -786,6 +786,10 @@ int run_cycle(fnls_ctx* c, bool fp64, Bufs& b, int restart, int lookahead, int t
     double est_last = 1.0, est_prev = 1.0, tol_last = 0.0;
     while (true) {
         while (issued < restart && issued <= waited + lookahead) {
+            // an iteration whose predecessor was issued only up to its first
+            // pass must wait for that predecessor's rest (its first pass runs
+            // the predecessor's Givens step)
+            if (issued >= 1 && partial[issued - 1]) break;
             rec_first.push_back(c->recs.size());
             bool first_only = false;
             if (c->fuse && issued >= 1 && waited >= 1 && est_prev > 0.0 && tol_last > 0.0) {

@@ -211,6 +211,29 @@ def test_lookahead_settings_agree(torch_dev):
     assert torch.equal(xs[0], xs[1]) and torch.equal(xs[0], xs[2])
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_lookahead_settings_agree_uneven_convergence(torch_dev, precision):
+    """A random right-hand side converges at an uneven rate, so the host's
+    prediction of the stopping iteration (which issues only the next first
+    pass ahead) is sometimes wrong and the iteration is completed afterwards:
+    lookahead 0, 1 and 3 must still give bitwise equal results, over several
+    restart cycles, with the oracle's iteration count."""
+    torch, dev = torch_dev
+    s, o, u, ut = make(torch_dev, 2, 255, -10, 10, 1.3, 2.0, 0.02)
+    bn = inputs.random_field(u.shape, seed=17)
+    b = torch.from_numpy(bn).to(dev)
+    tol = 1e-13 if precision == "fp64" else 1e-11
+    runs = [s.solve(b, tol=tol, restart=3, lookahead=la, precision=precision) for la in (0, 1, 3)]
+    its = [r[1].iters for r in runs]
+    print("%s: IT %s, outer %s" % (precision, its, [r[1].outer_iters for r in runs]), flush=True)
+    assert all(r[1].status == 0 for r in runs)
+    assert torch.equal(runs[0][0], runs[1][0]) and torch.equal(runs[0][0], runs[2][0])
+    assert its[0] == its[1] == its[2]
+    if precision == "fp64":
+        _, io = o.solve(bn, tol=tol, restart=3)
+        assert abs(io.iters - its[0]) <= 1
+
+
 def test_step_and_first_step(torch_dev):
     torch, dev = torch_dev
     d, n, lo, hi, alpha, rho, tau = 2, 63, -10.0, 10.0, 1.5, 2.0, 0.005
