@@ -804,7 +804,10 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs a) {
 // are complex<R>; arithmetic in FP64.  Each thread owns kEpt elements
 // (stride = workgroup size: every load instruction of a wavefront is
 // contiguous) and issues all kEpt loads of a vector at once.
-template <typename R, int MODE, bool BJ = false>
+// NVR > 0 (MODE 0, nv = NVR known at launch): the basis values of the
+// thread's elements are read once into registers and serve both the update
+// and the second-round dot products (a single read of V instead of two).
+template <typename R, int MODE, bool BJ = false, int NVR = 0>
 __device__ __forceinline__ void cgs_body(const StreamArgs& a, int blk) {
     using C = cplx<R>;
     __shared__ double2 s_red[(kMaxRestart + 2) * kMaxWaves];
@@ -847,20 +850,44 @@ __device__ __forceinline__ void cgs_body(const StreamArgs& a, int blk) {
         wx[q] = w.x;
         wy[q] = w.y;
     }
-    for (int vi = 0; vi < nv; ++vi) {
-        const void* vp = (vi == 0) ? a.v0
-                                   : (const void*)(reinterpret_cast<const C*>(a.vbase) + (long long)(vi - 1) * N);
-        const double2 c = s_coef[vi];
-        C v[kEpt];
+    constexpr bool kRegV = (MODE == 0 && NVR > 0);
+    C vr[kRegV ? NVR : 1][kRegV ? kEpt : 1];
+    if constexpr (kRegV) {
 #pragma unroll
-        for (int q = 0; q < kEpt; ++q) {
-            const long long i = base + (long long)q * kStreamThreads;
-            v[q] = i < N ? ld<R>(vp, i) : czero<C>();
+        for (int vi = 0; vi < NVR; ++vi) {
+            const void* vp = (vi == 0) ? a.v0
+                                       : (const void*)(reinterpret_cast<const C*>(a.vbase) + (long long)(vi - 1) * N);
+#pragma unroll
+            for (int q = 0; q < kEpt; ++q) {
+                const long long i = base + (long long)q * kStreamThreads;
+                vr[vi][q] = i < N ? ld<R>(vp, i) : czero<C>();
+            }
         }
 #pragma unroll
-        for (int q = 0; q < kEpt; ++q) {
-            wx[q] -= c.x * v[q].x - c.y * v[q].y;
-            wy[q] -= c.x * v[q].y + c.y * v[q].x;
+        for (int vi = 0; vi < NVR; ++vi) {
+            const double2 c = s_coef[vi];
+#pragma unroll
+            for (int q = 0; q < kEpt; ++q) {
+                wx[q] -= c.x * vr[vi][q].x - c.y * vr[vi][q].y;
+                wy[q] -= c.x * vr[vi][q].y + c.y * vr[vi][q].x;
+            }
+        }
+    } else {
+        for (int vi = 0; vi < nv; ++vi) {
+            const void* vp = (vi == 0) ? a.v0
+                                       : (const void*)(reinterpret_cast<const C*>(a.vbase) + (long long)(vi - 1) * N);
+            const double2 c = s_coef[vi];
+            C v[kEpt];
+#pragma unroll
+            for (int q = 0; q < kEpt; ++q) {
+                const long long i = base + (long long)q * kStreamThreads;
+                v[q] = i < N ? ld<R>(vp, i) : czero<C>();
+            }
+#pragma unroll
+            for (int q = 0; q < kEpt; ++q) {
+                wx[q] -= c.x * v[q].x - c.y * v[q].y;
+                wy[q] -= c.x * v[q].y + c.y * v[q].x;
+            }
         }
     }
     C wr[kEpt];
@@ -875,7 +902,21 @@ __device__ __forceinline__ void cgs_body(const StreamArgs& a, int blk) {
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int nout;
-    if (MODE == 0) {
+    if constexpr (kRegV) {
+#pragma unroll
+        for (int vi = 0; vi < NVR; ++vi) {
+            double sx = 0.0, sy = 0.0;
+#pragma unroll
+            for (int q = 0; q < kEpt; ++q) {
+                sx += (double)vr[vi][q].x * wr[q].x + (double)vr[vi][q].y * wr[q].y;
+                sy += (double)vr[vi][q].x * wr[q].y - (double)vr[vi][q].y * wr[q].x;
+            }
+            sx = wave_sum(sx);
+            sy = wave_sum(sy);
+            if (lane == 0) s_red[vi * kMaxWaves + wave] = dmk(sx, sy);
+        }
+        nout = NVR;
+    } else if (MODE == 0) {
         for (int vi = 0; vi < nv; ++vi) {
             const void* vp = (vi == 0) ? a.v0
                                        : (const void*)(reinterpret_cast<const C*>(a.vbase) + (long long)(vi - 1) * N);
@@ -1013,8 +1054,8 @@ __global__ __launch_bounds__(kStreamThreads) void k_zupdate_batch(const StreamAr
     zupdate_body<R>(args[i], g - offs[i]);
 }
 
-template <typename R, int MODE>
-__global__ __launch_bounds__(kStreamThreads) void k_cgs(StreamArgs a) { cgs_body<R, MODE>(a, (int)blockIdx.x); }
+template <typename R, int MODE, int NVR = 0>
+__global__ __launch_bounds__(kStreamThreads) void k_cgs(StreamArgs a) { cgs_body<R, MODE, false, NVR>(a, (int)blockIdx.x); }
 template <typename R, int MODE>
 __global__ __launch_bounds__(kStreamThreads) void k_cgs_batch(const StreamArgs* args, const int* offs, int count) {
     const int g = (int)blockIdx.x;
@@ -1236,8 +1277,25 @@ hipError_t launch_finish(const StreamArgs& a, hipStream_t s, const LaunchEvents*
     return launch_k(k_finish, dim3(1), dim3(kStreamThreads), 0, s, te, a);
 }
 
+// First update with nv basis vectors held in registers (nv <= kCgsRegMax)
+template <typename R>
+static hipError_t launch_cgs_reg(const StreamArgs& a, dim3 g, dim3 b, hipStream_t s, const LaunchEvents* te) {
+    switch (a.nv) {
+        case 1: return launch_k(k_cgs<R, 0, 1>, g, b, 0, s, te, a);
+        case 2: return launch_k(k_cgs<R, 0, 2>, g, b, 0, s, te, a);
+        case 3: return launch_k(k_cgs<R, 0, 3>, g, b, 0, s, te, a);
+        case 4: return launch_k(k_cgs<R, 0, 4>, g, b, 0, s, te, a);
+        default: return launch_k(k_cgs<R, 0, 5>, g, b, 0, s, te, a);
+    }
+}
+// (six vectors would spill: one workgroup per CU leaves 256 VGPRs, which
+// the basis values, w and the sums exceed)
+constexpr int kCgsRegMax = 5;
+
 hipError_t launch_cgs(int fp64, int mode, const StreamArgs& a, int blocks, hipStream_t s, const LaunchEvents* te) {
     const dim3 g(blocks), b(kStreamThreads);
+    if (mode == 0 && a.nv >= 1 && a.nv <= kCgsRegMax)
+        return fp64 ? launch_cgs_reg<double>(a, g, b, s, te) : launch_cgs_reg<float>(a, g, b, s, te);
     if (fp64)
         return mode == 0 ? launch_k(k_cgs<double, 0>, g, b, 0, s, te, a) : launch_k(k_cgs<double, 1>, g, b, 0, s, te, a);
     return mode == 0 ? launch_k(k_cgs<float, 0>, g, b, 0, s, te, a) : launch_k(k_cgs<float, 1>, g, b, 0, s, te, a);
