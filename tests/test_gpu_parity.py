@@ -51,8 +51,8 @@ def to_np(t):
     return t.cpu().numpy()
 
 
-OP_CASES = [(1, 1), (1, 3), (1, 7), (1, 15), (1, 63), (1, 1023),
-            (2, 1), (2, 3), (2, 7), (2, 31), (2, 127),
+OP_CASES = [(1, 1), (1, 3), (1, 7), (1, 15), (1, 63), (1, 255), (1, 511), (1, 1023),
+            (2, 1), (2, 3), (2, 7), (2, 31), (2, 127), (2, 255), (2, 511),
             (3, 1), (3, 3), (3, 7), (3, 15), (3, 31)]
 
 
