@@ -204,6 +204,23 @@ __device__ void reduce_partials(const double2* __restrict__ p, int ps, int nb, i
     __syncthreads();
 }
 
+// Complex update w -= c v and accumulation of conj(v) w as explicit fused
+// multiply-adds: the rounding is fixed by the source, not by the contraction
+// the compiler picks in each kernel, so every kernel that applies them (one
+// instance or a batch, register-held or streamed basis) rounds alike.
+__device__ __forceinline__ void cmsub(double& wx, double& wy, double2 c, double vx, double vy) {
+    wx = fma(-c.x, vx, wx);
+    wx = fma(c.y, vy, wx);
+    wy = fma(-c.x, vy, wy);
+    wy = fma(-c.y, vx, wy);
+}
+__device__ __forceinline__ void cdot_acc(double& sx, double& sy, double vx, double vy, double wx, double wy) {
+    sx = fma(vx, wx, sx);
+    sx = fma(vy, wy, sx);
+    sy = fma(vx, wy, sy);
+    sy = fma(-vy, wx, sy);
+}
+
 // Write this workgroup's partial of nv values: red[i * nw + w] holds the
 // wavefront sums (nw wavefronts); summed in wavefront order.
 __device__ void block_partial_write(const double2* red, int nv, double2* partials, int pstride, int blk) {
@@ -868,8 +885,7 @@ __device__ __forceinline__ void cgs_body(const StreamArgs& a, int blk) {
             const double2 c = s_coef[vi];
 #pragma unroll
             for (int q = 0; q < kEpt; ++q) {
-                wx[q] -= c.x * vr[vi][q].x - c.y * vr[vi][q].y;
-                wy[q] -= c.x * vr[vi][q].y + c.y * vr[vi][q].x;
+                cmsub(wx[q], wy[q], c, vr[vi][q].x, vr[vi][q].y);
             }
         }
     } else {
@@ -885,8 +901,7 @@ __device__ __forceinline__ void cgs_body(const StreamArgs& a, int blk) {
             }
 #pragma unroll
             for (int q = 0; q < kEpt; ++q) {
-                wx[q] -= c.x * v[q].x - c.y * v[q].y;
-                wy[q] -= c.x * v[q].y + c.y * v[q].x;
+                cmsub(wx[q], wy[q], c, v[q].x, v[q].y);
             }
         }
     }
@@ -898,7 +913,8 @@ __device__ __forceinline__ void cgs_body(const StreamArgs& a, int blk) {
         wr[q] = cm<R>(static_cast<R>(wx[q]), static_cast<R>(wy[q]));
         if (i < N) stc<R>(wp, i, wr[q]);
         else wr[q] = czero<C>();
-        nrm += (double)wr[q].x * wr[q].x + (double)wr[q].y * wr[q].y;
+        nrm = fma((double)wr[q].x, (double)wr[q].x, nrm);
+        nrm = fma((double)wr[q].y, (double)wr[q].y, nrm);
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int nout;
@@ -908,8 +924,7 @@ __device__ __forceinline__ void cgs_body(const StreamArgs& a, int blk) {
             double sx = 0.0, sy = 0.0;
 #pragma unroll
             for (int q = 0; q < kEpt; ++q) {
-                sx += (double)vr[vi][q].x * wr[q].x + (double)vr[vi][q].y * wr[q].y;
-                sy += (double)vr[vi][q].x * wr[q].y - (double)vr[vi][q].y * wr[q].x;
+                cdot_acc(sx, sy, vr[vi][q].x, vr[vi][q].y, wr[q].x, wr[q].y);
             }
             sx = wave_sum(sx);
             sy = wave_sum(sy);
@@ -929,8 +944,7 @@ __device__ __forceinline__ void cgs_body(const StreamArgs& a, int blk) {
             double sx = 0.0, sy = 0.0;
 #pragma unroll
             for (int q = 0; q < kEpt; ++q) {
-                sx += (double)v[q].x * wr[q].x + (double)v[q].y * wr[q].y;
-                sy += (double)v[q].x * wr[q].y - (double)v[q].y * wr[q].x;
+                cdot_acc(sx, sy, v[q].x, v[q].y, wr[q].x, wr[q].y);
             }
             sx = wave_sum(sx);
             sy = wave_sum(sy);
