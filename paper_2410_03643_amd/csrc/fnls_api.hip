@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <chrono>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -202,8 +203,7 @@ struct fnls_ctx {
     Layout lay{};
     HostStatus* hs = nullptr;       // pinned, device-written
     HostStatus* hs_dev = nullptr;
-    hipEvent_t ev[kEvents] = {};
-    hipEvent_t evp[kEvents] = {};   // after the first pass of an Arnoldi iteration
+    unsigned seq_base = 0;          // HostStatus::seq of this solve's configuration (reports follow it)
     int fuse = 0;                   // Givens step of iteration j in the first pass of j + 1
     int restart_cur = 0;            // restart length of the running cycle
     // optional per-launch timing (fnls_timing / fnls_timing_report)
@@ -448,10 +448,6 @@ int precond_front(fnls_ctx* c, bool fp64, int inm, const void* src, int basis_j,
         PassVariant v{cur_mode, ops, Z_NONE, OUT_LINE, FIN_WRITE};
         const bool launch = (part == 0) || (part == 1 ? npass == 0 : npass >= 1);
         int rc = launch ? run_pass(c, fp64, axis, v, a, g) : FNLS_OK;
-        if (rc == FNLS_OK && launch && npass == 0 && fused) {
-            hipError_t e = hipEventRecord(c->evp[basis_j % kEvents], c->stream);
-            if (e != hipSuccess) rc = set_err(c, FNLS_ERR_HIP, "hipEventRecord: %s", hipGetErrorString(e));
-        }
         cur_in = pingpong[pp];
         pp ^= 1;
         cur_mode = (fused && npass == 0) ? inm : IN_PLAIN;
@@ -748,11 +744,40 @@ int check_solve_ready(fnls_ctx* c) {
 }
 
 // Wait for event k and return a snapshot of the host status.
-int wait_status(fnls_ctx* c, hipEvent_t ev, HostStatus* out) {
-    hipError_t e = hipEventSynchronize(ev);
-    if (e != hipSuccess) return set_err(c, FNLS_ERR_HIP, "hipEventSynchronize: %s", hipGetErrorString(e));
-    std::memcpy(out, (const void*)c->hs, sizeof(HostStatus));
-    return FNLS_OK;
+// Wait until the device has reported the status after `target` iterations
+// in total (hs->total >= target) or the end of the solve, and copy it.  The
+// host polls the seqlock HostStatus::seq (reports of this solve carry values
+// in (seq_base, seq_base + kSeqStride)) instead of waiting on events: an
+// event record is a marker packet that leaves the device idle for several
+// microseconds between two kernels, and there were two per Arnoldi iteration.
+// After 20 ms without the report the stream is queried every 5 ms, so a
+// device error ends the wait, and so does a drained stream without the
+// awaited report.  (Not sooner: with a query every few microseconds the
+// kernel trace showed the same gap again, before every iteration's first pass.)
+constexpr unsigned kSeqStride = 1u << 24;
+
+int wait_report(fnls_ctx* c, int target, HostStatus* out) {
+    using clock = std::chrono::steady_clock;
+    bool drained = false;
+    auto next_query = clock::now() + std::chrono::milliseconds(20);
+    for (unsigned spin = 1;; ++spin) {
+        const unsigned s1 = __atomic_load_n(&c->hs->seq, __ATOMIC_ACQUIRE);
+        const unsigned rel = s1 - c->seq_base;
+        if ((s1 & 1u) == 0 && rel != 0 && rel < kSeqStride) {
+            std::memcpy(out, (const void*)c->hs, sizeof *out);
+            __atomic_thread_fence(__ATOMIC_ACQUIRE);
+            const unsigned s2 = __atomic_load_n(&c->hs->seq, __ATOMIC_RELAXED);
+            if (s1 == s2 && (out->total >= target || out->done)) return FNLS_OK;
+        }
+        if (drained) return set_err(c, FNLS_ERR_HIP, "the device finished without reporting iteration %d", target);
+        if ((spin & 1023u) == 0 && clock::now() >= next_query) {
+            const hipError_t q = hipStreamQuery(c->stream);
+            if (q == hipSuccess) drained = true;   // look once more: every write has landed
+            else if (q != hipErrorNotReady) return set_err(c, FNLS_ERR_HIP, "stream: %s", hipGetErrorString(q));
+            next_query = clock::now() + std::chrono::milliseconds(5);
+        }
+        __builtin_ia32_pause();
+    }
 }
 
 // One GMRES cycle (iterations until the device reports a stop), with up to
@@ -800,15 +825,12 @@ int run_cycle(fnls_ctx* c, bool fp64, Bufs& b, int restart, int lookahead, int t
             }
             int rc = arnoldi_step(c, fp64, b, issued, first_only ? 1 : 0);
             if (rc != FNLS_OK) return rc;
-            if (first_only) {
-                partial[issued] = 1;
-            } else {
-                HIPCHK(c, hipEventRecord(c->ev[issued % kEvents], c->stream));
-            }
+            if (first_only) partial[issued] = 1;
             ++issued;
         }
-        const bool via_next = c->fuse && waited + 1 < restart;
-        int rc = wait_status(c, via_next ? c->evp[(waited + 1) % kEvents] : c->ev[waited % kEvents], &hs);
+        // the status of iteration `waited` (with the fused Givens step it is
+        // written by the first pass of iteration waited + 1, already issued)
+        int rc = wait_report(c, total_before + waited + 1, &hs);
         if (rc != FNLS_OK) return rc;
         ++waited;
         if (hs.done) {
@@ -824,7 +846,6 @@ int run_cycle(fnls_ctx* c, bool fp64, Bufs& b, int restart, int lookahead, int t
         if (partial[waited]) {
             partial[waited] = 0;
             if ((rc = arnoldi_step(c, fp64, b, waited, 2)) != FNLS_OK) return rc;
-            HIPCHK(c, hipEventRecord(c->ev[waited % kEvents], c->stream));
         }
     }
     *total_after = hs.total;
@@ -850,8 +871,9 @@ void fill_info(fnls_ctx* c, fnls_info* info, int status) {
 int solve_impl(fnls_ctx* c, const fnls_c128* b, fnls_c128* x, const fnls_opts* o, fnls_info* info) {
     const bool fp64 = (o->precision == FNLS_FP64);
     const int restart = o->restart;
+    c->seq_base += kSeqStride;
     HIPCHK(c, launch_config(c->st(), fp64 ? o->tol : o->inner_tol, o->tol, restart, o->maxit,
-                            fp64 ? o->fixed_iters : 0, fp64 ? (1 << 30) : o->max_outer, c->stream));
+                            fp64 ? o->fixed_iters : 0, fp64 ? (1 << 30) : o->max_outer, c->seq_base, c->stream));
     StreamArgs s;
     std::memset(&s, 0, sizeof s);
     s.N = c->N;
@@ -895,6 +917,8 @@ int solve_impl(fnls_ctx* c, const fnls_c128* b, fnls_c128* x, const fnls_opts* o
         rc = cycle_final(c, fp64, bf, b, x, first);
         if (rc != FNLS_OK) return rc;
         first = 0;
+        // the residual's decision: a plain stream synchronisation (polling the
+        // status for it measured slower than this)
         HIPCHK(c, hipStreamSynchronize(c->stream));
         const HostStatus& hs = *c->hs;
         if (hs.nonfinite) {
@@ -980,18 +1004,6 @@ int fnls_create(fnls_ctx** out, int device, void* hip_stream) {
         delete c;
         return FNLS_ERR_HIP;
     }
-    for (int i = 0; i < kEvents; ++i) {
-        if (hipEventCreateWithFlags(&c->ev[i], hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&c->evp[i], hipEventDisableTiming) != hipSuccess) {
-            for (int k = 0; k <= i; ++k) {
-                if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
-                if (c->evp[k]) (void)hipEventDestroy(c->evp[k]);
-            }
-            (void)hipHostFree(c->hs);
-            delete c;
-            return FNLS_ERR_HIP;
-        }
-    }
     *out = c;
     return FNLS_OK;
 }
@@ -1000,10 +1012,6 @@ void fnls_destroy(fnls_ctx* c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
-    for (int i = 0; i < kEvents; ++i) {
-        if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
-        if (c->evp[i]) (void)hipEventDestroy(c->evp[i]);
-    }
     if (c->hs) (void)hipHostFree(c->hs);
     for (auto e : c->evpool) (void)hipEventDestroy(e);
     delete c;

@@ -51,7 +51,7 @@ struct GmresState {
 
 // Status mirrored into pinned host memory after every decision point.
 struct HostStatus {
-    unsigned seq;
+    unsigned seq;    // seqlock: odd while a report is written, else the last report's number
     int total;
     int stopped;     // 1: cycle stopped at this iteration
     int done;        // 1: whole solve finished

@@ -32,9 +32,18 @@ constexpr int kMaxWaves = kStreamThreads / 64;   // wavefronts of the streaming 
 // ---------------------------------------------------------------------------
 // status reporting
 // ---------------------------------------------------------------------------
+// The host polls hs->seq instead of waiting on events, so the status block
+// is published as a seqlock: seq is odd while the fields change and equals
+// st->seq (even) once they are complete.  Both seq stores are system-scope
+// atomics and the system-scope release orders the field stores between them,
+// so a host that reads the same even seq before and after copying the
+// fields holds one report, complete.
 __device__ void report(GmresState* st, HostStatus* hs, int stopped) {
-    st->seq += 1;
+    st->seq += 2;
     if (hs) {
+        const unsigned s = st->seq;
+        __hip_atomic_store(&hs->seq, s - 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __threadfence_system();
         hs->total = st->total;
         hs->stopped = stopped;
         hs->done = st->done;
@@ -46,10 +55,7 @@ __device__ void report(GmresState* st, HostStatus* hs, int stopped) {
         hs->relres = st->relres;
         hs->bnorm = st->bnorm;
         if (st->total >= 1 && st->total <= 64) hs->hist[st->total - 1] = st->hist[st->total - 1];
-        hs->seq = st->seq;
-        // no fence: the host reads this block only after waiting on an event
-        // recorded after this kernel, and kernel completion makes its writes
-        // to host memory visible
+        __hip_atomic_store(&hs->seq, s, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 
@@ -1020,7 +1026,7 @@ __device__ __forceinline__ void finish_body(const StreamArgs& a) {
 
 // Configure GMRES limits in the device state (single thread).
 __device__ __forceinline__ void config_one(GmresState* st, double tol, double outer_tol, int restart, int maxit,
-                                           int fixed_iters, int max_outer) {
+                                           int fixed_iters, int max_outer, unsigned seq0) {
     st->tol = tol;
     st->inner_tol0 = tol;
     st->outer_tol = outer_tol;
@@ -1029,6 +1035,7 @@ __device__ __forceinline__ void config_one(GmresState* st, double tol, double ou
     st->fixed_iters = fixed_iters;
     st->max_outer = max_outer;
     st->counter = 0;
+    st->seq = seq0;
     st->active = 0;
     st->done = 0;
 }
@@ -1038,13 +1045,13 @@ __device__ __forceinline__ void config_one(GmresState* st, double tol, double ou
 // workgroups of instance i form the block range [offs[i], offs[i+1]))
 // ---------------------------------------------------------------------------
 __global__ void k_config(GmresState* st, double tol, double outer_tol, int restart, int maxit, int fixed_iters,
-                         int max_outer) {
-    config_one(st, tol, outer_tol, restart, maxit, fixed_iters, max_outer);
+                         int max_outer, unsigned seq0) {
+    config_one(st, tol, outer_tol, restart, maxit, fixed_iters, max_outer, seq0);
 }
 __global__ void k_config_batch(const StreamArgs* args, int count, double tol, double outer_tol, int restart,
                                int maxit, int fixed_iters, int max_outer) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < count) config_one(args[i].st, tol, outer_tol, restart, maxit, fixed_iters, max_outer);
+    if (i < count) config_one(args[i].st, tol, outer_tol, restart, maxit, fixed_iters, max_outer, 0u);
 }
 
 __global__ void k_precond_setup(StreamArgs a) { precond_setup_body(a, (int)blockIdx.x, (int)gridDim.x); }
@@ -1326,9 +1333,9 @@ hipError_t launch_adjoint(const AdjointArgs& a, hipStream_t s, const LaunchEvent
 }
 
 hipError_t launch_config(GmresState* st, double tol, double outer_tol, int restart, int maxit, int fixed_iters,
-                         int max_outer, hipStream_t s) {
+                         int max_outer, unsigned seq0, hipStream_t s) {
     return launch_k(k_config, dim3(1), dim3(1), 0, s, nullptr, st, tol, outer_tol, restart, maxit, fixed_iters,
-                    max_outer);
+                    max_outer, seq0);
 }
 
 }  // namespace fnls

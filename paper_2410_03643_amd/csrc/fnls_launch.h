@@ -47,7 +47,8 @@ hipError_t launch_precond_setup_batch(const StreamArgs* args, const int* offs, i
 hipError_t launch_finish_batch(const StreamArgs* args, int count, hipStream_t s);   // one workgroup per instance
 hipError_t launch_config_batch(const StreamArgs* args, int count, double tol, double outer_tol, int restart,
                                int maxit, int fixed_iters, int max_outer, hipStream_t s);
+// seq0: first value of the status sequence (HostStatus::seq) for this solve
 hipError_t launch_config(GmresState* st, double tol, double outer_tol, int restart, int maxit, int fixed_iters,
-                         int max_outer, hipStream_t s);
+                         int max_outer, unsigned seq0, hipStream_t s);
 
 }  // namespace fnls

@@ -234,6 +234,27 @@ def test_lookahead_settings_agree_uneven_convergence(torch_dev, precision):
         assert abs(io.iters - its[0]) <= 1
 
 
+def test_status_sequence_across_solves(torch_dev):
+    """The host takes each Arnoldi iteration's status from a sequence number
+    the device publishes in pinned memory (no event per iteration).  Many
+    solves in a row on one context, alternating precision and restart length
+    (so with and without restarts), must repeat their iteration counts and
+    solutions bitwise."""
+    torch, dev = torch_dev
+    s, o, u, ut = make(torch_dev, 2, 63, -10, 10, 1.5, 2.0, 0.01)
+    b = s.rhs(ut)
+    ref = {}
+    for k in range(24):
+        key = (("fp64", "fp32_ir")[k % 2], (30, 3)[(k // 2) % 2])
+        x, info = s.solve(b, precision=key[0], restart=key[1])
+        assert info.status == 0
+        if key in ref:
+            assert info.iters == ref[key][1] and torch.equal(x, ref[key][0])
+        else:
+            ref[key] = (x.clone(), info.iters)
+    print({k: v[1] for k, v in ref.items()}, flush=True)
+
+
 def test_step_and_first_step(torch_dev):
     torch, dev = torch_dev
     d, n, lo, hi, alpha, rho, tau = 2, 63, -10.0, 10.0, 1.5, 2.0, 0.005
