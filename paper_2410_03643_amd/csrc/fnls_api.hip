@@ -644,13 +644,16 @@ int arnoldi_step(fnls_ctx* c, bool fp64, Bufs& b, int j, int part = 0) {
 // End of a cycle: x (+)= Ptilde^{-1} (sum_i y_i v_i).  FP64: the recomputed
 // residual r = b - A x follows in the same passes.  FP32 (IR): x is updated
 // in FP64 from the FP32 correction, then the FP64 residual chain runs.
-int cycle_final_passes(fnls_ctx* c, bool fp64, Bufs& b, const void* b64, void* x, int first);
+// guard 2: enqueued ahead of the stopping decision; every launch returns at
+// once unless the cycle has stopped by the time it runs.
+int cycle_final_passes(fnls_ctx* c, bool fp64, Bufs& b, const void* b64, void* x, int first, int guard);
 
-int cycle_final(fnls_ctx* c, bool fp64, Bufs& b, const void* b64, void* x, int first) {
-    int rc = cycle_final_passes(c, fp64, b, b64, x, first);
+int cycle_final(fnls_ctx* c, bool fp64, Bufs& b, const void* b64, void* x, int first, int guard = 0) {
+    int rc = cycle_final_passes(c, fp64, b, b64, x, first, guard);
     if (rc != FNLS_OK) return rc;
     StreamArgs s;
     std::memset(&s, 0, sizeof s);
+    s.check_active = guard;
     s.pin = c->at<double2>(c->lay.pr);
     s.pin_nb = pass_geo(c->d, c->n, 0, true, c->max_dyn_lds, c->pcfg).blocks;
     s.pin_stride = c->lay.pstride;
@@ -663,7 +666,7 @@ int cycle_final(fnls_ctx* c, bool fp64, Bufs& b, const void* b64, void* x, int f
     return run_finish(c, s, "finish.residual");
 }
 
-int cycle_final_passes(fnls_ctx* c, bool fp64, Bufs& b, const void* b64, void* x, int first) {
+int cycle_final_passes(fnls_ctx* c, bool fp64, Bufs& b, const void* b64, void* x, int first, int guard) {
     const int d = c->d;
     double2* r64 = c->at<double2>(c->lay.r64);
     float2* r32 = fp64 ? nullptr : c->at<float2>(c->lay.V);
@@ -672,6 +675,7 @@ int cycle_final_passes(fnls_ctx* c, bool fp64, Bufs& b, const void* b64, void* x
         // one line: x (+)= Ptilde^{-1} (V y) in a single pass (FP64: with the residual)
         Geo g = pass_geo(d, c->n, 0, fp64, c->max_dyn_lds, c->pcfg);
         PassArgs a = base_args(c, fp64, 0, g);
+        a.check_active = guard;
         a.v0 = b.v0;
         a.vbase = b.vbase;
         a.x64 = (double2*)x;
@@ -692,6 +696,7 @@ int cycle_final_passes(fnls_ctx* c, bool fp64, Bufs& b, const void* b64, void* x
     // FP64 residual r = b - A x (IR: with its complex64 copy as the next basis vector 0)
     Geo g = pass_geo(d, c->n, d - 1, true, c->max_dyn_lds, c->pcfg);
     PassArgs a = base_args(c, true, d - 1, g);
+    a.check_active = guard;
     a.in = x;
     a.cD = 1.0;
     a.ci = 1.0;
@@ -727,7 +732,7 @@ int cycle_final_passes(fnls_ctx* c, bool fp64, Bufs& b, const void* b64, void* x
     tmpl.r32 = r32;
     tmpl.ir = ir;
     tmpl.pout = c->at<double2>(c->lay.pr);
-    return toeplitz_tail(c, true, x, acc64, FIN_RESID, nullptr, tmpl, 0);
+    return toeplitz_tail(c, true, x, acc64, FIN_RESID, nullptr, tmpl, guard);
 }
 
 int check_ready(fnls_ctx* c) {
@@ -780,14 +785,24 @@ int wait_report(fnls_ctx* c, int target, HostStatus* out) {
     }
 }
 
+// Arguments of the end-of-cycle passes, for enqueueing them ahead.
+struct FinalArgs {
+    const void* b64;
+    void* x;
+    int first;
+};
+
 // One GMRES cycle (iterations until the device reports a stop), with up to
 // `lookahead` iterations enqueued beyond the one whose status is awaited.
 // Returns FNLS_OK and sets *done when the solve ended before the cycle
-// started (b == 0 or non-finite b).
+// started (b == 0 or non-finite b).  *final_issued = 1 when the end-of-cycle
+// passes (cycle_final) for the actual stop are already enqueued.
 int run_cycle(fnls_ctx* c, bool fp64, Bufs& b, int restart, int lookahead, int total_before, int* total_after,
-              int* done) {
+              int* done, const FinalArgs& fin, int* final_issued, HostStatus* stop_status) {
     int issued = 0, waited = 0;
+    int final_k = -1;   // cycle size for which the end-of-cycle passes are enqueued
     *done = 0;
+    *final_issued = 0;
     HostStatus hs;
     // first timing record of every issued iteration: launches of iterations
     // that the device skipped (issued ahead of the stopping decision) carry
@@ -817,7 +832,10 @@ int run_cycle(fnls_ctx* c, bool fp64, Bufs& b, int restart, int lookahead, int t
             if (issued >= 1 && partial[issued - 1]) break;
             rec_first.push_back(c->recs.size());
             bool first_only = false;
-            if (c->fuse && issued >= 1 && waited >= 1 && est_prev > 0.0 && tol_last > 0.0) {
+            // (a rate needs two estimates of this cycle: the drop from the
+            // initial residual to the first estimate is much steeper than
+            // later ones and predicted stops one iteration early)
+            if (c->fuse && issued >= 1 && waited >= 2 && est_prev > 0.0 && tol_last > 0.0) {
                 const double rate = est_last / est_prev;
                 double pred = est_last;
                 for (int k = waited; k < issued; ++k) pred *= rate;   // estimate of iteration issued - 1
@@ -825,7 +843,17 @@ int run_cycle(fnls_ctx* c, bool fp64, Bufs& b, int restart, int lookahead, int t
             }
             int rc = arnoldi_step(c, fp64, b, issued, first_only ? 1 : 0);
             if (rc != FNLS_OK) return rc;
-            if (first_only) partial[issued] = 1;
+            if (first_only) {
+                partial[issued] = 1;
+                // the predicted stop leaves a cycle of `issued` iterations:
+                // enqueue its end now, guarded, so the device need not wait
+                // for the host to see the stop (the launches return at once
+                // if the cycle goes on)
+                if (!c->timing) {
+                    if ((rc = cycle_final(c, fp64, b, fin.b64, fin.x, fin.first, 2)) != FNLS_OK) return rc;
+                    final_k = issued;
+                }
+            }
             ++issued;
         }
         // the status of iteration `waited` (with the fused Givens step it is
@@ -850,6 +878,8 @@ int run_cycle(fnls_ctx* c, bool fp64, Bufs& b, int restart, int lookahead, int t
     }
     *total_after = hs.total;
     c->cur_k = hs.total - total_before;   // iterations of this cycle
+    *final_issued = (c->cur_k == final_k) ? 1 : 0;
+    *stop_status = hs;
     unbill(c->cur_k);
     // let any speculative (inactive) iterations drain before the final passes
     return FNLS_OK;
@@ -899,13 +929,18 @@ int solve_impl(fnls_ctx* c, const fnls_c128* b, fnls_c128* x, const fnls_opts* o
     }
     int first = 1;
     int status = FNLS_OK;
-    int total = 0;   // iterations so far, as last reported by the device
+    int total = 0;        // iterations so far, as last reported by the device
+    bool ahead = false;   // this cycle was enqueued before the last residual's decision was seen
+    double relres_prev = 1.0;
     while (true) {
         Bufs bf = bufs(c, fp64, first ? (const void*)b : (const void*)c->at<double2>(c->lay.r64));
-        int done = 0;
-        int rc = run_cycle(c, fp64, bf, restart, std::max(0, o->lookahead), total, &total, &done);
+        int done = 0, final_issued = 0;
+        const FinalArgs fin{b, x, first};
+        HostStatus stop;
+        int rc = run_cycle(c, fp64, bf, restart, std::max(0, o->lookahead), total, &total, &done, fin,
+                           &final_issued, &stop);
         if (rc != FNLS_OK) return rc;
-        if (done) {
+        if (done && !ahead) {
             // b == 0 (x = 0) or non-finite b
             if (c->hs->nonfinite) return set_err(c, FNLS_ERR_NONFINITE, "non-finite value in b");
             HIPCHK(c, hipMemsetAsync(x, 0, (size_t)c->N * 16, c->stream));
@@ -914,9 +949,25 @@ int solve_impl(fnls_ctx* c, const fnls_c128* b, fnls_c128* x, const fnls_opts* o
             if (info) info->relres_true = 0.0;
             return FNLS_OK;
         }
-        rc = cycle_final(c, fp64, bf, b, x, first);
-        if (rc != FNLS_OK) return rc;
-        first = 0;
+        if (!done) {
+            if (!final_issued && (rc = cycle_final(c, fp64, bf, b, x, first)) != FNLS_OK) return rc;
+            first = 0;
+            // When the stop estimate leaves the outer tolerance clearly unmet
+            // (the recomputed residual tracks it: est relative to the cycle's
+            // reference norm, which in FP32-IR is the previous residual), the
+            // next cycle is enqueued at once.  Its launches return at once if
+            // the residual ends the solve after all, and its first status
+            // wait then returns that decision.
+            const double pred = stop.est * (fp64 ? 1.0 : relres_prev);
+            const bool more = pred > 8.0 * o->tol && stop.total < o->maxit && !stop.breakdown && !stop.nonfinite &&
+                              (fp64 ? o->fixed_iters == 0 : stop.outer + 1 < o->max_outer);
+            if (more) {
+                ahead = true;
+                relres_prev = pred;
+                continue;
+            }
+        }
+        ahead = false;
         // the residual's decision: a plain stream synchronisation (polling the
         // status for it measured slower than this)
         HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -932,6 +983,7 @@ int solve_impl(fnls_ctx* c, const fnls_c128* b, fnls_c128* x, const fnls_opts* o
                 status = (hs.relres < o->tol) ? FNLS_OK : FNLS_NOT_CONVERGED;
             break;
         }
+        relres_prev = hs.relres;
     }
     fill_info(c, info, status);
     return status;

@@ -114,7 +114,7 @@ struct PassArgs {
     int pstride;
     GmresState* st;
     HostStatus* hs;
-    int check_active;     // return at once if st->active == 0
+    int check_active;     // 1: return at once if st->active == 0; 2: unless st->active == 0
     int first_cycle;      // Z_XADD: 1 = set x (first correction), 0 = accumulate
     int zsum, z32;        // IN_COMBO: 1 = sum_k y_k z_k with z_k at vbase + k N (z32: complex64)
     int ir;               // FIN_RESID: 1 = refinement step of FP32-IR

@@ -59,6 +59,14 @@ __device__ void report(GmresState* st, HostStatus* hs, int stopped) {
     }
 }
 
+// check_active of a launch: 1 = it belongs to the running cycle (returns at
+// once after the cycle stopped); 2 = it closes the cycle and was enqueued
+// before the stop was known (returns at once unless the cycle has stopped).
+// Every workgroup reads st->active before any write to it in the same launch.
+__device__ __forceinline__ bool launch_skipped(int check_active, const GmresState* st) {
+    return check_active == 1 ? st->active == 0 : (check_active == 2 ? st->active != 0 : false);
+}
+
 __device__ __forceinline__ double2 dmk(double a, double b) { double2 r; r.x = a; r.y = b; return r; }
 __device__ __forceinline__ double2 ddiv(double2 a, double2 b) {
     const double den = b.x * b.x + b.y * b.y;
@@ -290,7 +298,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
     using C = cplx<R>;
     constexpr int kMaxEptLine = RMAX;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    if (a.check_active && a.st->active == 0) return;
+    if (launch_skipped(a.check_active, a.st)) return;
     // with a fused Givens step, logical block 0 (dispatched first, so it runs
     // beside the first round of line blocks) does it; line blocks follow
     const int blk = a.gfuse ? blk_in - 1 : blk_in;
@@ -836,7 +844,7 @@ __device__ __forceinline__ void cgs_body(const StreamArgs& a, int blk) {
     __shared__ double2 s_red[(kMaxRestart + 2) * kMaxWaves];
     __shared__ double2 s_tot[kMaxRestart + 2];
     __shared__ double2 s_coef[kMaxRestart + 1];
-    if (a.check_active && a.st->active == 0) return;
+    if (launch_skipped(a.check_active, a.st)) return;
     const long long N = a.N;
     int nv = a.nv;
     void* wp = a.w;
@@ -976,7 +984,7 @@ __device__ __forceinline__ void finish_body(const StreamArgs& a) {
     __shared__ double2 s_red[(kMaxRestart + 2) * kMaxWaves];
     __shared__ double2 s_tot[kMaxRestart + 2];
     GmresState* st = a.st;
-    if (a.check_active && st->active == 0) return;
+    if (launch_skipped(a.check_active, st)) return;
     const int nv = (a.mode == FIN_K_REDUCE) ? a.nv : 1;
     reduce_partials(a.pin, a.pin_stride, a.pin_nb, nv, s_tot, s_red);
     if (a.mode == FIN_K_REDUCE) {

@@ -255,6 +255,24 @@ def test_status_sequence_across_solves(torch_dev):
     print({k: v[1] for k, v in ref.items()}, flush=True)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_end_of_cycle_enqueued_ahead_matches(torch_dev, precision):
+    """Near a predicted stop the end-of-cycle passes are enqueued ahead,
+    guarded by the device's stop flag (not while per-launch timing is on).
+    With timing on and off, and over restart cycles of 3 where the prediction
+    is sometimes wrong, the results must be bitwise equal."""
+    torch, dev = torch_dev
+    s, o, u, ut = make(torch_dev, 2, 127, -10, 10, 1.3, 2.0, 0.02)
+    b = torch.from_numpy(inputs.random_field(u.shape, seed=23)).to(dev)
+    for restart in (30, 3):
+        x1, i1 = s.solve(b, tol=1e-12, restart=restart, precision=precision)
+        s.timing(True)
+        x2, i2 = s.solve(b, tol=1e-12, restart=restart, precision=precision)
+        s.timing(False)
+        assert i1.status == 0 and i1.iters == i2.iters and i1.outer_iters == i2.outer_iters
+        assert torch.equal(x1, x2)
+
+
 def test_step_and_first_step(torch_dev):
     torch, dev = torch_dev
     d, n, lo, hi, alpha, rho, tau = 2, 63, -10.0, 10.0, 1.5, 2.0, 0.005
