@@ -902,8 +902,6 @@ int solve_impl(fnls_ctx* c, const fnls_c128* b, fnls_c128* x, const fnls_opts* o
     const bool fp64 = (o->precision == FNLS_FP64);
     const int restart = o->restart;
     c->seq_base += kSeqStride;
-    HIPCHK(c, launch_config(c->st(), fp64 ? o->tol : o->inner_tol, o->tol, restart, o->maxit,
-                            fp64 ? o->fixed_iters : 0, fp64 ? (1 << 30) : o->max_outer, c->seq_base, c->stream));
     StreamArgs s;
     std::memset(&s, 0, sizeof s);
     s.N = c->N;
@@ -923,6 +921,13 @@ int solve_impl(fnls_ctx* c, const fnls_c128* b, fnls_c128* x, const fnls_opts* o
         f.pin_nb = stream_blocks(c->N);
         f.pin_stride = c->lay.pstride;
         f.mode = 0;
+        f.cfg_tol = fp64 ? o->tol : o->inner_tol;
+        f.cfg_outer_tol = o->tol;
+        f.cfg_restart = restart;
+        f.cfg_maxit = o->maxit;
+        f.cfg_fixed_iters = fp64 ? o->fixed_iters : 0;
+        f.cfg_max_outer = fp64 ? (1 << 30) : o->max_outer;
+        f.cfg_seq0 = c->seq_base;
         int rc0 = reduce_if_wide(c, f, 1);
         if (rc0 == FNLS_OK) rc0 = run_finish(c, f, "finish.prepare");
         if (rc0 != FNLS_OK) return rc0;

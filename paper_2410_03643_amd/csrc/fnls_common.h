@@ -157,6 +157,12 @@ struct StreamArgs {
     int mode;             // k_finish: FinishKind; k_zupdate: 1 = first correction (x = 0 before)
     int ir;               // k_finish residual decision: 1 = refinement step of FP32-IR
     double2* x64;         // k_zupdate: the iterate
+    // k_finish prepare: the solve's limits (GMRES tolerance, outer tolerance,
+    // restart, iteration cap, fixed iteration count, refinement steps) and
+    // the first value of the status sequence
+    double cfg_tol, cfg_outer_tol;
+    int cfg_restart, cfg_maxit, cfg_fixed_iters, cfg_max_outer;
+    unsigned cfg_seq0;
     // batched CGS launches: with dev_j set, j = st->j when the kernel starts,
     // nv = j + 1 and w is advanced by j * jw elements
     int dev_j;

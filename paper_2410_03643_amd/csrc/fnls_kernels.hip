@@ -974,6 +974,22 @@ __device__ __forceinline__ void cgs_body(const StreamArgs& a, int blk) {
     block_partial_write(s_red, nout, a.pout, a.pstride, blk);
 }
 
+// Configure GMRES limits in the device state (single thread).
+__device__ __forceinline__ void config_one(GmresState* st, double tol, double outer_tol, int restart, int maxit,
+                                           int fixed_iters, int max_outer, unsigned seq0) {
+    st->tol = tol;
+    st->inner_tol0 = tol;
+    st->outer_tol = outer_tol;
+    st->restart = restart;
+    st->maxit = maxit;
+    st->fixed_iters = fixed_iters;
+    st->max_outer = max_outer;
+    st->counter = 0;
+    st->seq = seq0;
+    st->active = 0;
+    st->done = 0;
+}
+
 // Scalar decision kernel (one workgroup): sums the producer's partials and
 //   FIN_K_PREPARE: initialises the GMRES state from ||b|| and reports;
 //   FIN_K_GIVENS:  finishes the Arnoldi step (Givens, stopping test);
@@ -1009,6 +1025,11 @@ __device__ __forceinline__ void finish_body(const StreamArgs& a) {
     }
     if (threadIdx.x != 0) return;
     if (a.mode == FIN_K_PREPARE) {
+        // a single solve's limits first (no separate configuration launch;
+        // batches configure their instances beforehand: cfg_restart = 0)
+        if (a.cfg_restart > 0)
+            config_one(st, a.cfg_tol, a.cfg_outer_tol, a.cfg_restart, a.cfg_maxit, a.cfg_fixed_iters,
+                       a.cfg_max_outer, a.cfg_seq0);
         const double bn = sqrt(s_tot[0].x);
         st->bnorm = bn;
         st->refnorm = bn;
@@ -1032,30 +1053,10 @@ __device__ __forceinline__ void finish_body(const StreamArgs& a) {
     }
 }
 
-// Configure GMRES limits in the device state (single thread).
-__device__ __forceinline__ void config_one(GmresState* st, double tol, double outer_tol, int restart, int maxit,
-                                           int fixed_iters, int max_outer, unsigned seq0) {
-    st->tol = tol;
-    st->inner_tol0 = tol;
-    st->outer_tol = outer_tol;
-    st->restart = restart;
-    st->maxit = maxit;
-    st->fixed_iters = fixed_iters;
-    st->max_outer = max_outer;
-    st->counter = 0;
-    st->seq = seq0;
-    st->active = 0;
-    st->done = 0;
-}
-
 // ---------------------------------------------------------------------------
 // kernel entry points: one instance, or many instances in one launch (the
 // workgroups of instance i form the block range [offs[i], offs[i+1]))
 // ---------------------------------------------------------------------------
-__global__ void k_config(GmresState* st, double tol, double outer_tol, int restart, int maxit, int fixed_iters,
-                         int max_outer, unsigned seq0) {
-    config_one(st, tol, outer_tol, restart, maxit, fixed_iters, max_outer, seq0);
-}
 __global__ void k_config_batch(const StreamArgs* args, int count, double tol, double outer_tol, int restart,
                                int maxit, int fixed_iters, int max_outer) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1340,10 +1341,5 @@ hipError_t launch_adjoint(const AdjointArgs& a, hipStream_t s, const LaunchEvent
     return launch_k(k_adjoint, dim3(blocks), dim3(256), 0, s, te, a);
 }
 
-hipError_t launch_config(GmresState* st, double tol, double outer_tol, int restart, int maxit, int fixed_iters,
-                         int max_outer, unsigned seq0, hipStream_t s) {
-    return launch_k(k_config, dim3(1), dim3(1), 0, s, nullptr, st, tol, outer_tol, restart, maxit, fixed_iters,
-                    max_outer, seq0);
-}
 
 }  // namespace fnls

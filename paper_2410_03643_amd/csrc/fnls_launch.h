@@ -24,7 +24,8 @@ hipError_t launch_pass(int fp64, const PassVariant& v, const PassArgs& a, int bl
                        const LaunchEvents* te = nullptr);
 hipError_t launch_precond_setup(const StreamArgs& a, int blocks, hipStream_t s, const LaunchEvents* te = nullptr);
 hipError_t launch_prepare(const StreamArgs& a, int blocks, hipStream_t s, const LaunchEvents* te = nullptr);
-// one workgroup: StreamArgs::mode = 0 prepare, 1 Givens, 2 residual (nv = 1 for IR), 3 reduce nv values
+// one workgroup: StreamArgs::mode = 0 prepare (configures the solve from the cfg_ fields), 1 Givens,
+// 2 residual (nv = 1 for IR), 3 reduce nv values
 hipError_t launch_finish(const StreamArgs& a, hipStream_t s, const LaunchEvents* te = nullptr);
 hipError_t launch_cgs(int fp64, int mode, const StreamArgs& a, int blocks, hipStream_t s,
                       const LaunchEvents* te = nullptr);
@@ -47,8 +48,5 @@ hipError_t launch_precond_setup_batch(const StreamArgs* args, const int* offs, i
 hipError_t launch_finish_batch(const StreamArgs* args, int count, hipStream_t s);   // one workgroup per instance
 hipError_t launch_config_batch(const StreamArgs* args, int count, double tol, double outer_tol, int restart,
                                int maxit, int fixed_iters, int max_outer, hipStream_t s);
-// seq0: first value of the status sequence (HostStatus::seq) for this solve
-hipError_t launch_config(GmresState* st, double tol, double outer_tol, int restart, int maxit, int fixed_iters,
-                         int max_outer, unsigned seq0, hipStream_t s);
 
 }  // namespace fnls
