@@ -273,6 +273,23 @@ def test_end_of_cycle_enqueued_ahead_matches(torch_dev, precision):
         assert torch.equal(x1, x2)
 
 
+def test_refinement_step_limit(torch_dev):
+    """FP32-IR with max_outer refinement steps: one step cannot reach 1e-10
+    (status NOT_CONVERGED after exactly one step, with the step's true
+    residual reported), while the default limit converges.  The next step is
+    never enqueued ahead past the limit."""
+    torch, dev = torch_dev
+    s, o, u, ut = make(torch_dev, 2, 127, -10, 10, 1.5, 2.0, 0.01)
+    b = s.rhs(ut)
+    x1, i1 = s.solve(b, precision="fp32_ir", max_outer=1)
+    assert i1.status == 1 and i1.outer_iters == 1 and 1e-10 < i1.relres_true < 1e-3
+    x2, i2 = s.solve(b, precision="fp32_ir")
+    assert i2.status == 0 and i2.outer_iters >= 2 and i2.relres_true < 1e-10
+    bn = to_np(b)
+    r = to_np(s.apply_A(x2)) - bn
+    assert np.linalg.norm(r) / np.linalg.norm(bn) < 1e-10
+
+
 def test_step_and_first_step(torch_dev):
     torch, dev = torch_dev
     d, n, lo, hi, alpha, rho, tau = 2, 63, -10.0, 10.0, 1.5, 2.0, 0.005
