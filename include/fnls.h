@@ -84,7 +84,7 @@ typedef enum {
 typedef struct {
     double tol;        /* relative residual ||b - A x|| / ||b|| to reach (default 1e-10) */
     int restart;       /* GMRES restart length m (default 30; <= workspace capacity)     */
-    int maxit;         /* total GMRES iterations allowed (default 2000, Sec. 5)          */
+    int maxit;         /* total GMRES iterations allowed (default 2000, Sec. 5; <= 2^21)  */
     int precision;     /* fnls_precision (default FNLS_FP64)                             */
     double inner_tol;  /* FNLS_FP32_IR: inner relative tolerance of the first refinement
                           step (default 1e-5); later steps stop at

@@ -796,9 +796,10 @@ struct FinalArgs {
 // `lookahead` iterations enqueued beyond the one whose status is awaited.
 // Returns FNLS_OK and sets *done when the solve ended before the cycle
 // started (b == 0 or non-finite b).  *final_issued = 1 when the end-of-cycle
-// passes (cycle_final) for the actual stop are already enqueued.
+// passes (cycle_final) for the actual stop are already enqueued.  `cycle`:
+// the number of cycles of this solve before this one (residuals reported).
 int run_cycle(fnls_ctx* c, bool fp64, Bufs& b, int restart, int lookahead, int total_before, int* total_after,
-              int* done, const FinalArgs& fin, int* final_issued, HostStatus* stop_status) {
+              int* done, const FinalArgs& fin, int* final_issued, HostStatus* stop_status, int cycle) {
     int issued = 0, waited = 0;
     int final_k = -1;   // cycle size for which the end-of-cycle passes are enqueued
     *done = 0;
@@ -861,6 +862,14 @@ int run_cycle(fnls_ctx* c, bool fp64, Bufs& b, int restart, int lookahead, int t
         int rc = wait_report(c, total_before + waited + 1, &hs);
         if (rc != FNLS_OK) return rc;
         ++waited;
+        if (hs.outer > cycle) {
+            // this cycle's end, enqueued behind its predicted stop, has run
+            // and reported the residual's decision before the host read the
+            // stop report: the cycle stopped where predicted
+            if (hs.total - total_before != final_k)
+                return set_err(c, FNLS_ERR_HIP, "status report of cycle %d out of order", cycle);
+            break;
+        }
         if (hs.done) {
             *done = 1;
             unbill(0);
@@ -937,13 +946,14 @@ int solve_impl(fnls_ctx* c, const fnls_c128* b, fnls_c128* x, const fnls_opts* o
     int total = 0;        // iterations so far, as last reported by the device
     bool ahead = false;   // this cycle was enqueued before the last residual's decision was seen
     double relres_prev = 1.0;
+    int cycle = 0;        // cycles of this solve whose end is enqueued
     while (true) {
         Bufs bf = bufs(c, fp64, first ? (const void*)b : (const void*)c->at<double2>(c->lay.r64));
         int done = 0, final_issued = 0;
         const FinalArgs fin{b, x, first};
         HostStatus stop;
         int rc = run_cycle(c, fp64, bf, restart, std::max(0, o->lookahead), total, &total, &done, fin,
-                           &final_issued, &stop);
+                           &final_issued, &stop, cycle);
         if (rc != FNLS_OK) return rc;
         if (done && !ahead) {
             // b == 0 (x = 0) or non-finite b
@@ -957,6 +967,9 @@ int solve_impl(fnls_ctx* c, const fnls_c128* b, fnls_c128* x, const fnls_opts* o
         if (!done) {
             if (!final_issued && (rc = cycle_final(c, fp64, bf, b, x, first)) != FNLS_OK) return rc;
             first = 0;
+            // the residual's decision may already be in (end enqueued ahead)
+            const bool decided = stop.outer > cycle;
+            ++cycle;
             // When the stop estimate leaves the outer tolerance clearly unmet
             // (the recomputed residual tracks it: est relative to the cycle's
             // reference norm, which in FP32-IR is the previous residual), the
@@ -964,11 +977,13 @@ int solve_impl(fnls_ctx* c, const fnls_c128* b, fnls_c128* x, const fnls_opts* o
             // the residual ends the solve after all, and its first status
             // wait then returns that decision.
             const double pred = stop.est * (fp64 ? 1.0 : relres_prev);
-            const bool more = pred > 8.0 * o->tol && stop.total < o->maxit && !stop.breakdown && !stop.nonfinite &&
-                              (fp64 ? o->fixed_iters == 0 : stop.outer + 1 < o->max_outer);
+            const bool more = decided ? (!stop.done && !stop.nonfinite)
+                                      : (pred > 8.0 * o->tol && stop.total < o->maxit && !stop.breakdown &&
+                                         !stop.nonfinite &&
+                                         (fp64 ? o->fixed_iters == 0 : stop.outer + 1 < o->max_outer));
             if (more) {
                 ahead = true;
-                relres_prev = pred;
+                relres_prev = decided ? stop.relres : pred;
                 continue;
             }
         }
@@ -1246,7 +1261,9 @@ static int resolve_opts(fnls_ctx* c, const fnls_opts* in, fnls_opts* o) {
     if (o->restart < 1 || o->restart > c->restart_cap)
         return set_err(c, FNLS_ERR_WORKSPACE, "restart %d exceeds the workspace capacity %d (or < 1)", o->restart,
                        c->restart_cap);
-    if (o->maxit < 1) return set_err(c, FNLS_ERR_INVALID_ARG, "maxit must be >= 1");
+    // (at most one status report per iteration plus one per cycle: a solve's
+    // reports stay inside its window of the status sequence)
+    if (o->maxit < 1 || o->maxit > (1 << 21)) return set_err(c, FNLS_ERR_INVALID_ARG, "maxit must lie in [1, 2^21]");
     if (o->precision != FNLS_FP64 && o->precision != FNLS_FP32_IR)
         return set_err(c, FNLS_ERR_INVALID_ARG, "unknown precision");
     if (o->precision == FNLS_FP32_IR) {

@@ -159,6 +159,24 @@ def test_nonfinite_rhs_is_reported(torch_dev):
     assert e.value.code == ERR_NONFINITE
 
 
+def test_option_limits_are_checked_before_any_work(torch_dev):
+    """maxit beyond 2^21 (the bound that keeps a solve's status reports inside
+    its window of the status sequence) and restart beyond the workspace are
+    rejected on the host; the context still solves afterwards."""
+    from paper_2410_03643_amd.fnls import FnlsError, ERR_INVALID_ARG, ERR_WORKSPACE
+    torch, dev = torch_dev
+    s, o, u, ut = make(torch_dev, 2, 31, -10, 10, 1.5, 2.0, 0.01)
+    b = s.rhs(ut)
+    with pytest.raises(FnlsError) as e:
+        s.solve(b, maxit=(1 << 21) + 1)
+    assert e.value.code == ERR_INVALID_ARG
+    with pytest.raises(FnlsError) as e:
+        s.solve(b, restart=31)
+    assert e.value.code == ERR_WORKSPACE
+    x, info = s.solve(b, maxit=1 << 21)
+    assert info.status == 0
+
+
 def test_exact_preconditioner_one_iteration(torch_dev):
     """alpha = 2, rho = 0: Ptilde = A, GMRES stops after one iteration."""
     torch, dev = torch_dev
