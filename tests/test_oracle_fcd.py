@@ -130,7 +130,7 @@ def test_lemma_eigenvalue_bounds(alpha, n):
     lo_x, hi_x = -3.0, 4.0
     h = (hi_x - lo_x) / (n + 1)
     dt = 0.05
-    mu = dt / h ** alpha
+    mu = fcd.mu(alpha, h, dt)
     _, _, theta, _ = fcd.tail_bounds(alpha, 3)
     c0 = math.gamma(alpha + 1) / math.gamma(alpha / 2 + 1) ** 2
     c2 = fcd.coefficients(alpha, 3)[2]
@@ -165,3 +165,37 @@ def test_tau_is_antisymmetric_part_of_circulant_embedding(alpha, n, mu):
     y = np.fft.ifft(np.fft.fft(col) * np.fft.fft(xe)).real[1:n + 1]
     ref = fcd.tau_T1(alpha, n, mu) @ x
     assert np.allclose(y, ref, atol=1e-12 * (1 + np.abs(ref).max()))
+
+
+@pytest.mark.parametrize("alpha", [1.2, 1.5, 1.8, 2.0])
+def test_mu_scales_T1_to_the_riesz_operator(alpha):
+    """mu = dt / h^alpha (Sec. 2.1, T_1 = mu T_0) makes T_1 u approximate
+    dt (-Laplacian)^(alpha/2) u, the operator whose Fourier symbol is
+    |omega|^alpha (the Riesz derivative the centred differences discretise,
+    with second-order accuracy).  Reference: numpy's FFT of a Gaussian on the
+    same grid, multiplied by |omega|^alpha (the Gaussian is ~e^-400 at the
+    ends, so the periodic transform sees the whole function).  mu is taken
+    from fcd.mu; a slip to dt/h^2, h^alpha/dt or dt h^alpha is off by a
+    factor 100 times the discretisation error or more (checked below), and the
+    error must shrink under refinement."""
+    lo, hi, dt = -20.0, 20.0, 0.01
+
+    def err(n, mu_of):
+        h = (hi - lo) / (n + 1)
+        x = lo + h * np.arange(1, n + 1)
+        u = np.exp(-x ** 2)
+        y = fcd.toeplitz_T1(alpha, n, mu_of(h)) @ u
+        w = 2 * np.pi * np.fft.fftfreq(n, h)
+        ref = dt * np.fft.ifft(np.abs(w) ** alpha * np.fft.fft(u)).real
+        centre = np.abs(x) < 5
+        return float(np.abs(y - ref)[centre].max() / np.abs(ref).max())
+
+    e1023 = err(1023, lambda h: fcd.mu(alpha, h, dt))
+    e511 = err(511, lambda h: fcd.mu(alpha, h, dt))
+    e2047 = err(2047, lambda h: fcd.mu(alpha, h, dt))
+    assert e1023 < 2e-3, e1023
+    assert e2047 < 0.5 * e511, (e511, e2047)
+    for slip in (lambda h: h ** alpha / dt, lambda h: dt * h ** alpha):
+        assert err(1023, slip) > 0.2
+    if alpha != 2.0:
+        assert err(1023, lambda h: dt / h ** 2) > 0.2
