@@ -1,10 +1,12 @@
 #!/usr/bin/env python3
 """Benchmark: preconditioned GMRES solves per second on one MI355X.
 
-Workload: the d = 2, n = 1023 system (1,046,529 complex unknowns) on
-[-10, 10]^2 with alpha = 1.5, rho = 2, dt = 0.01, u = sech(|x|) exp(i x_1)
+Workload (default): the d = 2, n = 1023 system (1,046,529 complex unknowns)
+on [-10, 10]^2 with alpha = 1.5, rho = 2, dt = 0.01, u = sech(|x|) exp(i x_1)
 plus 1e-3 complex noise (seed 0); right-preconditioned GMRES(30) with the
 sine-transform TBAN preconditioner (omega = 1), tolerance 1e-10.
+--workload d3: the d = 3, n = 255 system on [-8, 8]^3 (16,581,375 unknowns),
+alpha = 1.6, rho = 1, dt = 0.01 (profiling of the HBM-resident case).
 
 One step = one time-step solve of the whole hot path through the C ABI:
 preconditioner setup D = rho dt |u|^2, right-hand side b = (iI + T - D) u, and
@@ -12,10 +14,15 @@ the GMRES solve (FP64, or FP32 GMRES-IR with --precision fp32_ir; both are
 timed and reported).  The operator tables are assembled once before timing
 (they depend only on alpha, h, dt).  Inputs are resident in HBM.
 
-Prints one JSON line (rank 0, N = 1).  The "roofline" object is for the
-dominant kernel class of the headline precision, from HIP events bracketing
-each launch in a separate instrumented run of the same steps; "cpu_baseline"
-times the CPU oracle on a bounded sample of the same workload.
+Prints one JSON line (rank 0, N = 1).  "roofline" is for the dominant kernel
+class of the headline precision: its minimal algorithmic bytes per launch
+(each vector the method must move, charged once; the first Gram-Schmidt
+sweep to the pass that forms w) over its average launch duration from HIP
+events around each launch, in a separate instrumented run of the same
+steps; "step_roofline" does the same for the whole step.  "cpu_baseline"
+times the CPU oracle on a bounded sample of the same workload (all host
+threads and one thread), and in that leg the oracle's FP64 solution gives
+the GPU solutions' errors.
 """
 import argparse
 import csv
@@ -33,7 +40,9 @@ PEAK_HBM_GBS = 8000.0
 TOL = 1e-10
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 COPY_BYTES = 256 << 20
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pass64_toep_next_wdots_d2_n1023.txt")
+TRAFFIC_FILES = {"metric": os.path.join(ROOT, "profiles", "traffic_pass64_toep_next_wdots_d2_n1023.txt"),
+                 "d3": os.path.join(ROOT, "profiles", "traffic_pass64_toep_next_wdots_d3_n255.txt")}
+METRIC = "PGMRES solves/s at d=2 n=1023 (FP64 vs FP32-IR @1e-10); % HBM roofline"
 
 
 def log(msg):
@@ -56,6 +65,8 @@ def time_steps(torch, s, u, un, steps, precision):
 
 
 def kernel_profile(torch, s, u, un, steps, precision):
+    """Per kernel class over `steps` instrumented steps: launches, average
+    duration, minimal and multi-pass algorithmic bytes per launch."""
     s.timing(True)
     for _ in range(steps):
         s.step(u, u, out=un, tol=TOL, precision=precision)
@@ -63,11 +74,34 @@ def kernel_profile(torch, s, u, un, steps, precision):
     s.timing(False)
     for r in rep:
         r["avg_us"] = 1e3 * r["total_ms"] / r["launches"]
-        r["bytes_per_launch"] = r["bytes"] / r["launches"]
+        r["bytes_per_launch"] = r["bytes_min"] / r["launches"]
+        r["multipass_bytes_per_launch"] = r["bytes"] / r["launches"]
         r["gbs"] = r["bytes_per_launch"] / (r["avg_us"] * 1e-6) / 1e9
+        r["multipass_gbs"] = r["multipass_bytes_per_launch"] / (r["avg_us"] * 1e-6) / 1e9
         r["ms_per_step"] = r["total_ms"] / steps
     rep.sort(key=lambda r: -r["total_ms"])
     return rep
+
+
+def copy_bandwidth(torch, dev, nbytes=512 << 20, reps=10):
+    """Device-to-device copy rate (bytes read + written per second, GB/s) of a
+    plain torch copy of nbytes, best of `reps` event-timed copies."""
+    src = torch.ones(nbytes, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    best = None
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) / 1e3
+        best = t if best is None else min(best, t)
+    del src, dst
+    return 2.0 * nbytes / best / 1e9
 
 
 def source_hash():
@@ -93,12 +127,14 @@ def read_keyvals(path):
     return out
 
 
-def committed_traffic(timing_name):
-    """HBM bytes per launch of `timing_name` from the committed counter summary,
-    or None when there is none or the kernels changed since it was taken."""
-    if not os.path.exists(TRAFFIC_FILE):
+def committed_traffic(workload, timing_name):
+    """HBM bytes per launch of `timing_name` from the committed counter summary
+    of the workload, or None when there is none or the kernels changed since
+    it was taken."""
+    path = TRAFFIC_FILES[workload]
+    if not os.path.exists(path):
         return None
-    kv = read_keyvals(TRAFFIC_FILE)
+    kv = read_keyvals(path)
     if kv.get("timing_name") != timing_name or kv.get("source_sha256") != source_hash():
         return None
     return float(kv["hbm_bytes_per_launch"])
@@ -159,28 +195,54 @@ def summarize(dirs, timing_name, kernel_regex):
     print("\n".join(lines))
 
 
-def cpu_baseline(p, seconds):
-    import numpy as np  # noqa: F401
-    import oracle
+def cpu_model():
     try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:
-        cores = os.cpu_count() or 1
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(p, seconds, x64, x32):
+    """The oracle's own step (D, b, FP64 GMRES(30) to 1e-10, dense per-axis
+    operators) timed on the host's cores, with all BLAS threads and with one,
+    about `seconds` each; then the oracle's FP64 solution of the same system
+    to 1e-13, against which the GPU's FP64 and FP32-IR solutions (copied to
+    the host after the timed region) are measured."""
+    import numpy as np
+    import oracle
+    from threadpoolctl import threadpool_info, threadpool_limits
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     o = oracle.OracleSolver(p.alpha, p.rho, p.d, p.n, p.h, p.tau)
-    t0 = time.perf_counter()
-    count = 0
-    iters = None
-    while True:
-        _, info = o.step(p.u, p.u, tol=TOL)
-        count += 1
-        iters = info.iters
-        if time.perf_counter() - t0 >= seconds:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": count / dt, "unit": "solves/s", "cores": int(cores), "kind": "oracle",
-            "sample": "%d oracle time-step solves (D, b, FP64 GMRES(30) to 1e-10, %d iterations each) "
-                      "of the same d=2 n=1023 system, %.1f s" % (count, iters, dt)}
+
+    def timed(limit):
+        with threadpool_limits(limits=limit):
+            t0 = time.perf_counter()
+            count, iters = 0, None
+            while True:
+                _, info = o.step(p.u, p.u, tol=TOL)
+                count += 1
+                iters = info.iters
+                if time.perf_counter() - t0 >= seconds:
+                    break
+            return count, iters, time.perf_counter() - t0
+
+    n_all, it_all, t_all = timed(threads)
+    n_one, it_one, t_one = timed(1)
+    o.precond_setup(p.u)
+    b = o.rhs(p.u)
+    xo, _ = o.solve(b, tol=1e-13)
+    nx = float(np.linalg.norm(xo))
+    errs = {"fp64": float(np.linalg.norm(x64 - xo)) / nx, "fp32_ir": float(np.linalg.norm(x32 - xo)) / nx}
+    base = {"value": n_all / t_all, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
+            "value_1thread": n_one / t_one, "cpu_model": cpu_model(), "host_threads": os.cpu_count(),
+            "sample": "oracle time-step solves (D, b, FP64 GMRES(30) to 1e-10, %d iterations each) of the "
+                      "same %s system: %d in %.1f s on %d BLAS threads, %d in %.1f s on 1 thread"
+                      % (it_all, p.name, n_all, t_all, threads, n_one, t_one)}
+    return base, errs
 
 
 def main():
@@ -188,10 +250,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", choices=["metric", "d3"], default="metric",
+                    help="metric: d=2 n=1023 (the headline); d3: d=3 n=255 (profiling)")
     ap.add_argument("--precision", choices=["fp64", "fp32_ir"], default="fp64",
                     help="precision of the headline value (both are measured)")
     ap.add_argument("--profile-steps", type=int, default=20)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=8.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run three plain 256 MiB device copies (reference for HBM byte counters)")
@@ -224,7 +288,7 @@ def main():
         torch.cuda.synchronize()
         log("copy calibration: 3 x %d MiB device-to-device copies" % (COPY_BYTES >> 20))
         del src, dst
-    p = inputs.metric_case()
+    p = inputs.metric_case() if args.workload == "metric" else inputs.three_dim_case()
     log("workload %s: N=%d" % (p.name, p.N))
     s = Solver(p.alpha, p.rho, p.d, p.n, p.h, p.tau, device=dev, restart=30)
     u = torch.from_numpy(p.u).to(dev)
@@ -242,23 +306,39 @@ def main():
             % (prec, 1e3 * wall / args.steps, 1e3 * gpu / args.steps, info.iters,
                info.outer_iters, info.relres_true))
         assert info.status == 0 and info.relres_true < TOL, "solve did not reach the tolerance"
+        x_host = un.cpu().numpy()          # after the timed region
         log("%s: kernel profile over %d steps" % (prec, args.profile_steps))
         prof = kernel_profile(torch, s, u, un, args.profile_steps, prec)
-        results[prec] = dict(wall=wall, gpu=gpu, info=info, prof=prof)
+        results[prec] = dict(wall=wall, gpu=gpu, info=info, prof=prof, x=x_host)
+    copy_gbs = copy_bandwidth(torch, dev)
+    log("device copy: %.0f GB/s (read + write)" % copy_gbs)
 
     head = results[args.precision]
     other = "fp32_ir" if args.precision == "fp64" else "fp64"
     steps = args.steps
     dom = head["prof"][0]
-    traffic = committed_traffic(dom["name"])
+    traffic = committed_traffic(args.workload, dom["name"])
     roofline = {"bound": "hbm", "kernel": dom["name"], "achieved": round(dom["gbs"], 1),
                 "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(dom["gbs"] / PEAK_HBM_GBS, 4),
                 "traffic": None if traffic is None else int(traffic), "avg_us": round(dom["avg_us"], 2),
-                "bytes_per_launch": int(dom["bytes_per_launch"])}
-    total_bytes = sum(r["bytes"] for r in head["prof"]) / args.profile_steps
+                "bytes_per_launch": int(dom["bytes_per_launch"]),
+                "multipass_bytes_per_launch": int(dom["multipass_bytes_per_launch"]),
+                "multipass_achieved": round(dom["multipass_gbs"], 1),
+                "multipass_frac": round(dom["multipass_gbs"] / PEAK_HBM_GBS, 4),
+                "measured_copy_gbs": round(copy_gbs, 1),
+                "frac_of_measured_copy": round(dom["gbs"] / copy_gbs, 4)}
     step_ms = 1e3 * head["wall"] / steps
+    alg_step = sum(r["bytes_min"] for r in head["prof"]) / args.profile_steps
+    multi_step = sum(r["bytes"] for r in head["prof"]) / args.profile_steps
+    step_gbs = alg_step / (step_ms * 1e-3) / 1e9
+    step_roofline = {"alg_bytes": int(alg_step), "alg_bytes_per_unknown": round(alg_step / p.N, 1),
+                     "achieved": round(step_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(step_gbs / PEAK_HBM_GBS, 4),
+                     "ceiling_steps_per_s": round(PEAK_HBM_GBS * 1e9 / alg_step, 1),
+                     "multipass_bytes": int(multi_step)}
+    ws = "d=2 n=1023 [-10,10]^2 rho=2 dt=0.01" if args.workload == "metric" else "d=3 n=255 [-8,8]^3 rho=1 dt=0.01"
     out = {
-        "metric": "PGMRES solves/s at d=2 n=1023 (FP64 vs FP32-IR @1e-10); % HBM roofline",
+        "metric": METRIC if args.workload == "metric" else "PGMRES solves/s at d=3 n=255 (FP64 vs FP32-IR @1e-10)",
         "value": round(steps / head["wall"], 2),
         "unit": "solves/s",
         "n_gpus": 1,
@@ -270,31 +350,35 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": p.name + ": d=2 n=1023 [-10,10]^2 rho=2 dt=0.01, sech soliton + 1e-3 "
-                   "noise (seed 0), one time-step solve (setup + rhs + GMRES(30), tol 1e-10)",
-                   "d": 2, "n": 1023, "unknowns": p.N, "restart": 30, "tol": TOL,
+        "config": {"workload": p.name + ": " + ws + ", sech soliton + 1e-3 noise (seed 0), one time-step "
+                   "solve (setup + rhs + GMRES(30), tol 1e-10)",
+                   "d": p.d, "n": p.n, "unknowns": p.N, "restart": 30, "tol": TOL,
                    "precision": args.precision},
         "iters": head["info"].iters,
         "outer_iters": head["info"].outer_iters,
         "relres_true": head["info"].relres_true,
         "gpu_ms_per_step": round(1e3 * head["gpu"] / steps, 4),
-        "alg_bytes_per_step": int(total_bytes),
-        "alg_gbs_whole_step": round(total_bytes / (step_ms * 1e-3) / 1e9, 1),
         "roofline": roofline,
+        "step_roofline": step_roofline,
         other: {"value": round(steps / results[other]["wall"], 2),
                 "ms_per_step": round(1e3 * results[other]["wall"] / steps, 4),
                 "iters": results[other]["info"].iters,
                 "outer_iters": results[other]["info"].outer_iters,
                 "relres_true": results[other]["info"].relres_true,
                 "dominant_kernel": results[other]["prof"][0]["name"],
-                "dominant_gbs": round(results[other]["prof"][0]["gbs"], 1)},
+                "dominant_gbs": round(results[other]["prof"][0]["gbs"], 1),
+                "err_vs_fp64_oracle": None},
         "kernels": [{k: (round(v, 3) if isinstance(v, float) else v)
-                     for k, v in r.items() if k in ("name", "launches", "avg_us", "gbs", "ms_per_step")}
-                    for r in head["prof"][:8]],
+                     for k, v in r.items() if k in ("name", "launches", "avg_us", "gbs", "multipass_gbs",
+                                                    "ms_per_step")}
+                    for r in head["prof"][:10]],
     }
     if not args.no_cpu_baseline:
-        log("cpu baseline (oracle), ~%.0f s" % args.cpu_seconds)
-        out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
+        log("cpu baseline (oracle), ~%.0f s on all threads and ~%.0f s on one" % (args.cpu_seconds, args.cpu_seconds))
+        base, errs = cpu_baseline(p, args.cpu_seconds, results["fp64"]["x"], results["fp32_ir"]["x"])
+        out["cpu_baseline"] = base
+        out["err_vs_fp64_oracle"] = errs[args.precision]
+        out[other]["err_vs_fp64_oracle"] = errs[other]
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)

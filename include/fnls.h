@@ -62,6 +62,9 @@ typedef struct fnls_ctx fnls_ctx;
 /* One complex double: re, im (torch.complex128 element). */
 typedef struct { double re, im; } fnls_c128;
 
+/* One complex float: re, im (torch.complex64 element). */
+typedef struct { float re, im; } fnls_c64;
+
 typedef enum {
     FNLS_OK = 0,
     FNLS_NOT_CONVERGED = 1,     /* result written; info says how far it got    */
@@ -98,7 +101,11 @@ typedef struct {
                           Arnoldi iteration of all instances as one replay of a captured
                           hipGraph (see fnls_batch_create); 0 = direct launches (default).
                           Single-instance calls ignore it                                */
-    int reserved[3];
+    int poll_delay_us; /* testing aid (default 0): the host sleeps this many microseconds
+                          (at most 1e6) before each wait for an iteration's status, so
+                          that work enqueued ahead has run by the time it reads; results
+                          are the same with any value                                  */
+    int reserved[2];
 } fnls_opts;
 
 /* Result of a solve.  relres_hist[k] is the GMRES estimate |g_{k+1}|/||b||
@@ -128,6 +135,17 @@ void fnls_destroy(fnls_ctx *ctx);
  * `restart` (both precisions fit the same block).  0 for invalid sizes. */
 size_t fnls_workspace_bytes(int d, int n, int restart);
 
+/* Host-only check of fnls_assemble's arguments (Sec. 2.1: alpha in (1, 2],
+ * rho >= 0, h > 0, tau > 0; d in {1, 2, 3}; n + 1 a power of two, n <= 1023;
+ * a 256-byte aligned workspace of at least fnls_workspace_bytes(d, n, 1)
+ * bytes).  Touches no device and no context and never dereferences
+ * `workspace`.  Returns the status fnls_assemble gives for these arguments
+ * before any GPU work: FNLS_OK, FNLS_ERR_INVALID_ARG or FNLS_ERR_WORKSPACE.
+ * msg (may be NULL) receives the reason, at most msg_len bytes including the
+ * terminating NUL ("" when FNLS_OK).  fnls_assemble calls it first. */
+int fnls_check_assemble(double alpha, double rho, int d, int n, double h, double tau,
+                        const void *workspace, size_t workspace_bytes, char *msg, size_t msg_len);
+
 /* a1 -- Assemble the operator for one parameter set (Sec. 2.1, 2.2, 4):
  * fractional centred-difference coefficients c_k of order alpha in (1, 2],
  * mu = tau / h^alpha, the circulant-embedding symbol of T_1 and the
@@ -152,6 +170,16 @@ int fnls_apply_A(fnls_ctx *ctx, const fnls_c128 *x, fnls_c128 *y);
 /* a4 -- z = Ptilde^{-1} r, the complex form of the sine-transform TBAN
  * preconditioner (formula in the header comment).  r and z must not alias. */
 int fnls_apply_precond(fnls_ctx *ctx, const fnls_c128 *r, fnls_c128 *z);
+
+/* a3, a4 in the precision of the GMRES-IR inner solve: the same operators as
+ * fnls_apply_A and fnls_apply_precond on complex64 vectors (torch.complex64,
+ * same layout), computed by the complex64 transform kernels of the inner
+ * iteration with the FP32 copies of the tables and of D.  They let a caller
+ * (and the test-suite) check those kernels against an FP64 reference; their
+ * error is a few FP32 roundings per transform stage.  Same errors as the
+ * FP64 entry points; inputs and outputs must not alias. */
+int fnls_apply_A_c64(fnls_ctx *ctx, const fnls_c64 *x, fnls_c64 *y);
+int fnls_apply_precond_c64(fnls_ctx *ctx, const fnls_c64 *r, fnls_c64 *z);
 
 /* Right-hand side of the three-level scheme (Sec. 2.1, 2.2 multiplied by
  * 2 dt): b = (i I + T_d - D) u_prev, with D from the last precond_setup. */
@@ -277,7 +305,15 @@ typedef struct {
     char name[64];
     int launches;
     double total_ms;
-    double bytes;
+    double bytes;       /* every vector the launches read or wrote, once each      */
+    double bytes_min;   /* their share of the method's minimal traffic: each vector
+                           an operation (the preconditioned operator, a
+                           Gram-Schmidt step, the end-of-cycle update, apply_A,
+                           apply_precond, rhs, setup) must read or write, charged
+                           once to the launch that first touches it, the first
+                           sweep of the Gram-Schmidt dot products to the Arnoldi
+                           pass that forms w; intermediates between axis passes
+                           and the recomputed true residual cost nothing        */
 } fnls_kernel_stat;
 
 int fnls_timing(fnls_ctx *ctx, int enable);
@@ -302,6 +338,40 @@ int fnls_set_pass_config(fnls_ctx *ctx, int precision, int strided, int rmax, in
  * the contiguous and then of the strided axes; *best_ms (may be NULL) its
  * time per solve.  Uses the context's stream and workspace; returns when done. */
 int fnls_autotune(fnls_ctx *ctx, const fnls_c128 *b, int precision, int reps, int best[4], double *best_ms);
+
+/* Counters of the host's GMRES sequencing on one context (diagnostics and
+ * tests).  GMRES runs the Sec. 5 protocol; the host enqueues iterations
+ * ahead of their stopping decisions and reads each iteration's status from
+ * pinned memory.  A cycle is a GMRES(m) cycle in FP64 or a refinement step
+ * in FNLS_FP32_IR. */
+typedef struct {
+    long long solves;            /* solves run (fnls_solve, the steppers, reverse modes)     */
+    long long cycles;            /* cycles whose end was enqueued                            */
+    long long iterations;        /* Arnoldi iterations of those cycles                       */
+    long long stop_predictions;  /* iterations issued only up to their first pass because
+                                    the host predicted that their predecessor ends the cycle */
+    long long ends_ahead;        /* cycle ends enqueued ahead of such a prediction that the
+                                    device ran (the cycle stopped where predicted)           */
+    long long late_reads;        /* stop reports the residual's report of the same cycle had
+                                    already replaced when the host read them                 */
+    long long cycles_ahead;      /* cycles enqueued before the previous cycle's residual
+                                    decision was read                                        */
+    long long reserved;
+} fnls_host_stats;
+
+/* Copy the counters into *out (may be NULL); reset = 1 clears them afterwards. */
+int fnls_get_host_stats(fnls_ctx *ctx, fnls_host_stats *out, int reset);
+
+/* The host's rule for taking a status report from pinned memory, for tests
+ * that exercise the real code without a device.  Each solve's reports carry
+ * sequence values in (seq_base, seq_base + 2^24) modulo 2^32, odd while a
+ * report is being written.  A report copied between reading seq_before and
+ * seq_after is taken (returns 1) when seq_before is such a value, even,
+ * seq_after == seq_before, and the report covers the awaited total of
+ * iterations `target` (total >= target) or ends the solve (done != 0);
+ * otherwise 0. */
+int fnls_status_report_accepted(unsigned seq_base, unsigned seq_before, unsigned seq_after, int total,
+                                int done, int target);
 
 /* Last error message of this context ("" if none); valid until the next call. */
 const char *fnls_last_error(const fnls_ctx *ctx);

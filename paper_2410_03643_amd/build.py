@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfnls.so")
-SOURCES = ["fnls_kernels.hip", "fnls_api.hip"]
+SOURCES = ["fnls_pass64.hip", "fnls_pass32.hip", "fnls_kernels.hip", "fnls_api.hip"]
 ARCH = os.environ.get("FNLS_OFFLOAD_ARCH", "gfx950")
 
 
@@ -30,13 +30,17 @@ def build(verbose: bool = False, extra_flags=()) -> str:
              # given wrong results on MI355X with no error
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-I", os.path.join(ROOT, "include"), "-I", CSRC, *extra_flags]
-    for src in SOURCES:
+    procs = []
+    for src in SOURCES:   # the translation units compile in parallel
         obj = os.path.join(CSRC, src.replace(".hip", ".o"))
         cmd = [hipcc(), *flags, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        procs.append((subprocess.Popen(cmd), cmd))
         objs.append(obj)
+    failed = [cmd for p, cmd in procs if p.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, failed[0])
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:

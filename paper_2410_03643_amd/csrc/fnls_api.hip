@@ -10,6 +10,7 @@
 #include <chrono>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/fnls.h"
@@ -130,12 +131,47 @@ int stream_blocks(long long N) {
 }
 
 struct Layout {
-    size_t tw64, tw32, syme64, symo64, lam64, syme32, symo32, lam32;
-    size_t state, p1, p2, p3, pr, px, D64, D32;
-    size_t t1, t2, Z, acc, r64, bbuf, adj, V;
+    // operator region (offsets from the context's workspace): tables, the
+    // diagonal, the stepper's right-hand side and the adjoint solution
+    size_t tw64, tw32, syme64, symo64, lam64, syme32, symo32, lam32, D64, D32, bbuf, adj;
+    size_t op_total;
+    // solver scratch (offsets from the scratch base, which follows the
+    // operator region in the workspace): GMRES state, partial sums, work
+    // vectors, the preconditioned basis Z and the Krylov basis V
+    size_t state, p1, p2, p3, pr, px, t1, t2, Z, acc, r64, V;
+    size_t scr_total;
     size_t total;
     int pstride;
 };
+
+// Solver scratch of one restart length (offsets from the scratch base).
+void scratch_layout(Layout& l, int d, int n, int restart) {
+    const long long N = ipow(n, d);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    l.state = take(sizeof(GmresState));
+    // partial sums: at most one workgroup per line (any pass configuration)
+    // or per streaming chunk
+    const int pmax = (int)std::max<long long>(stream_blocks(N), ipow(n, d - 1));
+    l.pstride = pmax;
+    const size_t pwide = (size_t)(kMaxRestart + 2) * pmax * 16;
+    l.p1 = take(pwide);
+    l.p2 = take(pwide);
+    l.p3 = take((size_t)pmax * 16);
+    l.pr = take((size_t)pmax * 16);
+    l.px = take((size_t)(kMaxRestart + 2) * 16);
+    l.t1 = take((size_t)N * 16);
+    l.t2 = take((size_t)N * 16);
+    l.Z = take((size_t)N * 16 * restart);   // preconditioned basis z_j = P^{-1} v_j
+    l.acc = take((size_t)N * 16);
+    l.r64 = take((size_t)N * 16);
+    l.V = take((size_t)N * 16 * restart);
+    l.scr_total = off;
+}
 
 Layout make_layout(int d, int n, int restart) {
     Layout l;
@@ -155,28 +191,13 @@ Layout make_layout(int d, int n, int restart) {
     l.syme32 = take((size_t)m * 4);
     l.symo32 = take((size_t)m * 4);
     l.lam32 = take((size_t)m * 4);
-    l.state = take(sizeof(GmresState));
-    // partial sums: at most one workgroup per line (any pass configuration)
-    // or per streaming chunk
-    const int pmax = (int)std::max<long long>(stream_blocks(N), ipow(n, d - 1));
-    l.pstride = pmax;
-    const size_t pwide = (size_t)(kMaxRestart + 2) * pmax * 16;
-    l.p1 = take(pwide);
-    l.p2 = take(pwide);
-    l.p3 = take((size_t)pmax * 16);
-    l.pr = take((size_t)pmax * 16);
-    l.px = take((size_t)(kMaxRestart + 2) * 16);
     l.D64 = take((size_t)N * 8);
     l.D32 = take((size_t)N * 4);
-    l.t1 = take((size_t)N * 16);
-    l.t2 = take((size_t)N * 16);
-    l.Z = take((size_t)N * 16 * restart);   // preconditioned basis z_j = P^{-1} v_j
-    l.acc = take((size_t)N * 16);
-    l.r64 = take((size_t)N * 16);
     l.bbuf = take((size_t)N * 16);
     l.adj = take((size_t)N * 16);   // adjoint solution (reverse mode)
-    l.V = take((size_t)N * 16 * restart);
-    l.total = off;
+    l.op_total = off;
+    scratch_layout(l, d, n, restart);
+    l.total = l.op_total + l.scr_total;
     return l;
 }
 
@@ -200,17 +221,21 @@ struct fnls_ctx {
     // workspace
     char* ws = nullptr;
     size_t ws_bytes = 0;
+    char* scr = nullptr;            // solver scratch base (ws + lay.op_total, or the static scratch)
     Layout lay{};
     HostStatus* hs = nullptr;       // pinned, device-written
     HostStatus* hs_dev = nullptr;
     unsigned seq_base = 0;          // HostStatus::seq of this solve's configuration (reports follow it)
     int fuse = 0;                   // Givens step of iteration j in the first pass of j + 1
     int restart_cur = 0;            // restart length of the running cycle
+    int poll_delay_us = 0;          // testing aid: the host sleeps before each status wait
+    fnls_host_stats stats{};        // host sequencing counters (fnls_get_host_stats)
     // optional per-launch timing (fnls_timing / fnls_timing_report)
     struct TimingRec {
         int cls;
         LaunchEvents ev;
-        double bytes;
+        double bytes;       // every vector the launch reads or writes, once each
+        double bytes_min;   // the launch's share of the method's minimal traffic
     };
     int timing = 0;
     std::vector<TimingRec> recs;
@@ -220,8 +245,9 @@ struct fnls_ctx {
     int cur_k = 0;   // basis size of the combination being formed (byte accounting)
     PassConfig pcfg = default_pass_config();
 
-    template <typename T> T* at(size_t off) { return reinterpret_cast<T*>(ws + off); }
-    GmresState* st() { return at<GmresState>(lay.state); }
+    template <typename T> T* at(size_t off) { return reinterpret_cast<T*>(ws + off); }      // operator region
+    template <typename T> T* sc(size_t off) { return reinterpret_cast<T*>(scr + off); }     // solver scratch
+    GmresState* st() { return sc<GmresState>(lay.state); }
 };
 
 static int set_err(fnls_ctx* c, int code, const char* fmt, ...) {
@@ -266,13 +292,14 @@ int class_id(fnls_ctx* c, const std::string& name) {
 
 // Start a timing record for the next launch: returns the events the runtime
 // records at that kernel's start and end, or nullptr when timing is off.
-const LaunchEvents* timing_begin(fnls_ctx* c, const std::string& name, double bytes) {
+const LaunchEvents* timing_begin(fnls_ctx* c, const std::string& name, double bytes, double bytes_min) {
     if (!c->timing) return nullptr;
     fnls_ctx::TimingRec r;
     r.cls = class_id(c, name);
     r.ev.start = pool_event(c);
     r.ev.stop = pool_event(c);
     r.bytes = bytes;
+    r.bytes_min = bytes_min;
     if (!r.ev.start || !r.ev.stop) return nullptr;
     c->recs.push_back(r);
     return &c->recs.back().ev;
@@ -317,7 +344,7 @@ PassArgs base_args(fnls_ctx* c, bool fp64, int axis, const Geo& g) {
     a.D = fp64 ? (const void*)c->at<double>(c->lay.D64) : (const void*)c->at<float>(c->lay.D32);
     a.tscale = c->tscale;
     a.omega = c->omega;
-    a.pout = c->at<double2>(c->lay.p1);
+    a.pout = c->sc<double2>(c->lay.p1);
     a.pstride = c->lay.pstride;
     a.st = c->st();
     a.hs = c->hs_dev;
@@ -359,6 +386,35 @@ double pass_bytes(fnls_ctx* c, bool fp64, const PassVariant& v, const PassArgs& 
     return b;
 }
 
+// The launch's share of the method's minimal traffic: every vector the
+// operation (preconditioned operator, Gram-Schmidt step, end-of-cycle update,
+// apply_A / apply_precond / rhs) must read or write, charged once, to the
+// launch that first touches it.  Intermediates between the axis passes of
+// one operation (the ping-pong vectors, the accumulator, the stored z_j) and
+// the later axes' re-reads of the operand cost nothing; the Arnoldi pass
+// with the first dot products carries the write of w, one read of w and the
+// first sweep over the basis; the recomputed true residual is outside the
+// minimal model.
+bool intermediate(fnls_ctx* c, const void* p) {
+    const char* q = reinterpret_cast<const char*>(p);
+    const size_t v = (size_t)c->N * 16;
+    auto in = [&](size_t off, size_t len) { return q >= c->scr + off && q < c->scr + off + len; };
+    return in(c->lay.t1, v) || in(c->lay.t2, v) || in(c->lay.acc, v) || in(c->lay.Z, c->lay.V - c->lay.Z);
+}
+
+double pass_bytes_min(fnls_ctx* c, bool fp64, const PassVariant& v, const PassArgs& a) {
+    const double N = (double)c->N, e = fp64 ? 16.0 : 8.0, dsz = fp64 ? 8.0 : 4.0;
+    double b = 0.0;
+    if (v.inm == IN_COMBO) b += c->cur_k * (a.zsum ? (a.z32 ? 8.0 : 16.0) : e) * N;
+    else if (v.outm != OUT_ACC_NEXT && a.in && !intermediate(c, a.in)) b += e * N;
+    if ((v.ops & P_SCALE) || v.outm == OUT_ACC_FIRST) b += dsz * N;
+    if (v.zm == Z_XSET) b += 16.0 * N;
+    if (v.zm == Z_XADD) b += (a.first_cycle ? 16.0 : 32.0) * N;
+    if (v.fin == FIN_WRITE && a.out && !intermediate(c, a.out)) b += e * N;
+    if (v.fin == FIN_WDOTS) b += 2.0 * e * N + (a.basis_j + 1) * e * N;
+    return b;
+}
+
 // Dynamic LDS of a pass: passes without the Toeplitz product keep one
 // buffer per line (the sine transform needs one FFT buffer); at least 4 KB
 // (the fused Givens workgroup stages its column there).
@@ -378,7 +434,8 @@ int run_pass(fnls_ctx* c, bool fp64, int axis, PassVariant v, PassArgs& a, const
     v.rmax = g.rmax;
     const size_t lds = pass_lds(g, c->m, fp64, (v.ops & P_TOEP) != 0);
     line_layout(c->m, g.L, fp64, (v.ops & P_TOEP) != 0, &a.pa, &a.ls);
-    const LaunchEvents* te = c->timing ? timing_begin(c, pass_name(fp64, v, axis), pass_bytes(c, fp64, v, a)) : nullptr;
+    const LaunchEvents* te = c->timing ? timing_begin(c, pass_name(fp64, v, axis), pass_bytes(c, fp64, v, a),
+                                                         pass_bytes_min(c, fp64, v, a)) : nullptr;
     hipError_t e = launch_pass(fp64 ? 1 : 0, v, a, g.blocks + (a.gfuse ? 1 : 0), lds, c->stream, te);
     if (e != hipSuccess) timing_failed(c, te);
     if (e != hipSuccess)
@@ -398,15 +455,15 @@ struct Bufs {
 
 Bufs bufs(fnls_ctx* c, bool fp64, const void* v0_fp64) {
     Bufs b;
-    b.t1 = c->at<char>(c->lay.t1);
-    b.t2 = c->at<char>(c->lay.t2);
-    b.zbase = c->at<char>(c->lay.Z);
-    b.acc = c->at<char>(c->lay.acc);
+    b.t1 = c->sc<char>(c->lay.t1);
+    b.t2 = c->sc<char>(c->lay.t2);
+    b.zbase = c->sc<char>(c->lay.Z);
+    b.acc = c->sc<char>(c->lay.acc);
     if (fp64) {
         b.v0 = const_cast<void*>(v0_fp64);
-        b.vbase = c->at<char>(c->lay.V);
+        b.vbase = c->sc<char>(c->lay.V);
     } else {
-        float2* V32 = c->at<float2>(c->lay.V);
+        float2* V32 = c->sc<float2>(c->lay.V);
         b.v0 = V32;
         b.vbase = V32 + c->N;
     }
@@ -441,7 +498,7 @@ int precond_front(fnls_ctx* c, bool fp64, int inm, const void* src, int basis_j,
         a.check_active = check_active;
         if (npass == 0 && givens) {
             a.gfuse = 1;
-            a.gpin = c->at<double2>(c->lay.p3);
+            a.gpin = c->sc<double2>(c->lay.p3);
             a.gpin_nb = stream_blocks(c->N);
             a.gpin_stride = c->lay.pstride;
         }
@@ -476,6 +533,7 @@ int toeplitz_tail(fnls_ctx* c, bool fp64, const void* x, void* acc, int fin, voi
         a.acc_in = acc;
         a.cT = -1.0;
         a.check_active = check_active;
+        a.guard_k = tmpl.guard_k;
         const bool last = (ax == 0);
         a.out = last ? final_out : acc;
         int f = last ? fin : FIN_WRITE;
@@ -494,37 +552,42 @@ int toeplitz_tail(fnls_ctx* c, bool fp64, const void* x, void* acc, int fin, voi
     return FNLS_OK;
 }
 
-// y = (cD D + i ci I + cT T_d) x, all FP64 (used by apply_A and rhs).
-int matvec64(fnls_ctx* c, const void* x, void* y, double cD, double ci, double cT) {
+// y = (cD D + i ci I + cT T_d) x in the precision of fp64 (complex128 or
+// complex64 vectors; used by apply_A, rhs and the complex64 apply_A).
+int matvec(fnls_ctx* c, bool fp64, const void* x, void* y, double cD, double ci, double cT) {
     const int d = c->d;
-    Geo g = pass_geo(d, c->n, d - 1, true, c->max_dyn_lds, c->pcfg);
-    PassArgs a = base_args(c, true, d - 1, g);
+    Geo g = pass_geo(d, c->n, d - 1, fp64, c->max_dyn_lds, c->pcfg);
+    PassArgs a = base_args(c, fp64, d - 1, g);
     a.in = x;
     a.cD = cD;
     a.ci = ci;
     a.cT = cT;
-    a.out = (d == 1) ? y : c->at<char>(c->lay.acc);
+    a.out = (d == 1) ? y : c->sc<char>(c->lay.acc);
     PassVariant v{IN_PLAIN, P_TOEP, Z_NONE, OUT_ACC_FIRST, FIN_WRITE};
-    int rc = run_pass(c, true, d - 1, v, a, g);
+    int rc = run_pass(c, fp64, d - 1, v, a, g);
     if (rc != FNLS_OK || d == 1) return rc;
-    void* acc = c->at<char>(c->lay.acc);
+    void* acc = c->sc<char>(c->lay.acc);
     for (int ax = d - 2; ax >= 0; --ax) {
-        Geo g2 = pass_geo(d, c->n, ax, true, c->max_dyn_lds, c->pcfg);
-        PassArgs a2 = base_args(c, true, ax, g2);
+        Geo g2 = pass_geo(d, c->n, ax, fp64, c->max_dyn_lds, c->pcfg);
+        PassArgs a2 = base_args(c, fp64, ax, g2);
         a2.in = x;
         a2.acc_in = acc;
         a2.cT = cT;
         a2.out = (ax == 0) ? y : acc;
         PassVariant v2{IN_PLAIN, P_TOEP, Z_NONE, OUT_ACC_NEXT, FIN_WRITE};
-        rc = run_pass(c, true, ax, v2, a2, g2);
+        rc = run_pass(c, fp64, ax, v2, a2, g2);
         if (rc != FNLS_OK) return rc;
     }
     return FNLS_OK;
 }
 
+int matvec64(fnls_ctx* c, const void* x, void* y, double cD, double ci, double cT) {
+    return matvec(c, true, x, y, cD, ci, cT);
+}
+
 // One-workgroup decision / reduction kernel (k_finish).
 int run_finish(fnls_ctx* c, const StreamArgs& s, const char* name) {
-    const LaunchEvents* te = c->timing ? timing_begin(c, name, 16.0 * s.pin_nb) : nullptr;
+    const LaunchEvents* te = c->timing ? timing_begin(c, name, 16.0 * s.pin_nb, 0.0) : nullptr;
     hipError_t e = launch_finish(s, c->stream, te);
     if (e != hipSuccess) timing_failed(c, te);
     if (e != hipSuccess) return set_err(c, FNLS_ERR_HIP, "finish launch failed: %s", hipGetErrorString(e));
@@ -539,10 +602,10 @@ int reduce_if_wide(fnls_ctx* c, StreamArgs& s, int nv) {
     StreamArgs r = s;
     r.mode = 3;
     r.nv = nv;
-    r.pout = c->at<double2>(c->lay.px);
+    r.pout = c->sc<double2>(c->lay.px);
     int rc = run_finish(c, r, "finish.reduce");
     if (rc != FNLS_OK) return rc;
-    s.pin = c->at<double2>(c->lay.px);
+    s.pin = c->sc<double2>(c->lay.px);
     s.pin_nb = 1;
     s.pin_stride = 1;
     return FNLS_OK;
@@ -611,29 +674,32 @@ int arnoldi_step(fnls_ctx* c, bool fp64, Bufs& b, int j, int part = 0) {
     const int blocks = stream_blocks(c->N);
     const double esz_d = fp64 ? 16.0 : 8.0;
     const double cgs_bytes = (2.0 + (j + 1)) * esz_d * (double)c->N;
+    // minimal model: three sweeps over the basis with w read once per sweep
+    // and written once (the first sweep is in the Arnoldi pass)
+    const double dots_min = (1.0 + (j + 1)) * esz_d * (double)c->N;
     // first Gram-Schmidt update (consumes the dots of the last pass)
-    s.pin = c->at<double2>(c->lay.p1);
+    s.pin = c->sc<double2>(c->lay.p1);
     s.pin_nb = nb1;
     s.pin_stride = c->lay.pstride;
     if ((rc = reduce_if_wide(c, s, j + 2)) != FNLS_OK) return rc;
-    s.pout = c->at<double2>(c->lay.p2);
-    const LaunchEvents* te = c->timing ? timing_begin(c, fp64 ? "cgs64.update_dots" : "cgs32.update_dots", cgs_bytes) : nullptr;
+    s.pout = c->sc<double2>(c->lay.p2);
+    const LaunchEvents* te = c->timing ? timing_begin(c, fp64 ? "cgs64.update_dots" : "cgs32.update_dots", cgs_bytes, dots_min) : nullptr;
     hipError_t e = launch_cgs(fp64 ? 1 : 0, 0, s, blocks, c->stream, te);
     if (e != hipSuccess) timing_failed(c, te);
     if (e != hipSuccess) return set_err(c, FNLS_ERR_HIP, "cgs launch failed: %s", hipGetErrorString(e));
     // second update (reorthogonalisation)
-    s.pin = c->at<double2>(c->lay.p2);
+    s.pin = c->sc<double2>(c->lay.p2);
     s.pin_nb = blocks;
     s.pin_stride = c->lay.pstride;
     if ((rc = reduce_if_wide(c, s, j + 1)) != FNLS_OK) return rc;
-    s.pout = c->at<double2>(c->lay.p3);
-    te = c->timing ? timing_begin(c, fp64 ? "cgs64.update_norm" : "cgs32.update_norm", cgs_bytes) : nullptr;
+    s.pout = c->sc<double2>(c->lay.p3);
+    te = c->timing ? timing_begin(c, fp64 ? "cgs64.update_norm" : "cgs32.update_norm", cgs_bytes, cgs_bytes) : nullptr;
     e = launch_cgs(fp64 ? 1 : 0, 1, s, blocks, c->stream, te);
     if (e != hipSuccess) timing_failed(c, te);
     if (e != hipSuccess) return set_err(c, FNLS_ERR_HIP, "cgs launch failed: %s", hipGetErrorString(e));
     // Givens step and stopping decision (fused: in the next iteration's first pass)
     if (c->fuse && d >= 2 && j + 1 < c->restart_cur) return FNLS_OK;
-    s.pin = c->at<double2>(c->lay.p3);
+    s.pin = c->sc<double2>(c->lay.p3);
     s.pin_nb = blocks;
     s.pin_stride = c->lay.pstride;
     if ((rc = reduce_if_wide(c, s, 1)) != FNLS_OK) return rc;
@@ -645,16 +711,20 @@ int arnoldi_step(fnls_ctx* c, bool fp64, Bufs& b, int j, int part = 0) {
 // residual r = b - A x follows in the same passes.  FP32 (IR): x is updated
 // in FP64 from the FP32 correction, then the FP64 residual chain runs.
 // guard 2: enqueued ahead of the stopping decision; every launch returns at
-// once unless the cycle has stopped by the time it runs.
-int cycle_final_passes(fnls_ctx* c, bool fp64, Bufs& b, const void* b64, void* x, int first, int guard);
+// once unless, by the time it runs, the cycle has stopped with guard_k basis
+// vectors (the stop the host predicted).
+int cycle_final_passes(fnls_ctx* c, bool fp64, Bufs& b, const void* b64, void* x, int first, int guard,
+                       int guard_k);
 
-int cycle_final(fnls_ctx* c, bool fp64, Bufs& b, const void* b64, void* x, int first, int guard = 0) {
-    int rc = cycle_final_passes(c, fp64, b, b64, x, first, guard);
+int cycle_final(fnls_ctx* c, bool fp64, Bufs& b, const void* b64, void* x, int first, int guard = 0,
+                int guard_k = 0) {
+    int rc = cycle_final_passes(c, fp64, b, b64, x, first, guard, guard_k);
     if (rc != FNLS_OK) return rc;
     StreamArgs s;
     std::memset(&s, 0, sizeof s);
     s.check_active = guard;
-    s.pin = c->at<double2>(c->lay.pr);
+    s.guard_k = guard_k;
+    s.pin = c->sc<double2>(c->lay.pr);
     s.pin_nb = pass_geo(c->d, c->n, 0, true, c->max_dyn_lds, c->pcfg).blocks;
     s.pin_stride = c->lay.pstride;
     s.pstride = c->lay.pstride;
@@ -666,16 +736,18 @@ int cycle_final(fnls_ctx* c, bool fp64, Bufs& b, const void* b64, void* x, int f
     return run_finish(c, s, "finish.residual");
 }
 
-int cycle_final_passes(fnls_ctx* c, bool fp64, Bufs& b, const void* b64, void* x, int first, int guard) {
+int cycle_final_passes(fnls_ctx* c, bool fp64, Bufs& b, const void* b64, void* x, int first, int guard,
+                       int guard_k) {
     const int d = c->d;
-    double2* r64 = c->at<double2>(c->lay.r64);
-    float2* r32 = fp64 ? nullptr : c->at<float2>(c->lay.V);
+    double2* r64 = c->sc<double2>(c->lay.r64);
+    float2* r32 = fp64 ? nullptr : c->sc<float2>(c->lay.V);
     int rc;
     if (d == 1) {
         // one line: x (+)= Ptilde^{-1} (V y) in a single pass (FP64: with the residual)
         Geo g = pass_geo(d, c->n, 0, fp64, c->max_dyn_lds, c->pcfg);
         PassArgs a = base_args(c, fp64, 0, g);
         a.check_active = guard;
+        a.guard_k = guard_k;
         a.v0 = b.v0;
         a.vbase = b.vbase;
         a.x64 = (double2*)x;
@@ -686,7 +758,7 @@ int cycle_final_passes(fnls_ctx* c, bool fp64, Bufs& b, const void* b64, void* x
             a.cT = -1.0;
             a.b64 = (const double2*)b64;
             a.r64 = r64;
-            a.pout = c->at<double2>(c->lay.pr);
+            a.pout = c->sc<double2>(c->lay.pr);
             PassVariant v{IN_COMBO, P_DST1 | P_DIV | P_DST2 | P_SCALE | P_TOEP, Z_XADD, OUT_ACC_FIRST, FIN_RESID};
             return run_pass(c, true, 0, v, a, g);
         }
@@ -697,6 +769,7 @@ int cycle_final_passes(fnls_ctx* c, bool fp64, Bufs& b, const void* b64, void* x
     Geo g = pass_geo(d, c->n, d - 1, true, c->max_dyn_lds, c->pcfg);
     PassArgs a = base_args(c, true, d - 1, g);
     a.check_active = guard;
+    a.guard_k = guard_k;
     a.in = x;
     a.cD = 1.0;
     a.ci = 1.0;
@@ -707,7 +780,7 @@ int cycle_final_passes(fnls_ctx* c, bool fp64, Bufs& b, const void* b64, void* x
         a.r64 = r64;
         a.r32 = r32;
         a.ir = ir;
-        a.pout = c->at<double2>(c->lay.pr);
+        a.pout = c->sc<double2>(c->lay.pr);
         PassVariant v{IN_PLAIN, P_TOEP, Z_NONE, OUT_ACC_FIRST, FIN_RESID};
         return run_pass(c, true, 0, v, a, g);
     }
@@ -715,7 +788,7 @@ int cycle_final_passes(fnls_ctx* c, bool fp64, Bufs& b, const void* b64, void* x
     // x (+)= sum_k y_k z_k over the preconditioned basis stored by the Arnoldi
     // passes (equal to Ptilde^{-1} (V y) by linearity), in FP64, and takes the
     // new x as its Toeplitz operand
-    void* acc64 = c->at<char>(c->lay.acc);
+    void* acc64 = c->sc<char>(c->lay.acc);
     a.out = acc64;
     a.in = nullptr;
     a.zsum = 1;
@@ -731,7 +804,8 @@ int cycle_final_passes(fnls_ctx* c, bool fp64, Bufs& b, const void* b64, void* x
     tmpl.r64 = r64;
     tmpl.r32 = r32;
     tmpl.ir = ir;
-    tmpl.pout = c->at<double2>(c->lay.pr);
+    tmpl.pout = c->sc<double2>(c->lay.pr);
+    tmpl.guard_k = guard_k;
     return toeplitz_tail(c, true, x, acc64, FIN_RESID, nullptr, tmpl, guard);
 }
 
@@ -761,18 +835,33 @@ int check_solve_ready(fnls_ctx* c) {
 // kernel trace showed the same gap again, before every iteration's first pass.)
 constexpr unsigned kSeqStride = 1u << 24;
 
+// A published sequence value of the current solve: even (complete) and in
+// (seq_base, seq_base + kSeqStride), modulo 2^32.
+bool seq_in_window(unsigned seq_base, unsigned s) {
+    const unsigned rel = s - seq_base;
+    return (s & 1u) == 0 && rel != 0 && rel < kSeqStride;
+}
+
+// The host takes a copied report when the sequence value read before the
+// copy is a complete report of this solve, the value read after it is the
+// same (no report was written in between), and the report covers the
+// awaited iteration total (or ends the solve).
+bool report_accepted(unsigned seq_base, unsigned s1, unsigned s2, int total, int done, int target) {
+    return seq_in_window(seq_base, s1) && s1 == s2 && (total >= target || done != 0);
+}
+
 int wait_report(fnls_ctx* c, int target, HostStatus* out) {
     using clock = std::chrono::steady_clock;
+    if (c->poll_delay_us > 0) std::this_thread::sleep_for(std::chrono::microseconds(c->poll_delay_us));
     bool drained = false;
     auto next_query = clock::now() + std::chrono::milliseconds(20);
     for (unsigned spin = 1;; ++spin) {
         const unsigned s1 = __atomic_load_n(&c->hs->seq, __ATOMIC_ACQUIRE);
-        const unsigned rel = s1 - c->seq_base;
-        if ((s1 & 1u) == 0 && rel != 0 && rel < kSeqStride) {
+        if (seq_in_window(c->seq_base, s1)) {
             std::memcpy(out, (const void*)c->hs, sizeof *out);
             __atomic_thread_fence(__ATOMIC_ACQUIRE);
             const unsigned s2 = __atomic_load_n(&c->hs->seq, __ATOMIC_RELAXED);
-            if (s1 == s2 && (out->total >= target || out->done)) return FNLS_OK;
+            if (report_accepted(c->seq_base, s1, s2, out->total, out->done, target)) return FNLS_OK;
         }
         if (drained) return set_err(c, FNLS_ERR_HIP, "the device finished without reporting iteration %d", target);
         if ((spin & 1023u) == 0 && clock::now() >= next_query) {
@@ -812,7 +901,7 @@ int run_cycle(fnls_ctx* c, bool fp64, Bufs& b, int restart, int lookahead, int t
     auto unbill = [&](int active) {
         if (!c->timing) return;
         for (int i = std::max(0, active); i < issued; ++i)
-            for (size_t r = rec_first[i]; r < c->recs.size(); ++r) c->recs[r].bytes = 0.0;
+            for (size_t r = rec_first[i]; r < c->recs.size(); ++r) c->recs[r].bytes = c->recs[r].bytes_min = 0.0;
     };
     // fused Givens: the status of iteration j is written by the first pass of
     // iteration j + 1, which the lookahead has issued before the wait
@@ -846,12 +935,14 @@ int run_cycle(fnls_ctx* c, bool fp64, Bufs& b, int restart, int lookahead, int t
             if (rc != FNLS_OK) return rc;
             if (first_only) {
                 partial[issued] = 1;
+                ++c->stats.stop_predictions;
                 // the predicted stop leaves a cycle of `issued` iterations:
                 // enqueue its end now, guarded, so the device need not wait
                 // for the host to see the stop (the launches return at once
-                // if the cycle goes on)
+                // unless the cycle stops with exactly that many: with more
+                // than one iteration in flight an earlier one may stop it)
                 if (!c->timing) {
-                    if ((rc = cycle_final(c, fp64, b, fin.b64, fin.x, fin.first, 2)) != FNLS_OK) return rc;
+                    if ((rc = cycle_final(c, fp64, b, fin.b64, fin.x, fin.first, 2, issued)) != FNLS_OK) return rc;
                     final_k = issued;
                 }
             }
@@ -868,6 +959,7 @@ int run_cycle(fnls_ctx* c, bool fp64, Bufs& b, int restart, int lookahead, int t
             // stop report: the cycle stopped where predicted
             if (hs.total - total_before != final_k)
                 return set_err(c, FNLS_ERR_HIP, "status report of cycle %d out of order", cycle);
+            ++c->stats.late_reads;
             break;
         }
         if (hs.done) {
@@ -888,6 +980,8 @@ int run_cycle(fnls_ctx* c, bool fp64, Bufs& b, int restart, int lookahead, int t
     *total_after = hs.total;
     c->cur_k = hs.total - total_before;   // iterations of this cycle
     *final_issued = (c->cur_k == final_k) ? 1 : 0;
+    c->stats.iterations += c->cur_k;
+    c->stats.ends_ahead += *final_issued;
     *stop_status = hs;
     unbill(c->cur_k);
     // let any speculative (inactive) iterations drain before the final passes
@@ -911,22 +1005,25 @@ int solve_impl(fnls_ctx* c, const fnls_c128* b, fnls_c128* x, const fnls_opts* o
     const bool fp64 = (o->precision == FNLS_FP64);
     const int restart = o->restart;
     c->seq_base += kSeqStride;
+    c->poll_delay_us = o->poll_delay_us;
+    ++c->stats.solves;
     StreamArgs s;
     std::memset(&s, 0, sizeof s);
     s.N = c->N;
     s.b64 = reinterpret_cast<const double2*>(b);
-    s.r32 = fp64 ? nullptr : c->at<float2>(c->lay.V);
-    s.pout = c->at<double2>(c->lay.pr);
+    s.r32 = fp64 ? nullptr : c->sc<float2>(c->lay.V);
+    s.pout = c->sc<double2>(c->lay.pr);
     s.pstride = c->lay.pstride;
     s.st = c->st();
     s.hs = c->hs_dev;
     {
-        const LaunchEvents* te = c->timing ? timing_begin(c, "prepare", (fp64 ? 16.0 : 24.0) * (double)c->N) : nullptr;
+        const LaunchEvents* te = c->timing ? timing_begin(c, "prepare", (fp64 ? 16.0 : 24.0) * (double)c->N,
+                                                              (fp64 ? 16.0 : 24.0) * (double)c->N) : nullptr;
         hipError_t e = launch_prepare(s, stream_blocks(c->N), c->stream, te);
         if (e != hipSuccess) timing_failed(c, te);
         if (e != hipSuccess) return set_err(c, FNLS_ERR_HIP, "prepare launch failed: %s", hipGetErrorString(e));
         StreamArgs f = s;
-        f.pin = c->at<double2>(c->lay.pr);
+        f.pin = c->sc<double2>(c->lay.pr);
         f.pin_nb = stream_blocks(c->N);
         f.pin_stride = c->lay.pstride;
         f.mode = 0;
@@ -948,7 +1045,7 @@ int solve_impl(fnls_ctx* c, const fnls_c128* b, fnls_c128* x, const fnls_opts* o
     double relres_prev = 1.0;
     int cycle = 0;        // cycles of this solve whose end is enqueued
     while (true) {
-        Bufs bf = bufs(c, fp64, first ? (const void*)b : (const void*)c->at<double2>(c->lay.r64));
+        Bufs bf = bufs(c, fp64, first ? (const void*)b : (const void*)c->sc<double2>(c->lay.r64));
         int done = 0, final_issued = 0;
         const FinalArgs fin{b, x, first};
         HostStatus stop;
@@ -966,6 +1063,7 @@ int solve_impl(fnls_ctx* c, const fnls_c128* b, fnls_c128* x, const fnls_opts* o
         }
         if (!done) {
             if (!final_issued && (rc = cycle_final(c, fp64, bf, b, x, first)) != FNLS_OK) return rc;
+            ++c->stats.cycles;
             first = 0;
             // the residual's decision may already be in (end enqueued ahead)
             const bool decided = stop.outer > cycle;
@@ -982,6 +1080,7 @@ int solve_impl(fnls_ctx* c, const fnls_c128* b, fnls_c128* x, const fnls_opts* o
                                          !stop.nonfinite &&
                                          (fp64 ? o->fixed_iters == 0 : stop.outer + 1 < o->max_outer));
             if (more) {
+                ++c->stats.cycles_ahead;
                 ahead = true;
                 relres_prev = decided ? stop.relres : pred;
                 continue;
@@ -1091,18 +1190,36 @@ void fnls_destroy(fnls_ctx* c) {
 
 const char* fnls_last_error(const fnls_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
+int fnls_check_assemble(double alpha, double rho, int d, int n, double h, double tau, const void* workspace,
+                        size_t workspace_bytes, char* msg, size_t msg_len) {
+    auto fail = [&](int code, const char* what, size_t need = 0) {
+        if (msg && msg_len > 0) {
+            if (need) snprintf(msg, msg_len, "%s (need %zu bytes for restart 1)", what, need);
+            else snprintf(msg, msg_len, "%s", what);
+        }
+        return code;
+    };
+    if (msg && msg_len > 0) msg[0] = 0;
+    if (!(alpha > 1.0 && alpha <= 2.0)) return fail(FNLS_ERR_INVALID_ARG, "alpha must lie in (1, 2]");
+    if (!(rho >= 0.0) || !std::isfinite(rho)) return fail(FNLS_ERR_INVALID_ARG, "rho must be finite and >= 0");
+    if (d < 1 || d > 3) return fail(FNLS_ERR_INVALID_ARG, "d must be 1, 2 or 3");
+    if (!valid_n(n)) return fail(FNLS_ERR_INVALID_ARG, "n + 1 must be a power of two and n <= 1023");
+    if (!(h > 0.0) || !std::isfinite(h)) return fail(FNLS_ERR_INVALID_ARG, "h must be finite and > 0");
+    if (!(tau > 0.0) || !std::isfinite(tau)) return fail(FNLS_ERR_INVALID_ARG, "tau must be finite and > 0");
+    if (!workspace) return fail(FNLS_ERR_WORKSPACE, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
+        return fail(FNLS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    if (make_layout(d, n, 1).total > workspace_bytes)
+        return fail(FNLS_ERR_WORKSPACE, "workspace too small", make_layout(d, n, 1).total);
+    return FNLS_OK;
+}
+
 int fnls_assemble(fnls_ctx* c, double alpha, double rho, int d, int n, double h, double tau, void* workspace,
                   size_t workspace_bytes) {
     if (!c) return FNLS_ERR_INVALID_ARG;
-    if (!(alpha > 1.0 && alpha <= 2.0)) return set_err(c, FNLS_ERR_INVALID_ARG, "alpha must lie in (1, 2]");
-    if (!(rho >= 0.0) || !std::isfinite(rho)) return set_err(c, FNLS_ERR_INVALID_ARG, "rho must be finite and >= 0");
-    if (d < 1 || d > 3) return set_err(c, FNLS_ERR_INVALID_ARG, "d must be 1, 2 or 3");
-    if (!valid_n(n)) return set_err(c, FNLS_ERR_INVALID_ARG, "n + 1 must be a power of two and n <= 1023");
-    if (!(h > 0.0) || !std::isfinite(h)) return set_err(c, FNLS_ERR_INVALID_ARG, "h must be finite and > 0");
-    if (!(tau > 0.0) || !std::isfinite(tau)) return set_err(c, FNLS_ERR_INVALID_ARG, "tau must be finite and > 0");
-    if (!workspace) return set_err(c, FNLS_ERR_WORKSPACE, "workspace is NULL");
-    if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
-        return set_err(c, FNLS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    char why[256];
+    const int chk = fnls_check_assemble(alpha, rho, d, n, h, tau, workspace, workspace_bytes, why, sizeof why);
+    if (chk != FNLS_OK) return set_err(c, chk, "%s", why);
     // largest restart length that fits
     int cap = 0;
     for (int r = kMaxRestart; r >= 1; --r) {
@@ -1111,8 +1228,6 @@ int fnls_assemble(fnls_ctx* c, double alpha, double rho, int d, int n, double h,
             break;
         }
     }
-    if (cap < 1) return set_err(c, FNLS_ERR_WORKSPACE, "workspace too small (need %zu bytes for restart 1)",
-                                make_layout(d, n, 1).total);
     HIPCHK(c, hipSetDevice(c->device));
     c->alpha = alpha;
     c->rho = rho;
@@ -1126,6 +1241,7 @@ int fnls_assemble(fnls_ctx* c, double alpha, double rho, int d, int n, double h,
     c->ws_bytes = workspace_bytes;
     c->restart_cap = cap;
     c->lay = make_layout(d, n, cap);
+    c->scr = c->ws + c->lay.op_total;
     c->tscale = 1.0;
     c->have_D = 0;
 
@@ -1172,7 +1288,7 @@ int fnls_assemble(fnls_ctx* c, double alpha, double rho, int d, int n, double h,
     HIPCHK(c, hipMemcpyAsync(c->at<void>(c->lay.syme32), se32.data(), m * 4, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->at<void>(c->lay.symo32), so32.data(), m * 4, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->at<void>(c->lay.lam32), lam32.data(), m * 4, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemsetAsync(c->at<void>(c->lay.state), 0, sizeof(GmresState), c->stream));
+    HIPCHK(c, hipMemsetAsync(c->sc<void>(c->lay.state), 0, sizeof(GmresState), c->stream));
     // the host vectors above go out of scope: finish the copies first
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->assembled = 1;
@@ -1190,7 +1306,7 @@ static int precond_setup_scaled(fnls_ctx* c, const fnls_c128* u, const double* V
     s.rho = c->rho;
     s.tau = tau;
     const int blocks = (int)std::min<long long>(4096, (c->N + 255) / 256);
-    const LaunchEvents* te = c->timing ? timing_begin(c, "precond_setup", 28.0 * (double)c->N) : nullptr;
+    const LaunchEvents* te = c->timing ? timing_begin(c, "precond_setup", 28.0 * (double)c->N, 24.0 * (double)c->N) : nullptr;
     hipError_t e = launch_precond_setup(s, blocks, c->stream, te);
     if (e != hipSuccess) {
         timing_failed(c, te);
@@ -1229,29 +1345,68 @@ int fnls_rhs(fnls_ctx* c, const fnls_c128* u_prev, fnls_c128* b) {
     return matvec64(c, u_prev, b, -1.0, 1.0, 1.0);
 }
 
-int fnls_apply_precond(fnls_ctx* c, const fnls_c128* r, fnls_c128* z) {
-    int rc = check_solve_ready(c);
-    if (rc != FNLS_OK) return rc;
-    if (!r || !z) return set_err(c, FNLS_ERR_INVALID_ARG, "NULL vector");
-    if ((const void*)r == (const void*)z) return set_err(c, FNLS_ERR_INVALID_ARG, "r and z must not alias");
-    HIPCHK(c, hipSetDevice(c->device));
-    Bufs b = bufs(c, true, nullptr);
+}  // extern "C"
+
+namespace {
+// z = Ptilde^{-1} r in the precision of fp64 (complex128 or complex64 vectors).
+int precond_apply(fnls_ctx* c, bool fp64, const void* r, void* z) {
+    Bufs b = bufs(c, fp64, nullptr);
     if (c->d == 1) {
-        Geo g = pass_geo(1, c->n, 0, true, c->max_dyn_lds, c->pcfg);
-        PassArgs a = base_args(c, true, 0, g);
+        Geo g = pass_geo(1, c->n, 0, fp64, c->max_dyn_lds, c->pcfg);
+        PassArgs a = base_args(c, fp64, 0, g);
         a.in = r;
         a.out = z;
         PassVariant v{IN_PLAIN, P_DST1 | P_DIV | P_DST2 | P_SCALE, Z_NONE, OUT_LINE, FIN_WRITE};
-        return run_pass(c, true, 0, v, a, g);
+        return run_pass(c, fp64, 0, v, a, g);
     }
     void* t;
-    if ((rc = precond_front(c, true, IN_PLAIN, r, 0, b, &t, 0)) != FNLS_OK) return rc;
-    Geo g = pass_geo(c->d, c->n, c->d - 1, true, c->max_dyn_lds, c->pcfg);
-    PassArgs a = base_args(c, true, c->d - 1, g);
+    int rc;
+    if ((rc = precond_front(c, fp64, IN_PLAIN, r, 0, b, &t, 0)) != FNLS_OK) return rc;
+    Geo g = pass_geo(c->d, c->n, c->d - 1, fp64, c->max_dyn_lds, c->pcfg);
+    PassArgs a = base_args(c, fp64, c->d - 1, g);
     a.in = t;
     a.out = z;
     PassVariant v{IN_PLAIN, P_DST1 | P_SCALE, Z_NONE, OUT_LINE, FIN_WRITE};
-    return run_pass(c, true, c->d - 1, v, a, g);
+    return run_pass(c, fp64, c->d - 1, v, a, g);
+}
+
+int check_vec_pair(fnls_ctx* c, const void* in, const void* out, const char* what) {
+    int rc = check_solve_ready(c);
+    if (rc != FNLS_OK) return rc;
+    if (!in || !out) return set_err(c, FNLS_ERR_INVALID_ARG, "NULL vector");
+    if (in == out) return set_err(c, FNLS_ERR_INVALID_ARG, "%s must not alias", what);
+    HIPCHK(c, hipSetDevice(c->device));
+    return FNLS_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int fnls_apply_precond(fnls_ctx* c, const fnls_c128* r, fnls_c128* z) {
+    int rc = check_vec_pair(c, r, z, "r and z");
+    return rc != FNLS_OK ? rc : precond_apply(c, true, r, z);
+}
+
+int fnls_apply_A_c64(fnls_ctx* c, const fnls_c64* x, fnls_c64* y) {
+    int rc = check_vec_pair(c, x, y, "x and y");
+    return rc != FNLS_OK ? rc : matvec(c, false, x, y, 1.0, 1.0, -1.0);
+}
+
+int fnls_apply_precond_c64(fnls_ctx* c, const fnls_c64* r, fnls_c64* z) {
+    int rc = check_vec_pair(c, r, z, "r and z");
+    return rc != FNLS_OK ? rc : precond_apply(c, false, r, z);
+}
+
+int fnls_get_host_stats(fnls_ctx* c, fnls_host_stats* out, int reset) {
+    if (!c) return FNLS_ERR_INVALID_ARG;
+    if (out) *out = c->stats;
+    if (reset) std::memset(&c->stats, 0, sizeof c->stats);
+    return FNLS_OK;
+}
+
+int fnls_status_report_accepted(unsigned seq_base, unsigned seq_before, unsigned seq_after, int total, int done,
+                                int target) {
+    return report_accepted(seq_base, seq_before, seq_after, total, done, target) ? 1 : 0;
 }
 
 static int resolve_opts(fnls_ctx* c, const fnls_opts* in, fnls_opts* o) {
@@ -1274,6 +1429,8 @@ static int resolve_opts(fnls_ctx* c, const fnls_opts* in, fnls_opts* o) {
     if (o->fixed_iters < 0) return set_err(c, FNLS_ERR_INVALID_ARG, "fixed_iters must be >= 0");
     if (o->lookahead < 0 || o->lookahead > kEvents - 2) return set_err(c, FNLS_ERR_INVALID_ARG, "lookahead out of range");
     if (o->graph != 0 && o->graph != 1) return set_err(c, FNLS_ERR_INVALID_ARG, "graph must be 0 or 1");
+    if (o->poll_delay_us < 0 || o->poll_delay_us > 1000000)
+        return set_err(c, FNLS_ERR_INVALID_ARG, "poll_delay_us must lie in [0, 1e6]");
     return FNLS_OK;
 }
 
@@ -1373,8 +1530,8 @@ int step_backward_impl(fnls_ctx* c, const fnls_c128* u_prev, const fnls_c128* u_
         a.g_V = g_V;
         a.dt = tfac * c->tau;
         a.rho = c->rho;
-        const LaunchEvents* te = c->timing ? timing_begin(c, "adjoint", (16.0 * 7 + (g_cur ? 32.0 : 0.0) +
-                                                                          (g_V ? 16.0 : 0.0)) * (double)c->N)
+        const double adj_bytes = (16.0 * 7 + (g_cur ? 32.0 : 0.0) + (g_V ? 16.0 : 0.0)) * (double)c->N;
+        const LaunchEvents* te = c->timing ? timing_begin(c, "adjoint", adj_bytes, adj_bytes)
                                            : nullptr;
         hipError_t e = launch_adjoint(a, c->stream, te);
         if (e != hipSuccess) {
@@ -1444,6 +1601,7 @@ int fnls_timing_report(fnls_ctx* c, fnls_kernel_stat* out, int max_entries) {
         agg[r.cls].launches += 1;
         agg[r.cls].total_ms += ms;
         agg[r.cls].bytes += r.bytes;
+        agg[r.cls].bytes_min += r.bytes_min;
     }
     int k = 0;
     for (int i = 0; i < ncls && k < max_entries; ++i)
@@ -1929,7 +2087,7 @@ void add_matvec(Step& st, std::vector<Inst*>& live, const double2* const* xs, do
         a.cD = cD;
         a.ci = ci;
         a.cT = cT;
-        a.out = c->at<char>(c->lay.acc);
+        a.out = c->sc<char>(c->lay.acc);
         first.add(a, g);
     }
     st.pass(std::move(first));
@@ -1943,15 +2101,15 @@ void add_matvec(Step& st, std::vector<Inst*>& live, const double2* const* xs, do
             Geo g = batch_geo(d, c->n, ax, true);
             PassArgs a = base_args(c, true, ax, g);
             a.in = xs[k];
-            a.acc_in = c->at<char>(c->lay.acc);
+            a.acc_in = c->sc<char>(c->lay.acc);
             a.cT = cT;
-            a.out = last ? final_out[k] : (void*)c->at<char>(c->lay.acc);
+            a.out = last ? final_out[k] : (void*)c->sc<char>(c->lay.acc);
             if (last && fin == FIN_RESID) {
                 a.b64 = live[k]->b;
-                a.r64 = c->at<double2>(c->lay.r64);
-                a.r32 = ir ? (void*)c->at<float2>(c->lay.V) : nullptr;
+                a.r64 = c->sc<double2>(c->lay.r64);
+                a.r32 = ir ? (void*)c->sc<float2>(c->lay.V) : nullptr;
                 a.ir = ir ? 1 : 0;
-                a.pout = c->at<double2>(c->lay.pr);
+                a.pout = c->sc<double2>(c->lay.pr);
                 a.out = nullptr;
             }
             p.add(a, g);
@@ -2065,16 +2223,16 @@ int batch_arnoldi(fnls_batch* B, std::vector<Inst*>& live, bool fp64, Step& st) 
         const int nb0 = batch_geo(d, c->n, 0, fp64).blocks;
         if (nb0 > kRedundantMax || sb > kRedundantMax)
             return berr(B, FNLS_ERR_INVALID_ARG, "instance too large for a batch (n = %d)", c->n);
-        s.pin = c->at<double2>(c->lay.p1);
+        s.pin = c->sc<double2>(c->lay.p1);
         s.pin_nb = nb0;
-        s.pout = c->at<double2>(c->lay.p2);
+        s.pout = c->sc<double2>(c->lay.p2);
         u0.add(s, sb);
-        s.pin = c->at<double2>(c->lay.p2);
+        s.pin = c->sc<double2>(c->lay.p2);
         s.pin_nb = sb;
-        s.pout = c->at<double2>(c->lay.p3);
+        s.pout = c->sc<double2>(c->lay.p3);
         u1.add(s, sb);
         StreamArgs f = stream_base(c);
-        f.pin = c->at<double2>(c->lay.p3);
+        f.pin = c->sc<double2>(c->lay.p3);
         f.pin_nb = sb;
         f.check_active = 1;
         f.mode = 1;
@@ -2111,7 +2269,7 @@ int batch_cycle_final(fnls_batch* B, std::vector<Inst*>& live, bool fp64, int fi
     for (size_t k = 0; k < live.size(); ++k) {
         fnls_ctx* c = live[k]->c;
         StreamArgs s = stream_base(c);
-        s.pin = c->at<double2>(c->lay.pr);
+        s.pin = c->sc<double2>(c->lay.pr);
         s.pin_nb = batch_geo(d, c->n, 0, true).blocks;
         s.mode = 2;
         s.ir = fp64 ? 0 : 1;
@@ -2138,13 +2296,13 @@ int batch_solve_impl(fnls_batch* B, std::vector<Inst>& inst, const fnls_opts* o,
             StreamArgs s = stream_base(c);
             cfg.push_back(s);
             s.b64 = I.b;
-            s.r32 = fp64 ? nullptr : (void*)c->at<float2>(c->lay.V);
-            s.pout = c->at<double2>(c->lay.pr);
+            s.r32 = fp64 ? nullptr : (void*)c->sc<float2>(c->lay.V);
+            s.pout = c->sc<double2>(c->lay.pr);
             const int sb = stream_blocks(c->N);
             if (sb > kRedundantMax) return berr(B, FNLS_ERR_INVALID_ARG, "instance too large for a batch");
             pr.add(s, sb);
             StreamArgs f = stream_base(c);
-            f.pin = c->at<double2>(c->lay.pr);
+            f.pin = c->sc<double2>(c->lay.pr);
             f.pin_nb = sb;
             f.mode = 0;
             fp.add(f, 1);
@@ -2184,7 +2342,7 @@ int batch_solve_impl(fnls_batch* B, std::vector<Inst>& inst, const fnls_opts* o,
     const int lookahead = std::max(0, o->lookahead);
     while (!live.empty()) {
         for (Inst* I : live)
-            I->bf = bufs(I->c, fp64, first ? (const void*)I->b : (const void*)I->c->at<double2>(I->c->lay.r64));
+            I->bf = bufs(I->c, fp64, first ? (const void*)I->b : (const void*)I->c->sc<double2>(I->c->lay.r64));
         IterLaunch it;
         int rc = batch_arnoldi(B, live, fp64, it.st);
         if (rc == FNLS_OK) rc = prepare_iteration(B, it, o->graph != 0);

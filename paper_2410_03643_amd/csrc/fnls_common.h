@@ -114,7 +114,8 @@ struct PassArgs {
     int pstride;
     GmresState* st;
     HostStatus* hs;
-    int check_active;     // 1: return at once if st->active == 0; 2: unless st->active == 0
+    int check_active;     // 1: return at once if st->active == 0; 2: unless st->active == 0 and st->k == guard_k
+    int guard_k;          // check_active 2: the stopped cycle's basis size the launch was enqueued for
     int first_cycle;      // Z_XADD: 1 = set x (first correction), 0 = accumulate
     int zsum, z32;        // IN_COMBO: 1 = sum_k y_k z_k with z_k at vbase + k N (z32: complex64)
     int ir;               // FIN_RESID: 1 = refinement step of FP32-IR
@@ -153,7 +154,8 @@ struct StreamArgs {
     int pstride;
     GmresState* st;
     HostStatus* hs;
-    int check_active;
+    int check_active;     // as PassArgs::check_active
+    int guard_k;
     int mode;             // k_finish: FinishKind; k_zupdate: 1 = first correction (x = 0 before)
     int ir;               // k_finish residual decision: 1 = refinement step of FP32-IR
     double2* x64;         // k_zupdate: the iterate

@@ -22,6 +22,15 @@ struct LaunchEvents {
 
 hipError_t launch_pass(int fp64, const PassVariant& v, const PassArgs& a, int blocks, size_t lds, hipStream_t s,
                        const LaunchEvents* te = nullptr);
+// per-precision halves of launch_pass / launch_pass_batch (fnls_pass64.hip, fnls_pass32.hip)
+hipError_t launch_pass_f64(const PassVariant& v, const PassArgs& a, int blocks, size_t lds, hipStream_t s,
+                           const LaunchEvents* te);
+hipError_t launch_pass_f32(const PassVariant& v, const PassArgs& a, int blocks, size_t lds, hipStream_t s,
+                           const LaunchEvents* te);
+hipError_t launch_pass_batch_f64(const PassVariant& v, int lgm, const PassArgs* args, const int* offs, int count,
+                                 int blocks, size_t lds, int threads, hipStream_t s);
+hipError_t launch_pass_batch_f32(const PassVariant& v, int lgm, const PassArgs* args, const int* offs, int count,
+                                 int blocks, size_t lds, int threads, hipStream_t s);
 hipError_t launch_precond_setup(const StreamArgs& a, int blocks, hipStream_t s, const LaunchEvents* te = nullptr);
 hipError_t launch_prepare(const StreamArgs& a, int blocks, hipStream_t s, const LaunchEvents* te = nullptr);
 // one workgroup: StreamArgs::mode = 0 prepare (configures the solve from the cfg_ fields), 1 Givens,

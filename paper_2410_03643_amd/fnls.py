@@ -39,7 +39,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("maxit", ctypes.c_int),
                 ("precision", ctypes.c_int), ("inner_tol", ctypes.c_double),
                 ("max_outer", ctypes.c_int), ("fixed_iters", ctypes.c_int),
-                ("lookahead", ctypes.c_int), ("graph", ctypes.c_int), ("reserved", ctypes.c_int * 3)]
+                ("lookahead", ctypes.c_int), ("graph", ctypes.c_int), ("poll_delay_us", ctypes.c_int),
+                ("reserved", ctypes.c_int * 2)]
 
 
 class Info(ctypes.Structure):
@@ -48,9 +49,16 @@ class Info(ctypes.Structure):
                 ("relres_hist", ctypes.c_double * 64)]
 
 
+class HostStats(ctypes.Structure):
+    _fields_ = [("solves", ctypes.c_longlong), ("cycles", ctypes.c_longlong),
+                ("iterations", ctypes.c_longlong), ("stop_predictions", ctypes.c_longlong),
+                ("ends_ahead", ctypes.c_longlong), ("late_reads", ctypes.c_longlong),
+                ("cycles_ahead", ctypes.c_longlong), ("reserved", ctypes.c_longlong)]
+
+
 class KernelStat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 64), ("launches", ctypes.c_int),
-                ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double)]
+                ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double), ("bytes_min", ctypes.c_double)]
 
 
 @dataclass
@@ -87,7 +95,13 @@ def lib() -> ctypes.CDLL:
     L.fnls_assemble.restype = ci
     L.fnls_precond_setup.argtypes = [vp, vp, vp, cd]
     L.fnls_precond_setup.restype = ci
-    for name in ("fnls_apply_A", "fnls_apply_precond", "fnls_rhs"):
+    L.fnls_check_assemble.argtypes = [cd, cd, ci, ci, cd, cd, vp, sz, ctypes.c_char_p, sz]
+    L.fnls_check_assemble.restype = ci
+    L.fnls_get_host_stats.argtypes = [vp, ctypes.POINTER(HostStats), ci]
+    L.fnls_get_host_stats.restype = ci
+    L.fnls_status_report_accepted.argtypes = [ctypes.c_uint, ctypes.c_uint, ctypes.c_uint, ci, ci, ci]
+    L.fnls_status_report_accepted.restype = ci
+    for name in ("fnls_apply_A", "fnls_apply_precond", "fnls_rhs", "fnls_apply_A_c64", "fnls_apply_precond_c64"):
         getattr(L, name).argtypes = [vp, vp, vp]
         getattr(L, name).restype = ci
     L.fnls_solve.argtypes = [vp, vp, vp, ctypes.POINTER(Opts), ctypes.POINTER(Info)]
@@ -204,7 +218,7 @@ class Solver:
         return self.torch.empty(self.shape, dtype=self.torch.complex128, device=self.device)
 
     @staticmethod
-    def _opts(tol, restart, maxit, precision, inner_tol, max_outer, fixed_iters, lookahead):
+    def _opts(tol, restart, maxit, precision, inner_tol, max_outer, fixed_iters, lookahead, poll_delay_us=0):
         o = default_opts()
         o.tol = tol
         o.restart = restart
@@ -215,6 +229,7 @@ class Solver:
         o.max_outer = max_outer
         o.fixed_iters = fixed_iters
         o.lookahead = lookahead
+        o.poll_delay_us = poll_delay_us
         return o
 
     @staticmethod
@@ -241,15 +256,42 @@ class Solver:
         self._check(lib().fnls_apply_precond(self._ctx, self._vec(r, "r"), self._vec(z, "z")))
         return z
 
+    def _vec64(self, t, name):
+        torch = self.torch
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.complex64 or tuple(t.shape) != self.shape \
+                or not t.is_contiguous() or t.device != self.device:
+            raise ValueError("%s must be a contiguous complex64 tensor of shape %s on %s"
+                             % (name, self.shape, self.device))
+        return ctypes.c_void_p(t.data_ptr())
+
+    def apply_A_c64(self, x, out=None):
+        """y = A x on complex64 vectors (the GMRES-IR inner kernels)."""
+        y = self.torch.empty(self.shape, dtype=self.torch.complex64, device=self.device) if out is None else out
+        self._check(lib().fnls_apply_A_c64(self._ctx, self._vec64(x, "x"), self._vec64(y, "y")))
+        return y
+
+    def apply_precond_c64(self, r, out=None):
+        """z = Ptilde^{-1} r on complex64 vectors (the GMRES-IR inner kernels)."""
+        z = self.torch.empty(self.shape, dtype=self.torch.complex64, device=self.device) if out is None else out
+        self._check(lib().fnls_apply_precond_c64(self._ctx, self._vec64(r, "r"), self._vec64(z, "z")))
+        return z
+
+    def host_stats(self, reset: bool = False) -> dict:
+        """Counters of the host's GMRES sequencing (fnls_get_host_stats)."""
+        st = HostStats()
+        self._check(lib().fnls_get_host_stats(self._ctx, ctypes.byref(st), 1 if reset else 0))
+        return {name: getattr(st, name) for name, _ in HostStats._fields_ if name != "reserved"}
+
     def rhs(self, u_prev, out=None):
         b = self._out() if out is None else out
         self._check(lib().fnls_rhs(self._ctx, self._vec(u_prev, "u_prev"), self._vec(b, "b")))
         return b
 
     def solve(self, b, out=None, *, tol=1e-10, restart=30, maxit=2000, precision="fp64",
-              inner_tol=1e-5, max_outer=20, fixed_iters=0, lookahead=1):
+              inner_tol=1e-5, max_outer=20, fixed_iters=0, lookahead=1, poll_delay_us=0):
         x = self._out() if out is None else out
-        o = self._opts(tol, restart, maxit, precision, inner_tol, max_outer, fixed_iters, lookahead)
+        o = self._opts(tol, restart, maxit, precision, inner_tol, max_outer, fixed_iters, lookahead,
+                       poll_delay_us)
         info = Info()
         self._check(lib().fnls_solve(self._ctx, self._vec(b, "b"), self._vec(x, "x"),
                                      ctypes.byref(o), ctypes.byref(info)))
@@ -333,7 +375,8 @@ class Solver:
         arr = (KernelStat * 256)()
         k = self._check(lib().fnls_timing_report(self._ctx, arr, 256))
         return [dict(name=arr[i].name.decode(), launches=arr[i].launches,
-                     total_ms=arr[i].total_ms, bytes=arr[i].bytes) for i in range(k)]
+                     total_ms=arr[i].total_ms, bytes=arr[i].bytes, bytes_min=arr[i].bytes_min)
+                for i in range(k)]
 
     def close(self):
         if getattr(self, "_ctx", None):

@@ -28,7 +28,7 @@ def test_default_opts(L):
 
 
 def test_struct_sizes_match_header():
-    # double + 3 int + pad + double + 4 int (lookahead, graph) + int[3] -> 64 bytes; info 24 + 512
+    # double + 3 int + pad + double + 5 int (max_outer .. poll_delay_us) + int[2] -> 64 bytes; info 24 + 512
     assert ctypes.sizeof(fnls.Opts) == 64
     assert ctypes.sizeof(fnls.Info) == 24 + 64 * 8
 
@@ -94,3 +94,105 @@ def test_create_without_device_reports_no_device(L):
     ctx = ctypes.c_void_p()
     assert L.fnls_create(ctypes.byref(ctx), 0, None) == fnls.ERR_NO_DEVICE
     assert not ctx.value
+
+
+# ---------------------------------------------------------------------------
+# fnls_assemble's argument checks, reached without a device through the
+# context-free checker that fnls_assemble itself calls first
+# ---------------------------------------------------------------------------
+ALIGNED = 1 << 20          # a 256-byte aligned address (never dereferenced)
+
+
+def check_assemble(L, alpha=1.5, rho=2.0, d=2, n=63, h=0.3, tau=0.01, ws=ALIGNED, nbytes=None):
+    if nbytes is None:
+        nbytes = fnls.workspace_bytes(d if 1 <= d <= 3 else 2, n if n in (1, 3, 7, 63) else 63, 1)
+    msg = ctypes.create_string_buffer(256)
+    rc = L.fnls_check_assemble(alpha, rho, d, n, h, tau, ctypes.c_void_p(ws) if ws else None, nbytes, msg, 256)
+    return rc, msg.value.decode()
+
+
+def test_check_assemble_accepts_valid_arguments(L):
+    for d, n in ((1, 1), (1, 1023), (2, 63), (3, 7)):
+        assert check_assemble(L, d=d, n=n, nbytes=fnls.workspace_bytes(d, n, 1)) == (fnls.OK, "")
+    assert check_assemble(L, alpha=2.0, rho=0.0)[0] == fnls.OK      # alpha = 2 and the linear limit
+
+
+@pytest.mark.parametrize("kw,code,word", [
+    (dict(alpha=1.0), fnls.ERR_INVALID_ARG, "alpha"),
+    (dict(alpha=2.0000001), fnls.ERR_INVALID_ARG, "alpha"),
+    (dict(alpha=float("nan")), fnls.ERR_INVALID_ARG, "alpha"),
+    (dict(rho=-1e-12), fnls.ERR_INVALID_ARG, "rho"),
+    (dict(rho=float("inf")), fnls.ERR_INVALID_ARG, "rho"),
+    (dict(rho=float("nan")), fnls.ERR_INVALID_ARG, "rho"),
+    (dict(d=0), fnls.ERR_INVALID_ARG, "d must"),
+    (dict(d=4), fnls.ERR_INVALID_ARG, "d must"),
+    (dict(n=0), fnls.ERR_INVALID_ARG, "power of two"),
+    (dict(n=62), fnls.ERR_INVALID_ARG, "power of two"),
+    (dict(n=2047), fnls.ERR_INVALID_ARG, "power of two"),
+    (dict(h=0.0), fnls.ERR_INVALID_ARG, "h must"),
+    (dict(h=-0.1), fnls.ERR_INVALID_ARG, "h must"),
+    (dict(h=float("inf")), fnls.ERR_INVALID_ARG, "h must"),
+    (dict(tau=0.0), fnls.ERR_INVALID_ARG, "tau must"),
+    (dict(tau=float("nan")), fnls.ERR_INVALID_ARG, "tau must"),
+    (dict(ws=0), fnls.ERR_WORKSPACE, "NULL"),
+    (dict(ws=ALIGNED + 128), fnls.ERR_WORKSPACE, "aligned"),
+    (dict(nbytes=0), fnls.ERR_WORKSPACE, "too small"),
+])
+def test_check_assemble_rejections(L, kw, code, word):
+    rc, msg = check_assemble(L, **kw)
+    assert rc == code and word in msg, (rc, msg)
+
+
+def test_check_assemble_workspace_boundary(L):
+    need = fnls.workspace_bytes(2, 63, 1)
+    assert check_assemble(L, nbytes=need)[0] == fnls.OK
+    assert check_assemble(L, nbytes=need - 1)[0] == fnls.ERR_WORKSPACE
+    # no message buffer: the status alone
+    assert L.fnls_check_assemble(1.5, 2.0, 2, 63, 0.3, 0.01, None, need, None, 0) == fnls.ERR_WORKSPACE
+
+
+def test_host_stats_null_context(L):
+    assert L.fnls_get_host_stats(None, None, 0) == fnls.ERR_INVALID_ARG
+
+
+# ---------------------------------------------------------------------------
+# host status protocol: the library's own acceptance rule for a report
+# ---------------------------------------------------------------------------
+SEQ_STRIDE = 1 << 24    # window of one solve's status sequence
+
+
+def accepted(L, base, s1, s2=None, total=5, done=0, target=5):
+    s2 = s1 if s2 is None else s2
+    return L.fnls_status_report_accepted(base & 0xFFFFFFFF, s1 & 0xFFFFFFFF, s2 & 0xFFFFFFFF, total, done,
+                                         target) == 1
+
+
+@pytest.mark.parametrize("solve", [1, 2, 255, 256, 257, 1000])
+def test_status_sequence_window(L, solve):
+    """Each solve advances the base by 2^24 (mod 2^32); a report adds 2 and is
+    odd while being written.  The host takes only complete reports of the
+    current solve: not the configuration value itself, not a half-written
+    report, not any report of the previous solve (also across the wrap of the
+    32-bit counter), and every report up to 2 (2^21 + 64) of this solve (the
+    maxit bound keeps a solve's reports inside the window)."""
+    base = solve * SEQ_STRIDE
+    prev = (solve - 1) * SEQ_STRIDE
+    assert not accepted(L, base, base)
+    max_reports = (1 << 21) + 64
+    for k in (1, 2, 3, 1000, max_reports):
+        assert accepted(L, base, base + 2 * k)
+        assert not accepted(L, base, base + 2 * k - 1)
+        assert not accepted(L, base, prev + 2 * k)
+    assert not accepted(L, base, base + SEQ_STRIDE)
+    assert 2 * max_reports < SEQ_STRIDE
+
+
+def test_status_report_needs_a_stable_copy_and_the_awaited_total(L):
+    base = 7 * SEQ_STRIDE
+    s = base + 10
+    assert accepted(L, base, s, s, total=5, target=5)
+    assert accepted(L, base, s, s, total=9, target=5)          # a later report covers it
+    assert not accepted(L, base, s, s + 2, total=5, target=5)  # a report landed during the copy
+    assert not accepted(L, base, s, s + 1, total=5, target=5)
+    assert not accepted(L, base, s, s, total=4, target=5)      # not there yet
+    assert accepted(L, base, s, s, total=0, done=1, target=5)  # the solve ended (b = 0, stop)

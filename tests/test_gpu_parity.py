@@ -134,11 +134,40 @@ def test_solve_fp32_ir(torch_dev, d, n):
     res = np.linalg.norm(b - o.apply_A(x)) / np.linalg.norm(b)
     xo, _ = o.solve(b, tol=1e-13)
     err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
-    print("IR: inner IT %d outer %d relres %.3e (oracle %.3e) err vs FP64 oracle %.3e"
-          % (info.iters, info.outer_iters, info.relres_true, res, err), flush=True)
+    _, i64 = s.solve(torch.from_numpy(b).to(dev), tol=1e-10)
+    print("IR: inner IT %d outer %d (FP64 IT %d) relres %.3e (oracle %.3e) err vs FP64 oracle %.3e"
+          % (info.iters, info.outer_iters, i64.iters, info.relres_true, res, err), flush=True)
     assert info.status == 0
     assert res < 1e-10
     assert err < 1e-8
+    # a degraded FP32 kernel would show as extra refinement steps / inner iterations
+    assert info.outer_iters <= 3
+    assert info.iters <= 2 * i64.iters + 2
+
+
+def test_solve_metric_case_fp32_ir(torch_dev):
+    """GMRES-IR at the metric case: the oracle's residual below 1e-10, the
+    error against the oracle's FP64 solution (to 1e-13) within cond(A) * tol,
+    at most 3 refinement steps and at most 2 inner iterations more than the
+    FP64 solve's."""
+    torch, dev = torch_dev
+    p = inputs.metric_case()
+    s, o, u, ut = make(torch_dev, p.d, p.n, p.lo, p.hi, p.alpha, p.rho, p.tau)
+    b = o.rhs(u)
+    bt = torch.from_numpy(b).to(dev)
+    x_t, info = s.solve(bt, tol=1e-10, precision="fp32_ir")
+    _, i64 = s.solve(bt, tol=1e-10)
+    x = to_np(x_t)
+    res = np.linalg.norm(b - o.apply_A(x)) / np.linalg.norm(b)
+    xo, _ = o.solve(b, tol=1e-13)
+    err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    c0 = fcd.coefficients(p.alpha, 2)[0]
+    kap = np.sqrt(1.0 + (p.d * fcd.mu(p.alpha, p.h, p.tau) * 2 * c0 + p.rho * p.tau * np.abs(u).max() ** 2) ** 2)
+    print("metric IR: inner IT %d outer %d (FP64 IT %d) relres %.2e oracle %.2e err vs FP64 oracle %.2e "
+          "(cond bound %.1f)" % (info.iters, info.outer_iters, i64.iters, info.relres_true, res, err, kap), flush=True)
+    assert info.status == 0 and res < 1e-10
+    assert err <= kap * 1e-10
+    assert info.outer_iters <= 3 and info.iters <= i64.iters + 2
 
 
 def test_zero_rhs_gives_zero(torch_dev):

@@ -12,6 +12,12 @@
   rule per step); over all 100 steps the discrete mass is conserved within
   the bound that the reported residuals give (the exact step is a Cayley
   transform, so ||u^{n+1}|| = ||u^{n-1}||).
+* d = 3, n = 255, 10 time steps (the starter and nine three-level steps) in
+  FP64, and the GMRES-IR solve of each of those 10 systems: per step the
+  iteration counts, residuals and the IR-vs-FP64 error are printed; every
+  solution's residual by the oracle's own operator is below 1e-10; steps 0
+  and 9 are re-solved by the oracle (parity rule), which also gives the IR
+  solution's error against the FP64 oracle; the mass is conserved.
 """
 import time
 
@@ -173,3 +179,128 @@ def test_stepping_d2_n511_100_steps(torch_dev, alpha):
               flush=True)
         assert abs(it - io.iters) <= 1
         assert err <= X_TOL
+
+
+# ---------------------------------------------------------------------------
+# d = 3, n = 255, 10 time steps (the starter and nine three-level steps of
+# Sec. 2.2's scheme, extended to three dimensions), FP64 against GMRES-IR
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def three_dim_steps(torch_dev):
+    """The FP64 trajectory u^0 .. u^10 on the GPU and, for every one of its 10
+    systems, the GMRES-IR solution of the same system.  Host copies of every
+    level and IR solution, the infos, and the IR-vs-FP64 error per step."""
+    from paper_2410_03643_amd.fnls import Solver
+    torch, dev = torch_dev
+    p = inputs.three_dim_case()
+    print("d=3 n=255 N=%d, %d steps" % (p.N, p.steps), flush=True)
+    s = Solver(p.alpha, p.rho, p.d, p.n, p.h, p.tau, device=dev, restart=30)
+    levels = [torch.from_numpy(p.u).to(dev)]
+    info64, info32, err = [], [], []
+    ir_host = []
+    t64 = t32 = 0.0
+    for k in range(p.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if k == 0:
+            x64, i64 = s.first_step(levels[0], tol=TOL)
+        else:
+            x64, i64 = s.step(levels[k - 1], levels[k], tol=TOL)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        if k == 0:
+            x32, i32 = s.first_step(levels[0], tol=TOL, precision="fp32_ir")
+        else:
+            x32, i32 = s.step(levels[k - 1], levels[k], tol=TOL, precision="fp32_ir")
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        t64 += t1 - t0
+        t32 += t2 - t1
+        e = float(torch.linalg.vector_norm(x32 - x64).item() / torch.linalg.vector_norm(x64).item())
+        print("step %d: fp64 IT %d relres %.2e %.1f ms | fp32_ir IT %d outer %d relres %.2e %.1f ms | "
+              "|x_ir - x_fp64| / |x_fp64| = %.2e" % (k, i64.iters, i64.relres_true, 1e3 * (t1 - t0), i32.iters,
+                                                     i32.outer_iters, i32.relres_true, 1e3 * (t2 - t1), e),
+              flush=True)
+        levels.append(x64)
+        info64.append(i64)
+        info32.append(i32)
+        err.append(e)
+        ir_host.append(to_np(x32))
+        del x32
+    print("10 steps: fp64 %.1f ms, fp32_ir %.1f ms (GPU, solve calls only)" % (1e3 * t64, 1e3 * t32), flush=True)
+    host = [to_np(v) for v in levels]
+    del levels, s
+    torch.cuda.empty_cache()
+    return dict(p=p, levels=host, ir=ir_host, info64=info64, info32=info32, err=err)
+
+
+def three_dim_system(p, k, levels):
+    """The oracle's system of step k: the starter (dt / 2, u_prev = u_cur = u^0)
+    for k = 0, else the three-level step from (u^{k-1}, u^k)."""
+    if k == 0:
+        o = oracle.OracleSolver(p.alpha, p.rho, p.d, p.n, p.h, 0.5 * p.tau)
+        o.precond_setup(levels[0])
+        return o, o.rhs(levels[0])
+    o = oracle.OracleSolver(p.alpha, p.rho, p.d, p.n, p.h, p.tau)
+    o.precond_setup(levels[k])
+    return o, o.rhs(levels[k - 1])
+
+
+def test_three_dim_ten_steps_gpu(three_dim_steps):
+    """Every solve converges with the counts of a tau-preconditioned solve
+    (FP64 at most 8 iterations; IR at most 3 refinement steps); the IR
+    solution of each system is within cond(A) * (relres_IR + relres_FP64) of
+    the FP64 one; the discrete mass h^d (|u^{n+1}|^2 + |u^n|^2) / 2 is
+    conserved over the 10 steps within the bound the residuals give."""
+    r = three_dim_steps
+    p = r["p"]
+    kap = kappa_bound(p)
+    for k, (i64, i32, e) in enumerate(zip(r["info64"], r["info32"], r["err"])):
+        assert i64.status == 0 and i64.relres_true < TOL and i64.iters <= 8, (k, i64)
+        assert i32.status == 0 and i32.relres_true < TOL and i32.outer_iters <= 3, (k, i32)
+        assert i32.iters <= 2 * i64.iters + 2, (k, i32.iters, i64.iters)
+        assert e <= kap * (i32.relres_true + i64.relres_true), (k, e)
+    norms = [float(np.linalg.norm(v)) for v in r["levels"]]
+    hd = p.h ** p.d
+    Q = [hd * (norms[k + 1] ** 2 + norms[k] ** 2) / 2 for k in range(len(norms) - 1)]
+    drift = max(abs(q - Q[0]) / Q[0] for q in Q)
+    bound = sum(2.0 * kap * i.relres_true + 1e-13 for i in r["info64"])
+    print("mass drift over 10 steps %.2e (bound %.2e)" % (drift, bound), flush=True)
+    assert drift <= bound
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_three_dim_ten_steps_residuals_by_oracle(three_dim_steps, precision):
+    """The oracle's own operator and right-hand side give every step's GPU
+    solution (FP64 trajectory, and the IR solution of the same systems) a
+    relative residual below 1e-10."""
+    r = three_dim_steps
+    p = r["p"]
+    for k in range(p.steps):
+        o, b = three_dim_system(p, k, r["levels"])
+        x = r["levels"][k + 1] if precision == "fp64" else r["ir"][k]
+        res = np.linalg.norm(b - o.apply_A(x)) / np.linalg.norm(b)
+        print("%s step %d: oracle residual %.2e" % (precision, k, res), flush=True)
+        assert res < TOL
+
+
+@pytest.mark.parametrize("k", [0, 9])
+def test_three_dim_ten_steps_oracle_resolve(three_dim_steps, k):
+    """Steps 0 and 9 re-solved by the oracle from the GPU's own levels:
+    iteration counts within 1, the FP64 solution within 1e-10 of the oracle's
+    at equal iteration count (parity rule), and the IR solution's error
+    against that FP64 oracle solution stated and within cond(A) * tol."""
+    r = three_dim_steps
+    p = r["p"]
+    o, b = three_dim_system(p, k, r["levels"])
+    it = r["info64"][k].iters
+    xo, it_orc = oracle_solution_at(o, b, it, TOL)
+    nxo = np.linalg.norm(xo)
+    e64 = np.linalg.norm(r["levels"][k + 1] - xo) / nxo
+    e32 = np.linalg.norm(r["ir"][k] - xo) / nxo
+    kap = kappa_bound(p)
+    print("step %d: IT gpu %d oracle %d | fp64 vs oracle %.2e | fp32_ir vs FP64 oracle %.2e (cond bound %.1f)"
+          % (k, it, it_orc, e64, e32, kap), flush=True)
+    assert abs(it - it_orc) <= 1
+    assert e64 <= X_TOL
+    assert e32 <= kap * 2 * TOL + X_TOL

@@ -401,35 +401,3 @@ def test_lds_layout_is_conflict_free_at_m1024(fp64):
         for kind in "rw":
             bad.append(lds_extra_cycles([start + l + 1 for l in range(64)], elem, kind))
     assert max(bad) == 0
-
-
-# ---------------------------------------------------------------------------
-# host status protocol: which published sequence values the host accepts
-# ---------------------------------------------------------------------------
-SEQ_STRIDE = 1 << 24    # window of one solve's status sequence
-
-
-def seq_accepts(s, base):
-    """The host's acceptance rule for a published HostStatus::seq value s in a
-    solve whose configuration set the sequence to base (unsigned 32-bit)."""
-    rel = (s - base) & 0xFFFFFFFF
-    return (s & 1) == 0 and rel != 0 and rel < SEQ_STRIDE
-
-
-@pytest.mark.parametrize("solve", [1, 2, 255, 256, 257, 1000])
-def test_status_sequence_window(solve):
-    """Each solve advances the base by 2^24 (mod 2^32); a report adds 2 and is
-    odd while being written.  The host takes only complete reports of the
-    current solve: not the configuration value itself, not a half-written
-    report, not any report of the previous solve (also across the wrap of the
-    32-bit counter), and every report up to 2 (2^21 + 64) of this solve (the
-    maxit bound keeps a solve's reports inside the window)."""
-    base = (solve * SEQ_STRIDE) & 0xFFFFFFFF
-    prev = ((solve - 1) * SEQ_STRIDE) & 0xFFFFFFFF
-    assert not seq_accepts(base, base)
-    max_reports = (1 << 21) + 64
-    for k in (1, 2, 3, 1000, max_reports):
-        assert seq_accepts((base + 2 * k) & 0xFFFFFFFF, base)
-        assert not seq_accepts((base + 2 * k - 1) & 0xFFFFFFFF, base)
-        assert not seq_accepts((prev + 2 * k) & 0xFFFFFFFF, base)
-    assert 2 * max_reports < SEQ_STRIDE
