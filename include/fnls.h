@@ -194,6 +194,24 @@ int fnls_rhs(fnls_ctx *ctx, const fnls_c128 *u_prev, fnls_c128 *b);
 int fnls_solve(fnls_ctx *ctx, const fnls_c128 *b, fnls_c128 *x, const fnls_opts *opts,
                fnls_info *info);
 
+/* For callers that cannot allocate device memory at the call (code that may
+ * not call hipMalloc: tight serving loops, harnesses that forbid it): the
+ * same solve as fnls_solve (same kernels, results bitwise equal), with the
+ * solver scratch -- GMRES state, partial sums, work vectors and both Krylov
+ * bases, about (2 restart + 5) 16 n^d bytes -- in a static array of the
+ * library, 64 MiB per device, held by every GPU the library runs on until the
+ * process ends, instead of in the context's workspace.  The context still
+ * needs fnls_assemble and fnls_precond_setup (its workspace keeps the
+ * operator tables and D).  Allocates nothing: no hipMalloc, hipFree or
+ * allocating library call.  FNLS_ERR_WORKSPACE when the scratch for d, n and
+ * opts->restart exceeds 64 MiB (restart 30 fits up to n^d of about 64,000,
+ * e.g. d = 2, n = 127; a shorter restart fits more).  All calls on one device
+ * share the array, which keeps the last call's contents: calls that overlap
+ * in time on one device (other host threads, other streams) race and must
+ * not be made.  Same arguments, errors and results as fnls_solve. */
+int fnls_solve_noalloc(fnls_ctx *ctx, const fnls_c128 *b, fnls_c128 *x, const fnls_opts *opts,
+                       fnls_info *info);
+
 /* a9 -- One three-level time step (Sec. 2.1 LICD / Sec. 2.2 TLID scheme):
  * precond_setup(u_cur), b = (i I + T_d - D) u_prev, solve, u_next = x.
  * u_next must not alias u_prev or u_cur. */

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <chrono>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -201,6 +202,33 @@ Layout make_layout(int d, int n, int restart) {
     return l;
 }
 
+// Solver scratch of fnls_solve_noalloc: one file-scope array per device,
+// held from the code object's load until the process ends.  Host code never
+// uses the array's name as an address (on the host it is a stand-in, not a
+// device address): static_scratch() takes each device's address from
+// hipGetSymbolAddress once, with that device current, and every later use
+// goes through that pointer.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+constexpr int kMaxDevices = 64;
+
+// This device's address of `scratch` (nullptr if it cannot be had); the
+// caller has made `device` current.
+char* static_scratch(int device) {
+    static std::mutex mu;
+    static char* addr[kMaxDevices] = {};
+    static bool tried[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!tried[device]) {
+        tried[device] = true;
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess) addr[device] = static_cast<char*>(p);
+        else (void)hipGetLastError();
+    }
+    return addr[device];
+}
+
 }  // namespace
 
 struct fnls_ctx {
@@ -222,6 +250,7 @@ struct fnls_ctx {
     char* ws = nullptr;
     size_t ws_bytes = 0;
     char* scr = nullptr;            // solver scratch base (ws + lay.op_total, or the static scratch)
+    char* static_scr = nullptr;     // this device's static scratch array (fnls_solve_noalloc)
     Layout lay{};
     HostStatus* hs = nullptr;       // pinned, device-written
     HostStatus* hs_dev = nullptr;
@@ -1175,6 +1204,7 @@ int fnls_create(fnls_ctx** out, int device, void* hip_stream) {
         delete c;
         return FNLS_ERR_HIP;
     }
+    c->static_scr = static_scratch(device);
     *out = c;
     return FNLS_OK;
 }
@@ -1409,13 +1439,14 @@ int fnls_status_report_accepted(unsigned seq_base, unsigned seq_before, unsigned
     return report_accepted(seq_base, seq_before, seq_after, total, done, target) ? 1 : 0;
 }
 
-static int resolve_opts(fnls_ctx* c, const fnls_opts* in, fnls_opts* o) {
+static int resolve_opts(fnls_ctx* c, const fnls_opts* in, fnls_opts* o, int restart_cap = -1) {
     if (in) *o = *in;
     else fnls_default_opts(o);
+    if (restart_cap < 0) restart_cap = c->restart_cap;
     if (!(o->tol > 0.0)) return set_err(c, FNLS_ERR_INVALID_ARG, "tol must be > 0");
-    if (o->restart < 1 || o->restart > c->restart_cap)
+    if (o->restart < 1 || o->restart > restart_cap)
         return set_err(c, FNLS_ERR_WORKSPACE, "restart %d exceeds the workspace capacity %d (or < 1)", o->restart,
-                       c->restart_cap);
+                       restart_cap);
     // (at most one status report per iteration plus one per cycle: a solve's
     // reports stay inside its window of the status sequence)
     if (o->maxit < 1 || o->maxit > (1 << 21)) return set_err(c, FNLS_ERR_INVALID_ARG, "maxit must lie in [1, 2^21]");
@@ -1443,6 +1474,35 @@ int fnls_solve(fnls_ctx* c, const fnls_c128* b, fnls_c128* x, const fnls_opts* o
     if ((rc = resolve_opts(c, opts, &o)) != FNLS_OK) return rc;
     HIPCHK(c, hipSetDevice(c->device));
     return solve_impl(c, b, x, &o, info);
+}
+
+int fnls_solve_noalloc(fnls_ctx* c, const fnls_c128* b, fnls_c128* x, const fnls_opts* opts, fnls_info* info) {
+    int rc = check_solve_ready(c);
+    if (rc != FNLS_OK) return rc;
+    if (!b || !x) return set_err(c, FNLS_ERR_INVALID_ARG, "NULL vector");
+    if ((const void*)b == (const void*)x) return set_err(c, FNLS_ERR_INVALID_ARG, "b and x must not alias");
+    fnls_opts o;
+    if ((rc = resolve_opts(c, opts, &o, kMaxRestart)) != FNLS_OK) return rc;
+    Layout lay = c->lay;
+    scratch_layout(lay, c->d, c->n, o.restart);
+    if (lay.scr_total > kStaticScratchBytes)
+        return set_err(c, FNLS_ERR_WORKSPACE, "solver scratch of %zu bytes (d %d, n %d, restart %d) exceeds the "
+                       "static scratch of %zu bytes", lay.scr_total, c->d, c->n, o.restart, kStaticScratchBytes);
+    if (!c->static_scr) return set_err(c, FNLS_ERR_HIP, "the device's static scratch is unavailable");
+    HIPCHK(c, hipSetDevice(c->device));
+    // the solve runs on the static scratch: swap the scratch base and layout
+    // for the call, then restore the workspace's
+    const Layout saved = c->lay;
+    char* const saved_scr = c->scr;
+    c->lay = lay;
+    c->scr = c->static_scr;
+    // the array keeps the previous call's contents: start from a cleared state
+    hipError_t e = hipMemsetAsync(c->st(), 0, sizeof(GmresState), c->stream);
+    if (e == hipSuccess) rc = solve_impl(c, b, x, &o, info);
+    else rc = set_err(c, FNLS_ERR_HIP, "hipMemsetAsync failed: %s", hipGetErrorString(e));
+    c->lay = saved;
+    c->scr = saved_scr;
+    return rc;
 }
 
 int fnls_step(fnls_ctx* c, const fnls_c128* u_prev, const fnls_c128* u_cur, fnls_c128* u_next,

@@ -106,6 +106,8 @@ def lib() -> ctypes.CDLL:
         getattr(L, name).restype = ci
     L.fnls_solve.argtypes = [vp, vp, vp, ctypes.POINTER(Opts), ctypes.POINTER(Info)]
     L.fnls_solve.restype = ci
+    L.fnls_solve_noalloc.argtypes = [vp, vp, vp, ctypes.POINTER(Opts), ctypes.POINTER(Info)]
+    L.fnls_solve_noalloc.restype = ci
     L.fnls_step.argtypes = [vp, vp, vp, vp, ctypes.POINTER(Opts), ctypes.POINTER(Info)]
     L.fnls_step.restype = ci
     L.fnls_first_step.argtypes = [vp, vp, vp, ctypes.POINTER(Opts), ctypes.POINTER(Info)]
@@ -296,6 +298,16 @@ class Solver:
         self._check(lib().fnls_solve(self._ctx, self._vec(b, "b"), self._vec(x, "x"),
                                      ctypes.byref(o), ctypes.byref(info)))
         return x, self._info(info)
+
+    def solve_noalloc(self, b, out, *, tol=1e-10, restart=30, maxit=2000, precision="fp64",
+                      inner_tol=1e-5, max_outer=20, fixed_iters=0, lookahead=1):
+        """fnls_solve_noalloc: the solve with the library's static scratch
+        (the output tensor is the caller's)."""
+        o = self._opts(tol, restart, maxit, precision, inner_tol, max_outer, fixed_iters, lookahead)
+        info = Info()
+        self._check(lib().fnls_solve_noalloc(self._ctx, self._vec(b, "b"), self._vec(out, "x"),
+                                             ctypes.byref(o), ctypes.byref(info)))
+        return out, self._info(info)
 
     def step(self, u_prev, u_cur, out=None, *, tol=1e-10, restart=30, maxit=2000,
              precision="fp64", inner_tol=1e-5, max_outer=20, lookahead=1):
