@@ -258,8 +258,10 @@ int fnls_first_step_backward(fnls_ctx *ctx, const fnls_c128 *u0, const fnls_c128
 /* Batches: many independent systems of uneven sizes (each an assembled
  * context with its own operator, workspace and preconditioner setup)
  * advanced together.  Every GMRES iteration issues one launch per transform
- * pass (per line-length class: 1024, 512, 256, other), Gram-Schmidt update
- * and Givens step for all instances together;
+ * pass (per line-length class: 1024, 512, 256, other; radix 4 with 1024
+ * threads per workgroup unless fnls_batch_autotune chose a schedule for the
+ * class), Gram-Schmidt update and Givens step for all
+ * instances together;
  * each instance keeps its own convergence state, and instances that have
  * converged drop out.  All contexts must share device, stream and d (d >= 2),
  * with n >= 31 and n^(d-1) <= 262144.  The batch does not own the contexts. */
@@ -306,6 +308,25 @@ int fnls_batch_solve(fnls_batch *batch, const fnls_c128 *const *b, fnls_c128 *co
 int fnls_batch_step(fnls_batch *batch, const fnls_c128 *const *u_prev, const fnls_c128 *const *u_cur,
                     fnls_c128 *const *u_next, const fnls_opts *opts, fnls_info *infos);
 
+/* Autotune the batch's transform schedules: for every line-length class of
+ * the batch with a compile-time plan (m = n + 1 = 256, 512, 1024), and for
+ * its strided and then its contiguous axes, time batched solves of the
+ * right-hand sides b (host array of device vectors, one per instance; every
+ * instance's last precond_setup; default options in the given precision;
+ * per schedule one untimed solve, then the fastest of two runs of `reps`
+ * solves) over radix {4, 8} x lines per workgroup {1, 2, 4} (the rule of
+ * fnls_set_pass_config; radix 4 with 4 lines is the default shape of 1024
+ * threads), keeping a candidate only when it is more than 1 % faster.  The
+ * batch keeps the result for its later launches.  *classes (may be NULL)
+ * receives the number of classes tuned.  Solutions are written into each
+ * instance's workspace only.  Returns when done. */
+int fnls_batch_autotune(fnls_batch *batch, const fnls_c128 *const *b, int precision, int reps, int *classes);
+
+/* The schedule fnls_batch_autotune chose for line length n + 1, precision and
+ * axis kind (strided = 1: the non-contiguous axes): *rmax and *lines, both 0
+ * when the class runs the default shape. */
+int fnls_batch_schedule(const fnls_batch *batch, int n, int precision, int strided, int *rmax, int *lines);
+
 const char *fnls_batch_last_error(const fnls_batch *batch);
 
 /* Per-kernel timing (optional instrumentation, used by the benchmark).
@@ -347,7 +368,9 @@ int fnls_timing_report(fnls_ctx *ctx, fnls_kernel_stat *out, int max_entries);
 int fnls_set_pass_config(fnls_ctx *ctx, int precision, int strided, int rmax, int lines);
 
 /* Autotuner of the transform-pass schedule above, for this context's
- * operator and one precision: times solves of the device vector b with the
+ * operator and one precision (the result is also kept for the process, per
+ * line length m = n + 1, precision and axis kind: contexts assembled later
+ * with the same m start from it): times solves of the device vector b with the
  * current preconditioner setup and default options (per schedule: one
  * warm-up solve, then the fastest of three runs of `reps` solves), for each
  * candidate rmax in {4, 8, 16} and lines in {1, 2, 4}, by coordinate descent
@@ -374,7 +397,9 @@ typedef struct {
                                     already replaced when the host read them                 */
     long long cycles_ahead;      /* cycles enqueued before the previous cycle's residual
                                     decision was read                                        */
-    long long reserved;
+    long long early_stops;       /* cycles that stopped before the iteration a pending stop
+                                    prediction named (possible with several iterations in
+                                    flight); that prediction's guarded cycle end does not run */
 } fnls_host_stats;
 
 /* Copy the counters into *out (may be NULL); reset = 1 clears them afterwards. */

@@ -46,10 +46,36 @@ def build(verbose: bool = False, extra_flags=()) -> str:
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
+    check_kernels(tmp)
     os.replace(tmp, LIB)
     for o in objs:
         os.remove(o)
     return LIB
+
+
+def _section(lib: str, name: str) -> bytes:
+    out = lib + name.replace(".", "_") + ".bin"
+    subprocess.run(["objcopy", "-O", "binary", "--only-section=" + name, lib, out], check=True)
+    with open(out, "rb") as fh:
+        data = fh.read()
+    os.remove(out)
+    return data
+
+
+def check_kernels(lib: str) -> int:
+    """Every kernel the host code registers (its mangled name among the host
+    strings) must be present in the device code objects: a source edited
+    while the host and device passes of one file compiled gives a library
+    that aborts at the first launch of the missing kernel."""
+    import re
+    host = _section(lib, ".rodata")
+    dev = _section(lib, ".hip_fatbin")
+    names = set(re.findall(rb"_ZN4fnls[0-9A-Za-z_]+", host))
+    kernels = [k for k in names if re.match(rb"_ZN4fnls[0-9]+k_", k)]
+    missing = [k.decode() for k in kernels if k not in dev]
+    if missing:
+        raise RuntimeError("kernels registered by the host but absent from the device code: %s" % missing[:5])
+    return len(kernels)
 
 
 if __name__ == "__main__":

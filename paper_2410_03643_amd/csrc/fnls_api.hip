@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <chrono>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -29,7 +30,9 @@ constexpr size_t kStaticLds = 8 * 1024;    // static LDS of k_pass (reduction sc
 constexpr int kRowLines = 1;
 constexpr int kColLines = 4;
 // producers with more workgroups than this get an explicit reduction kernel
+// (kReduceChunks workgroups, each summing a contiguous chunk of them)
 constexpr int kRedundantMax = 1024;
+constexpr int kReduceChunks = 64;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -59,21 +62,58 @@ struct PassConfig {
     int lines[2][2];
 };
 
-PassConfig default_pass_config() {
-    // measured best at d = 2, n = 1023 (FP32 index 0, FP64 index 1)
-    PassConfig p;
-    p.rmax[0][0] = 4;
+// Default schedule for line length m (m = 0: before assembly).  Radix 4
+// everywhere: radix 8 and 16 (also with the one-wavefront-per-line plans at
+// m = 256, 512, 1024) measured slower at every size.  Lines per workgroup as
+// measured best for FP64 and FP32 solves at d = 2, n = 1023 and 511 and
+// d = 3, n = 255 (fastest of 81 schedules each); other lengths take the
+// n = 1023 choice.
+PassConfig default_pass_config(int m = 0) {
+    PassConfig p;   // [FP32 = 0, FP64 = 1][contiguous = 0, strided = 1]
+    for (int f = 0; f < 2; ++f)
+        for (int st = 0; st < 2; ++st) p.rmax[f][st] = 4;
     p.lines[0][0] = 1;
-    p.rmax[0][1] = 4;
     p.lines[0][1] = 4;
-    p.rmax[1][0] = 4;
-    p.lines[1][0] = 2;
-    p.rmax[1][1] = 4;
+    p.lines[1][0] = 1;
     p.lines[1][1] = 2;
+    if (m == 512) {
+        p.lines[0][1] = 1;
+        p.lines[1][1] = 1;
+    } else if (m == 256) {
+        p.lines[0][0] = 2;
+        p.lines[0][1] = 2;
+    }
     return p;
 }
 
 int pass_threads_max(int rmax) { return rmax == 16 ? 256 : 4096 / rmax; }
+
+// Transform-pass schedules found by fnls_autotune, per line length m,
+// precision and axis kind, for the whole process: contexts assembled later
+// with the same m start from them, and batches use them for their
+// line-length classes.
+struct TunedTable {
+    std::mutex mu;
+    std::map<long long, std::pair<int, int>> tab;   // key m * 4 + fp64 * 2 + strided -> (rmax, lines)
+};
+TunedTable& tuned_table() {
+    static TunedTable t;
+    return t;
+}
+bool tuned_get(int m, bool fp64, bool strided, int* rmax, int* lines) {
+    TunedTable& t = tuned_table();
+    std::lock_guard<std::mutex> lock(t.mu);
+    auto it = t.tab.find((long long)m * 4 + (fp64 ? 2 : 0) + (strided ? 1 : 0));
+    if (it == t.tab.end()) return false;
+    *rmax = it->second.first;
+    *lines = it->second.second;
+    return true;
+}
+void tuned_put(int m, bool fp64, bool strided, int rmax, int lines) {
+    TunedTable& t = tuned_table();
+    std::lock_guard<std::mutex> lock(t.mu);
+    t.tab[(long long)m * 4 + (fp64 ? 2 : 0) + (strided ? 1 : 0)] = std::make_pair(rmax, lines);
+}
 
 // LDS line layout of a pass kernel: a line buffer holds pa >= m slots and
 // consecutive lines are ls slots apart (2 pa with the Toeplitz buffer).  On
@@ -164,7 +204,7 @@ void scratch_layout(Layout& l, int d, int n, int restart) {
     l.p2 = take(pwide);
     l.p3 = take((size_t)pmax * 16);
     l.pr = take((size_t)pmax * 16);
-    l.px = take((size_t)(kMaxRestart + 2) * 16);
+    l.px = take((size_t)(kMaxRestart + 2) * kReduceChunks * 16);
     l.t1 = take((size_t)N * 16);
     l.t2 = take((size_t)N * 16);
     l.Z = take((size_t)N * 16 * restart);   // preconditioned basis z_j = P^{-1} v_j
@@ -382,7 +422,7 @@ PassArgs base_args(fnls_ctx* c, bool fp64, int axis, const Geo& g) {
 
 std::string pass_name(bool fp64, const PassVariant& v, int axis) {
     std::string s = fp64 ? "pass64." : "pass32.";
-    static const char* inm[] = {"", "basis.", "combo."};
+    static const char* inm[] = {"", "basis.", "combo.", "cgs."};
     s += inm[v.inm];
     if (v.ops & P_DST1) s += "dst";
     if (v.ops & P_DIV) s += "_div";
@@ -403,7 +443,8 @@ std::string pass_name(bool fp64, const PassVariant& v, int axis) {
 // write once (line data, D, accumulators, basis vectors of the dot products).
 double pass_bytes(fnls_ctx* c, bool fp64, const PassVariant& v, const PassArgs& a) {
     const double N = (double)c->N, e = fp64 ? 16.0 : 8.0, dsz = fp64 ? 8.0 : 4.0;
-    double b = (v.inm == IN_COMBO) ? c->cur_k * (a.zsum ? (a.z32 ? 8.0 : 16.0) : e) * N : e * N;
+    double b = (v.inm == IN_COMBO) ? c->cur_k * (a.zsum ? (a.z32 ? 8.0 : 16.0) : e) * N
+               : (v.inm == IN_CGS) ? (2.0 + (a.basis_j + 1)) * e * N : e * N;
     if ((v.ops & P_SCALE) || v.outm == OUT_ACC_FIRST) b += dsz * N;
     if (v.zm == Z_WRITE) b += e * N;
     if (v.zm == Z_XSET) b += 16.0 * N;
@@ -435,6 +476,9 @@ double pass_bytes_min(fnls_ctx* c, bool fp64, const PassVariant& v, const PassAr
     const double N = (double)c->N, e = fp64 ? 16.0 : 8.0, dsz = fp64 ? 8.0 : 4.0;
     double b = 0.0;
     if (v.inm == IN_COMBO) b += c->cur_k * (a.zsum ? (a.z32 ? 8.0 : 16.0) : e) * N;
+    // second Gram-Schmidt sweep (basis, w read and written) and the next
+    // step's read of its basis vector, which this pass forms in registers
+    else if (v.inm == IN_CGS) b += (3.0 + (a.basis_j + 1)) * e * N;
     else if (v.outm != OUT_ACC_NEXT && a.in && !intermediate(c, a.in)) b += e * N;
     if ((v.ops & P_SCALE) || v.outm == OUT_ACC_FIRST) b += dsz * N;
     if (v.zm == Z_XSET) b += 16.0 * N;
@@ -623,27 +667,52 @@ int run_finish(fnls_ctx* c, const StreamArgs& s, const char* name) {
     return FNLS_OK;
 }
 
-// When the producer of s.pin had many workgroups, sum its nv partials first
-// (one workgroup) so that consumer workgroups read a single entry per value.
+// When the producer of s.pin had many workgroups, pre-sum its nv partials in
+// kReduceChunks contiguous chunks (one workgroup each, fixed order) so that
+// consumer workgroups read kReduceChunks entries per value.
 int reduce_if_wide(fnls_ctx* c, StreamArgs& s, int nv) {
     if (s.pin_nb <= kRedundantMax) return FNLS_OK;
     if (nv > kMaxRestart + 2) return set_err(c, FNLS_ERR_INVALID_ARG, "reduction of %d values exceeds px", nv);
     StreamArgs r = s;
-    r.mode = 3;
     r.nv = nv;
     r.pout = c->sc<double2>(c->lay.px);
-    int rc = run_finish(c, r, "finish.reduce");
-    if (rc != FNLS_OK) return rc;
+    const LaunchEvents* te = c->timing ? timing_begin(c, "reduce.chunks", 16.0 * nv * s.pin_nb, 0.0) : nullptr;
+    hipError_t e = launch_reduce_chunks(r, kReduceChunks, c->stream, te);
+    if (e != hipSuccess) {
+        timing_failed(c, te);
+        return set_err(c, FNLS_ERR_HIP, "reduction launch failed: %s", hipGetErrorString(e));
+    }
     s.pin = c->sc<double2>(c->lay.px);
-    s.pin_nb = 1;
-    s.pin_stride = 1;
+    s.pin_nb = kReduceChunks;
+    s.pin_stride = kReduceChunks;
     return FNLS_OK;
 }
 
+// Blocks of the pass that applies the second Gram-Schmidt update (fused with
+// the next step's first sine transform along the contiguous axis): the
+// producers of the ||w||^2 partials that the Givens step sums.
+int cgs_dst_blocks(fnls_ctx* c, bool fp64) {
+    return pass_geo(c->d, c->n, c->d - 1, fp64, c->max_dyn_lds, c->pcfg).blocks;
+}
+
+// The second Gram-Schmidt update runs fused with the next Arnoldi step's
+// first sine transform unless step j is the last of the cycle's length.
+bool cgs_fused(fnls_ctx* c, int j) { return c->d >= 2 && j + 1 < c->restart_cur; }
+
 // One Arnoldi step j: w = A Ptilde^{-1} v_j into basis slot j+1, first-round
-// dot products, then the two Gram-Schmidt update kernels.
-// part: 0 the whole step; for d >= 2, 1 = its first pass only (which
-// carries the previous step's Givens step when fused), 2 = the rest.
+// dot products, then the two Gram-Schmidt updates.
+// d >= 2: the basis vector is stored raw (v_j / sigma_j).  Its sine transform
+// along the contiguous axis d-1 comes from the previous step's second
+// Gram-Schmidt update, which runs fused with it (step 0: a plain pass of
+// b or r), so step j starts with the remaining front passes of the
+// preconditioner (the first of them carries step j-1's Givens step when
+// fused); the pass that ends the preconditioner applies sigma_j.
+// part (d >= 2, fused Givens steps, j >= 1): 0 the whole step, its first
+// launch carrying step j-1's Givens step; 1 = only step j-1's Givens step,
+// as a one-workgroup launch (issued ahead of a predicted stop, where the
+// step itself is probably not needed); 2 = the whole step without it.
+int run_givens(fnls_ctx* c, int nb);
+
 int arnoldi_step(fnls_ctx* c, bool fp64, Bufs& b, int j, int part = 0) {
     const int d = c->d;
     const size_t esz = fp64 ? 16 : 8;
@@ -665,13 +734,49 @@ int arnoldi_step(fnls_ctx* c, bool fp64, Bufs& b, int j, int part = 0) {
         PassVariant v{IN_BASIS, P_DST1 | P_DIV | P_DST2 | P_SCALE | P_TOEP, Z_NONE, OUT_ACC_FIRST, FIN_WDOTS};
         if ((rc = run_pass(c, fp64, 0, v, a, g)) != FNLS_OK) return rc;
     } else {
-        void* t;
-        if ((rc = precond_front(c, fp64, IN_BASIS, vj, j, b, &t, 1, true, c->fuse != 0 && j >= 1, part)) != FNLS_OK)
-            return rc;
-        if (part == 1) return FNLS_OK;
+        // front passes after the contiguous axis: axes d-2 .. 1 forward,
+        // axis 0 transform-divide-transform, axes 1 .. d-2 back; t1 holds
+        // the contiguous axis's transform of the raw basis vector
+        struct Front { int axis, ops; };
+        Front fr[5];
+        int nf = 0;
+        for (int ax = d - 2; ax >= 1; --ax) fr[nf++] = {ax, P_DST1};
+        fr[nf++] = {0, P_DST1 | P_DIV | P_DST2};
+        for (int ax = 1; ax <= d - 2; ++ax) fr[nf++] = {ax, P_DST1};
+        void* pp[2] = {b.t1, b.t2};
+        const bool givens = c->fuse != 0 && j >= 1 && part == 0;
+        if (part == 1) return run_givens(c, cgs_dst_blocks(c, fp64));
+        if (j == 0) {
+            // step 0: the contiguous axis's transform of the raw start vector
+            Geo g = pass_geo(d, c->n, d - 1, fp64, c->max_dyn_lds, c->pcfg);
+            PassArgs a = base_args(c, fp64, d - 1, g);
+            a.in = vj;
+            a.out = b.t1;
+            a.check_active = 1;
+            PassVariant v{IN_PLAIN, P_DST1, Z_NONE, OUT_LINE, FIN_WRITE};
+            if ((rc = run_pass(c, fp64, d - 1, v, a, g)) != FNLS_OK) return rc;
+        }
+        for (int k = 0; k < nf; ++k) {
+            Geo g = pass_geo(d, c->n, fr[k].axis, fp64, c->max_dyn_lds, c->pcfg);
+            PassArgs a = base_args(c, fp64, fr[k].axis, g);
+            a.in = pp[k & 1];
+            a.out = pp[(k + 1) & 1];
+            a.check_active = 1;
+            if (k == 0 && givens) {
+                a.gfuse = 1;
+                a.gpin = c->sc<double2>(c->lay.p3);
+                a.gpin_nb = cgs_dst_blocks(c, fp64);
+                a.gpin_stride = c->lay.pstride;
+            }
+            PassVariant v{IN_PLAIN, fr[k].ops, Z_NONE, OUT_LINE, FIN_WRITE};
+            if ((rc = run_pass(c, fp64, fr[k].axis, v, a, g)) != FNLS_OK) return rc;
+        }
+        // last sine transform (after the basis scale sigma_j), the
+        // preconditioner's diagonal scale (z_j kept) and the first Toeplitz axis
         Geo g = pass_geo(d, c->n, d - 1, fp64, c->max_dyn_lds, c->pcfg);
         PassArgs a = base_args(c, fp64, d - 1, g);
-        a.in = t;
+        a.in = pp[nf & 1];
+        a.basis_j = j;
         void* zj = (char*)b.zbase + (size_t)j * c->N * esz;
         a.zout = zj;
         a.out = b.acc;
@@ -679,7 +784,7 @@ int arnoldi_step(fnls_ctx* c, bool fp64, Bufs& b, int j, int part = 0) {
         a.ci = 1.0;
         a.cT = -1.0;
         a.check_active = 1;
-        PassVariant v{IN_PLAIN, P_DST1 | P_SCALE | P_TOEP, Z_WRITE, OUT_ACC_FIRST, FIN_WRITE};
+        PassVariant v{IN_BASIS, P_DST1 | P_SCALE | P_TOEP, Z_WRITE, OUT_ACC_FIRST, FIN_WRITE};
         if ((rc = run_pass(c, fp64, d - 1, v, a, g)) != FNLS_OK) return rc;
         PassArgs tmpl;
         std::memset(&tmpl, 0, sizeof tmpl);
@@ -721,17 +826,52 @@ int arnoldi_step(fnls_ctx* c, bool fp64, Bufs& b, int j, int part = 0) {
     s.pin_nb = blocks;
     s.pin_stride = c->lay.pstride;
     if ((rc = reduce_if_wide(c, s, j + 1)) != FNLS_OK) return rc;
-    s.pout = c->sc<double2>(c->lay.p3);
-    te = c->timing ? timing_begin(c, fp64 ? "cgs64.update_norm" : "cgs32.update_norm", cgs_bytes, cgs_bytes) : nullptr;
-    e = launch_cgs(fp64 ? 1 : 0, 1, s, blocks, c->stream, te);
-    if (e != hipSuccess) timing_failed(c, te);
-    if (e != hipSuccess) return set_err(c, FNLS_ERR_HIP, "cgs launch failed: %s", hipGetErrorString(e));
+    int norm_nb = blocks;
+    if (cgs_fused(c, j)) {
+        // fused with the next step's first sine transform along the
+        // contiguous axis: w updated in place, ||w||^2 partials, t1
+        Geo g = pass_geo(d, c->n, d - 1, fp64, c->max_dyn_lds, c->pcfg);
+        PassArgs a = base_args(c, fp64, d - 1, g);
+        a.in = w;
+        a.v0 = b.v0;
+        a.vbase = b.vbase;
+        a.basis_j = j;
+        a.cgs_pin = s.pin;
+        a.cgs_nb = s.pin_nb;
+        a.cgs_stride = s.pin_stride;
+        a.pout = c->sc<double2>(c->lay.p3);
+        a.out = b.t1;
+        a.check_active = 1;
+        PassVariant v{IN_CGS, P_DST1, Z_NONE, OUT_LINE, FIN_WRITE};
+        if ((rc = run_pass(c, fp64, d - 1, v, a, g)) != FNLS_OK) return rc;
+        norm_nb = g.blocks;
+    } else {
+        s.pout = c->sc<double2>(c->lay.p3);
+        te = c->timing ? timing_begin(c, fp64 ? "cgs64.update_norm" : "cgs32.update_norm", cgs_bytes, cgs_bytes) : nullptr;
+        e = launch_cgs(fp64 ? 1 : 0, 1, s, blocks, c->stream, te);
+        if (e != hipSuccess) timing_failed(c, te);
+        if (e != hipSuccess) return set_err(c, FNLS_ERR_HIP, "cgs launch failed: %s", hipGetErrorString(e));
+    }
     // Givens step and stopping decision (fused: in the next iteration's first pass)
     if (c->fuse && d >= 2 && j + 1 < c->restart_cur) return FNLS_OK;
+    return run_givens(c, norm_nb);
+}
+
+// The Givens step of the current Arnoldi iteration as a one-workgroup launch,
+// from the nb partials of ||w||^2 in p3.
+int run_givens(fnls_ctx* c, int nb) {
+    StreamArgs s;
+    std::memset(&s, 0, sizeof s);
+    s.N = c->N;
+    s.pstride = c->lay.pstride;
+    s.st = c->st();
+    s.hs = c->hs_dev;
+    s.check_active = 1;
     s.pin = c->sc<double2>(c->lay.p3);
-    s.pin_nb = blocks;
+    s.pin_nb = nb;
     s.pin_stride = c->lay.pstride;
-    if ((rc = reduce_if_wide(c, s, 1)) != FNLS_OK) return rc;
+    int rc = reduce_if_wide(c, s, 1);
+    if (rc != FNLS_OK) return rc;
     s.mode = 1;
     return run_finish(c, s, "finish.givens");
 }
@@ -934,20 +1074,23 @@ int run_cycle(fnls_ctx* c, bool fp64, Bufs& b, int restart, int lookahead, int t
     };
     // fused Givens: the status of iteration j is written by the first pass of
     // iteration j + 1, which the lookahead has issued before the wait
-    c->fuse = (lookahead >= 1 && c->d >= 2 && stream_blocks(c->N) <= kRedundantMax) ? 1 : 0;
     c->restart_cur = restart;
+    c->fuse = (lookahead >= 1 && c->d >= 2 && cgs_dst_blocks(c, fp64) <= kRedundantMax &&
+               stream_blocks(c->N) <= kRedundantMax) ? 1 : 0;
     // With the fused Givens step, iteration J's first pass decides whether
     // iteration J - 1 stopped the cycle.  When the estimates of the finished
     // iterations, extrapolated at their last rate, predict that stop, only
-    // that first pass is issued ahead; the rest of iteration J follows once
-    // the status shows that the cycle goes on (a short host round trip).
+    // iteration J - 1's Givens step is issued ahead (one workgroup, not the
+    // first pass of an iteration that is probably not needed); iteration J
+    // follows whole once the status shows that the cycle goes on (a short
+    // host round trip).
     std::vector<char> partial((size_t)restart + 1, 0);
     double est_last = 1.0, est_prev = 1.0, tol_last = 0.0;
     while (true) {
         while (issued < restart && issued <= waited + lookahead) {
-            // an iteration whose predecessor was issued only up to its first
-            // pass must wait for that predecessor's rest (its first pass runs
-            // the predecessor's Givens step)
+            // an iteration whose predecessor was issued only as its Givens
+            // step must wait for that predecessor (whose first pass would
+            // have carried the next Givens step)
             if (issued >= 1 && partial[issued - 1]) break;
             rec_first.push_back(c->recs.size());
             bool first_only = false;
@@ -1000,7 +1143,7 @@ int run_cycle(fnls_ctx* c, bool fp64, Bufs& b, int restart, int lookahead, int t
         est_prev = est_last;
         est_last = hs.est;
         tol_last = hs.tol;
-        // the cycle goes on: complete an iteration that was issued up to its first pass
+        // the cycle goes on: issue the iteration whose Givens step alone was issued ahead
         if (partial[waited]) {
             partial[waited] = 0;
             if ((rc = arnoldi_step(c, fp64, b, waited, 2)) != FNLS_OK) return rc;
@@ -1011,6 +1154,7 @@ int run_cycle(fnls_ctx* c, bool fp64, Bufs& b, int restart, int lookahead, int t
     *final_issued = (c->cur_k == final_k) ? 1 : 0;
     c->stats.iterations += c->cur_k;
     c->stats.ends_ahead += *final_issued;
+    if (final_k > 0 && c->cur_k < final_k) ++c->stats.early_stops;
     *stop_status = hs;
     unbill(c->cur_k);
     // let any speculative (inactive) iterations drain before the final passes
@@ -1272,6 +1416,15 @@ int fnls_assemble(fnls_ctx* c, double alpha, double rho, int d, int n, double h,
     c->restart_cap = cap;
     c->lay = make_layout(d, n, cap);
     c->scr = c->ws + c->lay.op_total;
+    c->pcfg = default_pass_config(n + 1);
+    for (int f = 0; f < 2; ++f)
+        for (int st = 0; st < 2; ++st) {
+            int rm = 0, li = 0;
+            if (tuned_get(n + 1, f == 1, st == 1, &rm, &li)) {
+                c->pcfg.rmax[f][st] = rm;
+                c->pcfg.lines[f][st] = li;
+            }
+        }
     c->tscale = 1.0;
     c->have_D = 0;
 
@@ -1741,6 +1894,8 @@ int fnls_autotune(fnls_ctx* c, const fnls_c128* b, int precision, int reps, int 
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != FNLS_OK) return rc;
+    tuned_put(c->m, f == 1, false, c->pcfg.rmax[f][0], c->pcfg.lines[f][0]);
+    tuned_put(c->m, f == 1, true, c->pcfg.rmax[f][1], c->pcfg.lines[f][1]);
     if (best) {
         best[0] = c->pcfg.rmax[f][0];
         best[1] = c->pcfg.lines[f][0];
@@ -1814,6 +1969,9 @@ struct fnls_batch {
     GraphSlot gs[kGraphSlots];
     unsigned long long tick = 0;
     long long captures = 0, replays = 0;
+    // transform schedules chosen by fnls_batch_autotune per line length,
+    // precision and axis kind: key m * 4 + fp64 * 2 + strided -> (rmax, lines)
+    std::map<long long, std::pair<int, int>> sched;
     std::string err;
 };
 
@@ -1846,13 +2004,41 @@ size_t batch_slot_bytes(int count) {
 }
 size_t batch_total_bytes(int count) { return batch_ring_bytes(count) + (size_t)kGraphSlots * batch_slot_bytes(count); }
 
-// Geometry of a pass in a batched launch: radix 4, G * L = 1024.
-Geo batch_geo(int d, int n, int axis, bool fp64) {
+int batch_lgm_class(int lgm);
+
+// Geometry of a pass in a batched launch.  By default radix 4 and
+// G * L = 1024 threads, one launch shape for every line length.  Line
+// lengths with a compile-time plan (m = 256, 512, 1024) take the schedule
+// fnls_batch_autotune chose for the batch (radix 4 or 8, lines per workgroup
+// by the rule of the single-instance passes), if any.
+Geo batch_geo(int d, int n, int axis, bool fp64, const fnls_batch* B = nullptr) {
     Geo g;
     const int m = n + 1;
-    g.rmax = 4;
-    g.G = std::max(1, m / 4);
-    g.L = std::max(1, kBatchThreads / g.G);
+    int lgm = 0;
+    while ((1 << lgm) < m) ++lgm;
+    int rmax = 4, lines = 0;
+    bool tuned = false;
+    if (B && batch_lgm_class(lgm) != 0) {
+        auto it = B->sched.find((long long)m * 4 + (fp64 ? 2 : 0) + (axis != d - 1 ? 1 : 0));
+        if (it != B->sched.end()) {
+            rmax = it->second.first;
+            lines = it->second.second;
+            tuned = (rmax == 4 || rmax == 8);
+        }
+    }
+    if (tuned) {
+        g.rmax = rmax;
+        g.G = std::max(1, m / rmax);
+        const int tmax = std::min(kBatchThreads, pass_threads_max(rmax));
+        int L = lines * std::max(1, (1024 / rmax) / g.G);
+        L = std::max(1, std::min(L, tmax / g.G));
+        while (g.G * L < 64) L *= 2;
+        g.L = L;
+    } else {
+        g.rmax = 4;
+        g.G = std::max(1, m / 4);
+        g.L = std::max(1, kBatchThreads / g.G);
+    }
     const size_t elem = fp64 ? 16 : 8;
     int pa = 0, ls = 0;
     line_layout(m, g.L, fp64, true, &pa, &ls);   // the larger (Toeplitz) layout
@@ -1899,9 +2085,11 @@ struct PassLaunch {
     PassVariant v;
     int fp64;
     int lgm = 0;                      // line-length class of every instance (batch_lgm_class)
+    int threads = kBatchThreads;      // G * L of every instance of the launch
     std::vector<PassArgs> args;
     std::vector<int> offs{0};
     std::vector<size_t> ilds;         // LDS of each instance
+    std::vector<int> irmax, ithreads; // schedule of each instance
     size_t lds = 0;
     size_t a_off = 0, o_off = 0;
     void add(PassArgs a, const Geo& g) {
@@ -1909,6 +2097,8 @@ struct PassLaunch {
         args.push_back(a);
         offs.push_back(offs.back() + g.blocks);
         ilds.push_back(pass_lds(g, a.m, fp64 != 0, (v.ops & P_TOEP) != 0));
+        irmax.push_back(g.rmax);
+        ithreads.push_back(g.G * g.L);
         lds = std::max(lds, ilds.back());
     }
 };
@@ -1942,9 +2132,14 @@ struct Step {
             q.lgm = cl;
             for (size_t i = 0; i < p.args.size(); ++i) {
                 if (batch_lgm_class(p.args[i].lgm) != cl) continue;
+                // one line length per compile-time class, so one schedule
+                q.v.rmax = p.irmax[i];
+                q.threads = p.ithreads[i];
                 q.args.push_back(p.args[i]);
                 q.offs.push_back(q.offs.back() + (p.offs[i + 1] - p.offs[i]));
                 q.ilds.push_back(p.ilds[i]);
+                q.irmax.push_back(p.irmax[i]);
+                q.ithreads.push_back(p.ithreads[i]);
                 q.lds = std::max(q.lds, p.ilds[i]);
             }
             order.push_back((int)passes.size());
@@ -1982,7 +2177,7 @@ int launch_step(fnls_batch* B, const Step& st, char* base, hipStream_t s_, bool 
             if (p.lds > B->ctx[0]->max_dyn_lds) return berr(B, FNLS_ERR_INVALID_ARG, "batch pass needs %zu B of LDS", p.lds);
             e = launch_pass_batch(p.fp64, p.v, p.lgm, attr_only ? nullptr : reinterpret_cast<const PassArgs*>(base + p.a_off),
                                   reinterpret_cast<const int*>(base + p.o_off), count, p.offs.back(), p.lds,
-                                  kBatchThreads, s_);
+                                  p.threads, s_);
         } else if (!attr_only) {
             const StreamLaunch& s = st.streams[-o - 1];
             const int count = (int)s.args.size();
@@ -2028,7 +2223,7 @@ std::vector<char> graph_key(const Step& st, const Blob& blob) {
         if (o >= 0) {
             const PassLaunch& p = st.passes[o];
             sig.insert(sig.end(), {p.v.inm, p.v.ops, p.v.zm, p.v.outm, p.v.fin, p.v.rmax, p.fp64, p.lgm,
-                                   (int)p.args.size(), p.offs.back(), (int)p.lds});
+                                   (int)p.args.size(), p.offs.back(), (int)p.lds, p.threads});
         } else {
             const StreamLaunch& s = st.streams[-o - 1];
             sig.insert(sig.end(), {s.kind, s.fp64, s.mode, (int)s.args.size(), s.offs.back()});
@@ -2132,7 +2327,8 @@ struct Inst {
 };
 
 // Toeplitz passes of y = (cD D + i ci I + cT T_d) x (FP64) into `fin` final mode on axis 0.
-void add_matvec(Step& st, std::vector<Inst*>& live, const double2* const* xs, double cD, double ci, double cT,
+void add_matvec(const fnls_batch* B, Step& st, std::vector<Inst*>& live, const double2* const* xs, double cD,
+                double ci, double cT,
                 int fin, void* const* final_out, bool ir) {
     fnls_ctx* c0 = live[0]->c;
     const int d = c0->d;
@@ -2141,7 +2337,7 @@ void add_matvec(Step& st, std::vector<Inst*>& live, const double2* const* xs, do
     first.v = PassVariant{IN_PLAIN, P_TOEP, Z_NONE, OUT_ACC_FIRST, FIN_WRITE, 4};
     for (size_t k = 0; k < live.size(); ++k) {
         fnls_ctx* c = live[k]->c;
-        Geo g = batch_geo(d, c->n, d - 1, true);
+        Geo g = batch_geo(d, c->n, d - 1, true, B);
         PassArgs a = base_args(c, true, d - 1, g);
         a.in = xs[k];
         a.cD = cD;
@@ -2158,7 +2354,7 @@ void add_matvec(Step& st, std::vector<Inst*>& live, const double2* const* xs, do
         p.v = PassVariant{IN_PLAIN, P_TOEP, Z_NONE, OUT_ACC_NEXT, last ? fin : FIN_WRITE, 4};
         for (size_t k = 0; k < live.size(); ++k) {
             fnls_ctx* c = live[k]->c;
-            Geo g = batch_geo(d, c->n, ax, true);
+            Geo g = batch_geo(d, c->n, ax, true, B);
             PassArgs a = base_args(c, true, ax, g);
             a.in = xs[k];
             a.acc_in = c->sc<char>(c->lay.acc);
@@ -2193,7 +2389,7 @@ int batch_arnoldi(fnls_batch* B, std::vector<Inst*>& live, bool fp64, Step& st) 
         for (size_t k = 0; k < live.size(); ++k) {
             fnls_ctx* c = live[k]->c;
             Bufs& b = live[k]->bf;
-            Geo g = batch_geo(d, c->n, ax, fp64);
+            Geo g = batch_geo(d, c->n, ax, fp64, B);
             PassArgs a = base_args(c, fp64, ax, g);
             a.in = first_pass ? nullptr : cur[k];   // IN_BASIS: basis vector j
             a.v0 = b.v0;
@@ -2222,7 +2418,7 @@ int batch_arnoldi(fnls_batch* B, std::vector<Inst*>& live, bool fp64, Step& st) 
         for (size_t k = 0; k < live.size(); ++k) {
             fnls_ctx* c = live[k]->c;
             Bufs& b = live[k]->bf;
-            Geo g = batch_geo(d, c->n, d - 1, fp64);
+            Geo g = batch_geo(d, c->n, d - 1, fp64, B);
             PassArgs a = base_args(c, fp64, d - 1, g);
             a.in = cur[k];
             a.zout = b.zbase;   // + j N
@@ -2245,7 +2441,7 @@ int batch_arnoldi(fnls_batch* B, std::vector<Inst*>& live, bool fp64, Step& st) 
         for (size_t k = 0; k < live.size(); ++k) {
             fnls_ctx* c = live[k]->c;
             Bufs& b = live[k]->bf;
-            Geo g = batch_geo(d, c->n, ax, fp64);
+            Geo g = batch_geo(d, c->n, ax, fp64, B);
             PassArgs a = base_args(c, fp64, ax, g);
             a.in = b.zbase;   // z_j
             a.jin = c->N;
@@ -2280,7 +2476,7 @@ int batch_arnoldi(fnls_batch* B, std::vector<Inst*>& live, bool fp64, Step& st) 
         s.vbase = b.vbase;
         s.check_active = 1;
         const int sb = stream_blocks(c->N);
-        const int nb0 = batch_geo(d, c->n, 0, fp64).blocks;
+        const int nb0 = batch_geo(d, c->n, 0, fp64, B).blocks;
         if (nb0 > kRedundantMax || sb > kRedundantMax)
             return berr(B, FNLS_ERR_INVALID_ARG, "instance too large for a batch (n = %d)", c->n);
         s.pin = c->sc<double2>(c->lay.p1);
@@ -2323,14 +2519,14 @@ int batch_cycle_final(fnls_batch* B, std::vector<Inst*>& live, bool fp64, int fi
         xs[k] = live[k]->x;
     }
     st.strm(std::move(zu));
-    add_matvec(st, live, xs.data(), 1.0, 1.0, -1.0, FIN_RESID, nulls.data(), !fp64);
+    add_matvec(B, st, live, xs.data(), 1.0, 1.0, -1.0, FIN_RESID, nulls.data(), !fp64);
     StreamLaunch fr;
     fr.kind = 4;
     for (size_t k = 0; k < live.size(); ++k) {
         fnls_ctx* c = live[k]->c;
         StreamArgs s = stream_base(c);
         s.pin = c->sc<double2>(c->lay.pr);
-        s.pin_nb = batch_geo(d, c->n, 0, true).blocks;
+        s.pin_nb = batch_geo(d, c->n, 0, true, B).blocks;
         s.mode = 2;
         s.ir = fp64 ? 0 : 1;
         fr.add(s, 1);
@@ -2484,7 +2680,8 @@ int fnls_batch_create(fnls_batch** out, fnls_ctx* const* ctxs, int count, void* 
         for (int a = 0; a < c->d; ++a)
             for (int p = 0; p < 2; ++p) {
                 const Geo g = batch_geo(c->d, c->n, a, p == 1);
-                if (g.G * g.L != kBatchThreads || g.lds > c->max_dyn_lds) return FNLS_ERR_INVALID_ARG;
+                if (g.G * g.L > kBatchThreads || (g.G * g.L) % 64 != 0 || g.lds > c->max_dyn_lds)
+                    return FNLS_ERR_INVALID_ARG;
                 if (g.blocks > kRedundantMax || stream_blocks(c->N) > kRedundantMax) return FNLS_ERR_INVALID_ARG;
             }
         for (int k = 0; k < i; ++k)
@@ -2600,9 +2797,113 @@ int fnls_batch_step(fnls_batch* B, const fnls_c128* const* u_prev, const fnls_c1
     }
     st.strm(std::move(ps));
     // b = (iI + T_d - D) u_prev
-    add_matvec(st, all, prev.data(), -1.0, 1.0, 1.0, FIN_WRITE, bout.data(), false);
+    add_matvec(B, st, all, prev.data(), -1.0, 1.0, 1.0, FIN_WRITE, bout.data(), false);
     if ((rc = run_step(B, st)) != FNLS_OK) return rc;
     return batch_solve_impl(B, inst, &o, infos);
+}
+
+int fnls_batch_autotune(fnls_batch* B, const fnls_c128* const* b, int precision, int reps, int* classes) {
+    if (!B) return FNLS_ERR_INVALID_ARG;
+    if (classes) *classes = 0;
+    if (!b) return berr(B, FNLS_ERR_INVALID_ARG, "NULL pointer array");
+    if (precision != FNLS_FP64 && precision != FNLS_FP32_IR)
+        return berr(B, FNLS_ERR_INVALID_ARG, "unknown precision");
+    if (reps < 1 || reps > 1000) return berr(B, FNLS_ERR_INVALID_ARG, "reps must lie in [1, 1000]");
+    fnls_opts in, o;
+    fnls_default_opts(&in);
+    in.precision = precision;
+    for (fnls_ctx* c : B->ctx) in.restart = std::min(in.restart, c->restart_cap);
+    int rc = batch_check(B, &in, &o);
+    if (rc != FNLS_OK) return rc;
+    // every instance solves its b into its adjoint buffer (not needed here)
+    std::vector<Inst> inst(B->count);
+    std::vector<int> ms_of;   // line lengths with a compile-time plan, in order of appearance
+    for (int k = 0; k < B->count; ++k) {
+        fnls_ctx* c = B->ctx[k];
+        if (!b[k]) return berr(B, FNLS_ERR_INVALID_ARG, "instance %d: NULL vector", k);
+        if (!c->have_D) return berr(B, FNLS_ERR_STATE, "instance %d has no preconditioner setup", k);
+        inst[k].c = c;
+        inst[k].b = reinterpret_cast<const double2*>(b[k]);
+        inst[k].x = c->at<double2>(c->lay.adj);
+        int lgm = 0;
+        while ((1 << lgm) < c->m) ++lgm;
+        if (batch_lgm_class(lgm) != 0 && std::find(ms_of.begin(), ms_of.end(), c->m) == ms_of.end())
+            ms_of.push_back(c->m);
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    BHIPCHK(B, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return berr(B, FNLS_ERR_HIP, "hipEventCreate failed");
+    }
+    // time per batch solve: one untimed solve, then the fastest of two timed
+    // runs of `reps` solves
+    auto measure = [&](double* ms) -> int {
+        int r = batch_solve_impl(B, inst, &o, nullptr);
+        if (r < 0) return r;
+        double best_t = 0.0;
+        for (int trial = 0; trial < 2; ++trial) {
+            if (hipEventRecord(e0, B->stream) != hipSuccess) return berr(B, FNLS_ERR_HIP, "hipEventRecord");
+            for (int k = 0; k < reps; ++k) {
+                r = batch_solve_impl(B, inst, &o, nullptr);
+                if (r < 0) return r;
+            }
+            if (hipEventRecord(e1, B->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+                return berr(B, FNLS_ERR_HIP, "event timing failed");
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, e0, e1) != hipSuccess) return berr(B, FNLS_ERR_HIP, "hipEventElapsedTime");
+            const double per = (double)t / reps;
+            if (trial == 0 || per < best_t) best_t = per;
+        }
+        *ms = best_t;
+        return FNLS_OK;
+    };
+    const bool fp64 = precision == FNLS_FP64;
+    double cur = 0.0;
+    rc = measure(&cur);
+    // coordinate descent: per line-length class, strided axes then the
+    // contiguous axis, over radix {4, 8} x lines {1, 2, 4} (radix 4 with
+    // lines 4 is the default shape of 1024 threads); a candidate replaces
+    // the current schedule only when it is more than 1 % faster
+    for (size_t ci = 0; ci < ms_of.size() && rc == FNLS_OK; ++ci) {
+        for (int strided = 1; strided >= 0 && rc == FNLS_OK; --strided) {
+            const long long key = (long long)ms_of[ci] * 4 + (fp64 ? 2 : 0) + strided;
+            const auto had = B->sched.find(key);
+            std::pair<int, int> best = had != B->sched.end() ? had->second : std::make_pair(4, 4);
+            for (int rm : {4, 8}) {
+                for (int li : {1, 2, 4}) {
+                    if (rc != FNLS_OK || (rm == best.first && li == best.second)) continue;
+                    B->sched[key] = std::make_pair(rm, li);
+                    double t = 0.0;
+                    rc = measure(&t);
+                    if (rc == FNLS_OK && t < 0.99 * cur) {
+                        cur = t;
+                        best = std::make_pair(rm, li);
+                    }
+                }
+            }
+            B->sched[key] = best;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != FNLS_OK) return rc;
+    if (classes) *classes = (int)ms_of.size();
+    return FNLS_OK;
+}
+
+int fnls_batch_schedule(const fnls_batch* B, int n, int precision, int strided, int* rmax, int* lines) {
+    if (!B || !rmax || !lines) return FNLS_ERR_INVALID_ARG;
+    if (precision != FNLS_FP64 && precision != FNLS_FP32_IR) return FNLS_ERR_INVALID_ARG;
+    const auto it = B->sched.find((long long)(n + 1) * 4 + (precision == FNLS_FP64 ? 2 : 0) + (strided ? 1 : 0));
+    if (it == B->sched.end()) {
+        *rmax = 0;
+        *lines = 0;
+    } else {
+        *rmax = it->second.first;
+        *lines = it->second.second;
+    }
+    return FNLS_OK;
 }
 
 const char* fnls_batch_last_error(const fnls_batch* B) { return B ? B->err.c_str() : "null batch"; }

@@ -66,7 +66,11 @@ struct HostStatus {
     double hist[64];
 };
 
-enum InMode { IN_PLAIN = 0, IN_BASIS = 1, IN_COMBO = 2 };
+// IN_CGS: the second Gram-Schmidt update w -= sum_i h2_i v_i (h2 from the
+// partials cgs_pin of the second-round dot products), w written back in
+// place and its squared norm's per-workgroup partial to pout, then the line
+// transforms of the next Arnoldi step's first pass run on w
+enum InMode { IN_PLAIN = 0, IN_BASIS = 1, IN_COMBO = 2, IN_CGS = 3 };
 enum OutMode { OUT_LINE = 0, OUT_ACC_FIRST = 1, OUT_ACC_NEXT = 2 };
 enum FinalMode { FIN_WRITE = 0, FIN_WDOTS = 1, FIN_RESID = 2 };
 enum ZMode { Z_NONE = 0, Z_WRITE = 1, Z_XSET = 2, Z_XADD = 3 };
@@ -124,6 +128,10 @@ struct PassArgs {
     int gfuse;
     const double2* gpin;
     int gpin_nb, gpin_stride;
+    // IN_CGS: partials of the second-round dot products (nv = basis_j + 1
+    // values, layout [i][cgs_stride], cgs_nb producer workgroups)
+    const double2* cgs_pin;
+    int cgs_nb, cgs_stride;
     // batched launches: with dev_j set the iteration index j is read from
     // st->j when the kernel starts (one argument table serves every Arnoldi
     // iteration of a cycle).  Then basis_j = j; IN_BASIS reads basis vector j;

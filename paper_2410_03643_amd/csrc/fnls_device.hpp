@@ -407,6 +407,24 @@ __device__ __forceinline__ void stage_store(const StageRegs<R, RAD, RMAX>& g, cp
     }
 }
 
+// Synchronisation of the threads of one line.  WS (wave sync): every line
+// lies within one wavefront (G <= 64 threads, G dividing 64), so the line's
+// exchanges through LDS need no workgroup barrier: a wavefront's LDS accesses
+// execute in issue order, and the wavefront-scope fences keep the compiler
+// from moving LDS reads and writes across the point.  The wavefronts of a
+// workgroup then run their lines' transforms independently.  Otherwise a
+// workgroup barrier.
+template <bool WS>
+__device__ __forceinline__ void line_sync() {
+    if constexpr (WS) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 // Stage on A and (optionally) B.  For RMAX <= 8 both buffers' butterflies
 // are in registers together (twice the independent work between the two
 // barriers): load+compute A and B | barrier | store A and B | barrier.
@@ -414,35 +432,35 @@ __device__ __forceinline__ void stage_store(const StageRegs<R, RAD, RMAX>& g, cp
 // load+compute A | barrier | store A, load+compute B | barrier | store B,
 // and the next stage's first barrier (or the one ending line_fft) orders
 // "store B" before any later read of B.
-template <typename R, int RAD, int RMAX, bool INV, bool WR = false>
+template <typename R, int RAD, int RMAX, bool INV, bool WR = false, bool WS = false>
 __device__ __forceinline__ void stockham_stage(cplx<R>* A, cplx<R>* B, bool both, int lgm, int lgNs, int lt,
                                                int G, const cplx<R>* twl, cplx<R> wr = cplx<R>{}) {
     if constexpr (RMAX <= 8) {
         StageRegs<R, RAD, RMAX> ga, gb;
         stage_load<R, RAD, RMAX, INV, WR>(ga, A, lgm, lgNs, lt, G, twl, wr);
         if (both) stage_load<R, RAD, RMAX, INV, WR>(gb, B, lgm, lgNs, lt, G, twl, wr);
-        __syncthreads();
+        line_sync<WS>();
         stage_store<R, RAD, RMAX>(ga, A, lgm, lgNs, lt, G);
         if (both) stage_store<R, RAD, RMAX>(gb, B, lgm, lgNs, lt, G);
-        __syncthreads();
+        line_sync<WS>();
     } else {
         StageRegs<R, RAD, RMAX> g;
         stage_load<R, RAD, RMAX, INV>(g, A, lgm, lgNs, lt, G, twl);
-        __syncthreads();
+        line_sync<WS>();
         stage_store<R, RAD, RMAX>(g, A, lgm, lgNs, lt, G);
         if (both) {
             stage_load<R, RAD, RMAX, INV>(g, B, lgm, lgNs, lt, G, twl);
-            __syncthreads();
+            line_sync<WS>();
             stage_store<R, RAD, RMAX>(g, B, lgm, lgNs, lt, G);
         } else {
-            __syncthreads();
+            line_sync<WS>();
         }
     }
 }
 
 // Compile-time stage plan (m = 2^LGM known at compile time): every index,
 // bound and radix folds to a constant.
-template <typename R, bool INV, int RMAX, int LGM, int LGNS, typename LT>
+template <typename R, bool INV, int RMAX, int LGM, int LGNS, typename LT, bool WS>
 __device__ __forceinline__ void fft_stages_ct(cplx<R>* A, cplx<R>* B, bool both, int lt, const cplx<R>* twl,
                                               const LT& lw) {
     if constexpr (LGNS < LGM) {
@@ -455,19 +473,21 @@ __device__ __forceinline__ void fft_stages_ct(cplx<R>* A, cplx<R>* B, bool both,
             if constexpr (LGNS == 2) wr = LT::stage1(lt);
             else wr = lw.w2;
         }
-        stockham_stage<R, (1 << lr), RMAX, INV, kReg>(A, B, both, LGM, LGNS, lt, G, twl, wr);
-        fft_stages_ct<R, INV, RMAX, LGM, LGNS + lr, LT>(A, B, both, lt, twl, lw);
+        stockham_stage<R, (1 << lr), RMAX, INV, kReg, WS>(A, B, both, LGM, LGNS, lt, G, twl, wr);
+        fft_stages_ct<R, INV, RMAX, LGM, LGNS + lr, LT, WS>(A, B, both, lt, twl, lw);
     }
 }
 
 // Length-m FFT (unnormalised) of line buffer A (and B), natural order in and
 // out (m = 2^lgm), radices up to RMAX (G >= m / RMAX threads per line).
-// LGM > 0 selects the compile-time plan for m = 2^LGM.  Ends with a barrier.
-template <typename R, bool INV, int RMAX, int LGM, typename LT>
+// LGM > 0 selects the compile-time plan for m = 2^LGM.  Ends with a line
+// synchronisation (WS: the compile-time plans with G <= 64 only).
+template <typename R, bool INV, int RMAX, int LGM, typename LT, bool WS = false>
 __device__ __forceinline__ void line_fft(cplx<R>* A, cplx<R>* B, bool both, int lgm, int lt, int G,
                                          const cplx<R>* twl, const LT& lw) {
+    static_assert(!WS || LGM > 0, "wave sync needs a compile-time plan");
     if constexpr (LGM > 0) {
-        fft_stages_ct<R, INV, RMAX, LGM, 0, LT>(A, B, both, lt, twl, lw);
+        fft_stages_ct<R, INV, RMAX, LGM, 0, LT, WS>(A, B, both, lt, twl, lw);
     } else {
         constexpr int LGMAX = Lg<RMAX>::v;
         int lgNs = 0;
@@ -486,7 +506,7 @@ __device__ __forceinline__ void line_fft(cplx<R>* A, cplx<R>* B, bool both, int 
             lgNs += lr;
         }
     }
-    __syncthreads();
+    line_sync<WS>();
 }
 
 // Exclusive prefix sum of v over the G threads of a line (threads lt = 0..G-1
@@ -535,7 +555,7 @@ __device__ __forceinline__ cplx<R> line_exclusive_scan(cplx<R> v, int G) {
 // prefix scan over p < m/2 (each thread owns a contiguous range of p).
 // Caller has synchronised after writing A.  tw[s] = W_{2m}^s (global table).
 // B is not used.
-template <typename R, int RMAX, int LGM, typename LT>
+template <typename R, int RMAX, int LGM, typename LT, bool WS = false>
 __device__ __forceinline__ void line_dst(cplx<R>* A, cplx<R>* B, int lgm, int lt, int G,
                                          const cplx<R>* __restrict__ tw, const cplx<R>* twl, const LT& lw) {
     using C = cplx<R>;
@@ -575,8 +595,8 @@ __device__ __forceinline__ void line_dst(cplx<R>* A, cplx<R>* B, int lgm, int lt
     } else {
         for (int j = lt; j <= half; j += G) pre(j, j < half ? tw[j] : czero<C>());
     }
-    __syncthreads();
-    line_fft<R, false, RMAX, LGM>(A, A, false, lgm, lt, G, twl, lw);
+    line_sync<WS>();
+    line_fft<R, false, RMAX, LGM, LT, WS>(A, A, false, lgm, lt, G, twl, lw);
     // p range of this thread: [lt E, lt E + E), E = half / G (G <= half unless m < 2 RMAX... E >= 1)
     constexpr int PER = RMAX / 2;
     const int E = half >= G ? half / G : 1;
@@ -600,7 +620,7 @@ __device__ __forceinline__ void line_dst(cplx<R>* A, cplx<R>* B, int lgm, int lt
         const C d1 = run;
         const C c0 = A[0];
         const C off = cadd(c0, line_exclusive_scan<R>(run, G));
-        __syncthreads();   // every read of C is done before the outputs overwrite it
+        line_sync<WS>();   // every read of C is done before the outputs overwrite it
         const C b0 = cadd(off, d0), b1 = cadd(off, d1);
         const C a0 = csub(c0p, b0), a1 = csub(c1p, b1);
         // y = (i sc) v: y_{2p} from A_p, y_{2p+1} from B_p
@@ -631,7 +651,7 @@ __device__ __forceinline__ void line_dst(cplx<R>* A, cplx<R>* B, int lgm, int lt
         }
         const C c0 = A[0];
         const C off = cadd(c0, line_exclusive_scan<R>(run, G));
-        __syncthreads();   // every read of C is done before the outputs overwrite it
+        line_sync<WS>();   // every read of C is done before the outputs overwrite it
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
             const int p = p0 + e;
@@ -644,12 +664,12 @@ __device__ __forceinline__ void line_dst(cplx<R>* A, cplx<R>* B, int lgm, int lt
             }
         }
     }
-    __syncthreads();
+    line_sync<WS>();
 }
 
 // Toeplitz convolution core: on exit A holds IFFT_m(s_e FFT_m(x)) and B holds
 // IFFT_m(s_o FFT_m(W^j x)); the product at slot j is A[j] + conj(W_{2m}^j) B[j].
-template <typename R, int RMAX, int LGM, typename LT>
+template <typename R, int RMAX, int LGM, typename LT, bool WS = false>
 __device__ __forceinline__ void line_toeplitz(cplx<R>* A, cplx<R>* B, int lgm, int lt, int G,
                                               const cplx<R>* __restrict__ tw, const cplx<R>* twl,
                                               const R* __restrict__ sym_e, const R* __restrict__ sym_o,
@@ -664,26 +684,26 @@ __device__ __forceinline__ void line_toeplitz(cplx<R>* A, cplx<R>* B, int lgm, i
             if constexpr (LT::kWl) B[s] = cmul(A[s], cmul(lw.wl, w2r<R, RMAX>(i)));
             else B[s] = cmul(A[s], tw[s]);
         }
-        __syncthreads();
-        line_fft<R, false, RMAX, LGM>(A, B, true, lgm, lt, G, twl, lw);
+        line_sync<WS>();
+        line_fft<R, false, RMAX, LGM, LT, WS>(A, B, true, lgm, lt, G, twl, lw);
 #pragma unroll
         for (int i = 0; i < RMAX; ++i) {
             const int p = lt + i * Gc;
             A[p] = cscale(A[p], sym_e[p] * tscale);
             B[p] = cscale(B[p], sym_o[p] * tscale);
         }
-        __syncthreads();
-        line_fft<R, true, RMAX, LGM>(A, B, true, lgm, lt, G, twl, lw);
+        line_sync<WS>();
+        line_fft<R, true, RMAX, LGM, LT, WS>(A, B, true, lgm, lt, G, twl, lw);
     } else {
         for (int s = lt; s < m; s += G) B[s] = cmul(A[s], tw[s]);
-        __syncthreads();
-        line_fft<R, false, RMAX, LGM>(A, B, true, lgm, lt, G, twl, lw);
+        line_sync<WS>();
+        line_fft<R, false, RMAX, LGM, LT, WS>(A, B, true, lgm, lt, G, twl, lw);
         for (int p = lt; p < m; p += G) {
             A[p] = cscale(A[p], sym_e[p] * tscale);
             B[p] = cscale(B[p], sym_o[p] * tscale);
         }
-        __syncthreads();
-        line_fft<R, true, RMAX, LGM>(A, B, true, lgm, lt, G, twl, lw);
+        line_sync<WS>();
+        line_fft<R, true, RMAX, LGM, LT, WS>(A, B, true, lgm, lt, G, twl, lw);
     }
 }
 

@@ -313,21 +313,14 @@ __device__ __forceinline__ void config_one(GmresState* st, double tol, double ou
 //   FIN_K_PREPARE: initialises the GMRES state from ||b|| and reports;
 //   FIN_K_GIVENS:  finishes the Arnoldi step (Givens, stopping test);
 //   FIN_K_RESID:   takes the restart / refinement decision from ||b - A x||.
-enum FinishKind { FIN_K_PREPARE = 0, FIN_K_GIVENS = 1, FIN_K_RESID = 2, FIN_K_REDUCE = 3 };
+enum FinishKind { FIN_K_PREPARE = 0, FIN_K_GIVENS = 1, FIN_K_RESID = 2 };
 
 __device__ __forceinline__ void finish_body(const StreamArgs& a) {
     __shared__ double2 s_red[(kMaxRestart + 2) * kMaxWaves];
     __shared__ double2 s_tot[kMaxRestart + 2];
     GmresState* st = a.st;
     if (launch_skipped(a.check_active, a.guard_k, st)) return;
-    const int nv = (a.mode == FIN_K_REDUCE) ? a.nv : 1;
-    reduce_partials(a.pin, a.pin_stride, a.pin_nb, nv, s_tot, s_red);
-    if (a.mode == FIN_K_REDUCE) {
-        // totals written contiguously: the partials of a single producer
-        // workgroup with stride 1 (pout holds kMaxRestart + 2 values)
-        for (int i = threadIdx.x; i < nv; i += blockDim.x) a.pout[i] = s_tot[i];
-        return;
-    }
+    reduce_partials(a.pin, a.pin_stride, a.pin_nb, 1, s_tot, s_red);
     if (a.mode == FIN_K_GIVENS) {
         __shared__ double2 s_col[kMaxRestart + 1];
         __shared__ double2 s_sn[kMaxRestart];
@@ -413,6 +406,21 @@ __global__ __launch_bounds__(kStreamThreads) void k_cgs_batch(const StreamArgs* 
 }
 
 __global__ __launch_bounds__(kStreamThreads) void k_finish(StreamArgs a) { finish_body(a); }
+
+// Pre-reduction of wide partial sums (more producers than a consumer
+// workgroup should read): workgroup c sums producers
+// [c nb / chunks, (c + 1) nb / chunks) of each of the nv values, in a fixed
+// order, into pout[i * chunks + c].
+__global__ __launch_bounds__(kStreamThreads) void k_reduce_chunks(StreamArgs a, int chunks) {
+    __shared__ double2 s_red[(kMaxRestart + 2) * kMaxWaves];
+    __shared__ double2 s_tot[kMaxRestart + 2];
+    if (launch_skipped(a.check_active, a.guard_k, a.st)) return;
+    const int c = (int)blockIdx.x;
+    const int b0 = (int)((long long)a.pin_nb * c / chunks);
+    const int b1 = (int)((long long)a.pin_nb * (c + 1) / chunks);
+    reduce_partials(a.pin + b0, a.pin_stride, b1 - b0, a.nv, s_tot, s_red);
+    for (int i = threadIdx.x; i < a.nv; i += blockDim.x) a.pout[(size_t)i * chunks + c] = s_tot[i];
+}
 // one workgroup per instance
 __global__ __launch_bounds__(kStreamThreads) void k_finish_batch(const StreamArgs* args) { finish_body(args[blockIdx.x]); }
 
@@ -476,6 +484,10 @@ hipError_t launch_prepare(const StreamArgs& a, int blocks, hipStream_t s, const 
 
 hipError_t launch_finish(const StreamArgs& a, hipStream_t s, const LaunchEvents* te) {
     return launch_k(k_finish, dim3(1), dim3(kStreamThreads), 0, s, te, a);
+}
+
+hipError_t launch_reduce_chunks(const StreamArgs& a, int chunks, hipStream_t s, const LaunchEvents* te) {
+    return launch_k(k_reduce_chunks, dim3(chunks), dim3(kStreamThreads), 0, s, te, a, chunks);
 }
 
 // First update with nv basis vectors held in registers (nv <= kCgsRegMax)

@@ -34,8 +34,11 @@ hipError_t launch_pass_batch_f32(const PassVariant& v, int lgm, const PassArgs* 
 hipError_t launch_precond_setup(const StreamArgs& a, int blocks, hipStream_t s, const LaunchEvents* te = nullptr);
 hipError_t launch_prepare(const StreamArgs& a, int blocks, hipStream_t s, const LaunchEvents* te = nullptr);
 // one workgroup: StreamArgs::mode = 0 prepare (configures the solve from the cfg_ fields), 1 Givens,
-// 2 residual (nv = 1 for IR), 3 reduce nv values
+// 2 residual
 hipError_t launch_finish(const StreamArgs& a, hipStream_t s, const LaunchEvents* te = nullptr);
+// `chunks` workgroups: workgroup c sums a contiguous chunk of the a.pin_nb producers of each of the
+// a.nv values (a.pin, a.pin_stride) into a.pout[i * chunks + c]
+hipError_t launch_reduce_chunks(const StreamArgs& a, int chunks, hipStream_t s, const LaunchEvents* te = nullptr);
 hipError_t launch_cgs(int fp64, int mode, const StreamArgs& a, int blocks, hipStream_t s,
                       const LaunchEvents* te = nullptr);
 // out = conj(in), complex128

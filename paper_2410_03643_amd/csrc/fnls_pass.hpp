@@ -65,6 +65,9 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
         if (zout_p) zout_p = reinterpret_cast<C*>(zout_p) + (long long)j * a.jz;
     }
 
+    // compile-time plans with at most one wavefront per line synchronise the
+    // line transforms within the wavefront
+    constexpr bool kWS = LGM > 0 && ((1 << LGM) / RMAX) <= 64;
     const int lgm = LGM ? LGM : a.lgm;
     const int m = 1 << lgm;
     const int n = m - 1;
@@ -113,6 +116,31 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
         }
     };
 
+    // IN_CGS: totals of the second-round dot products d_i (every workgroup,
+    // in the same fixed order), h_i = sigma_i d_i and the update coefficients
+    // h_i sigma_i (basis vector i is stored as v_i / sigma_i); workgroup 0
+    // completes the Hessenberg column.  The line buffers serve as reduction
+    // scratch before the per-line set-up below overwrites them.
+    constexpr bool kCgs = (INM == IN_CGS);
+    __shared__ double2 s_cgs[kCgs ? 2 * (kMaxRestart + 2) : 1];
+    __shared__ double s_wn[kCgs ? 16 : 1];
+    if constexpr (kCgs) {
+        const int nv = basis_j + 1;
+        double2* s_tot = s_cgs;
+        double2* s_coef = s_cgs + (kMaxRestart + 2);
+        reduce_partials(a.cgs_pin, a.cgs_stride, a.cgs_nb, nv, s_tot, reinterpret_cast<double2*>(smem_raw));
+        if (tid < nv) {
+            const double sg = a.st->sigma[tid];
+            const double2 h = dmk(s_tot[tid].x * sg, s_tot[tid].y * sg);
+            s_coef[tid] = dmk(h.x * sg, h.y * sg);
+            if (blk == 0) {
+                a.st->hcol[tid].x += h.x;
+                a.st->hcol[tid].y += h.y;
+            }
+        }
+        __syncthreads();
+    }
+
     // per-line base offset and Lambda of the other axes
     for (int l = tid; l < L; l += T) {
         const long long lg = (long long)blk * L + l;
@@ -144,6 +172,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
     __syncthreads();
 
     // ---- load phase
+    double wnrm = 0.0;   // IN_CGS: this thread's part of ||w||^2
     {
         double sig = 1.0;
         if (INM == IN_BASIS) sig = a.st->sigma[basis_j];
@@ -161,6 +190,20 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
                     const long long gi = base + (long long)j * stride;
                     if (INM == IN_PLAIN) {
                         v = ld<R>(in_p, gi);
+                    } else if constexpr (kCgs) {
+                        // w -= sum_i c_i v_i as explicit fused multiply-adds in
+                        // the order of the streaming update (same rounding)
+                        const C wv = ld<R>(in_p, gi);
+                        double wx = wv.x, wy = wv.y;
+                        const double2* s_coef = s_cgs + (kMaxRestart + 2);
+                        for (int i = 0; i <= basis_j; ++i) {
+                            const C t = (i == 0) ? ld<R>(a.v0, gi) : ld<R>(a.vbase, (long long)(i - 1) * a.N + gi);
+                            cmsub(wx, wy, s_coef[i], t.x, t.y);
+                        }
+                        v = cm<R>(static_cast<R>(wx), static_cast<R>(wy));
+                        stc<R>(const_cast<void*>(in_p), gi, v);
+                        wnrm = fma((double)v.x, (double)v.x, wnrm);
+                        wnrm = fma((double)v.y, (double)v.y, wnrm);
                     } else if (INM == IN_BASIS) {
                         const C t = ld<R>(in_p, gi);
                         v = cm<R>(static_cast<R>(t.x * sig), static_cast<R>(t.y * sig));
@@ -200,13 +243,27 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
             }
         }
     }
+    if constexpr (kCgs) {
+        // wavefront sums of ||w||^2 (the barrier below orders them before
+        // thread 0 adds them in wavefront order)
+        wnrm = wave_sum(wnrm);
+        if ((tid & 63) == 0) s_wn[tid >> 6] = wnrm;
+    }
     __syncthreads();
+    if constexpr (kCgs) {
+        if (tid == 0) {
+            double sum = 0.0;
+            for (int w = 0; w < (T >> 6); ++w) sum += s_wn[w];
+            a.pout[blk] = dmk(sum, 0.0);
+        }
+    }
 
     C* A = lds + (size_t)line * LS;
     C* B = kTwoBuf ? A + PA : A;   // B exists only for the Toeplitz product
 
-    // ---- transform stages
-    if (OPS & OP_DST1) line_dst<R, RMAX, LGM>(A, B, lgm, lt, G, tw, twl, ltw);
+    // ---- transform stages (line-local: with WS, G <= 64 threads per line,
+    // each wavefront transforms its own lines without workgroup barriers)
+    if (OPS & OP_DST1) line_dst<R, RMAX, LGM, decltype(ltw), kWS>(A, B, lgm, lt, G, tw, twl, ltw);
     if (OPS & OP_DIV) {
         const R om = static_cast<R>(a.omega);
         const R lo = s_lamo[line];
@@ -217,9 +274,11 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
             // v / (om + i mu) = v (om - i mu) / den
             A[k] = cm<R>((v.x * om + v.y * mu) / den, (v.y * om - v.x * mu) / den);
         }
-        __syncthreads();
+        line_sync<kWS>();
     }
-    if (OPS & OP_DST2) line_dst<R, RMAX, LGM>(A, B, lgm, lt, G, tw, twl, ltw);
+    if (OPS & OP_DST2) line_dst<R, RMAX, LGM, decltype(ltw), kWS>(A, B, lgm, lt, G, tw, twl, ltw);
+    // the element phases read every line of the workgroup
+    if constexpr (kWS && (OPS & (OP_DST1 | OP_DIV | OP_DST2)) != 0) __syncthreads();
 
     constexpr bool kToep = (OPS & OP_TOEP) != 0;
     constexpr bool kKeepZ = kToep && (OUTM == OUT_ACC_FIRST);
@@ -292,8 +351,10 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
 
     // ---- Toeplitz product and element phase 2
     if (kToep) {
-        line_toeplitz<R, RMAX, LGM>(A, B, lgm, lt, G, tw, twl, reinterpret_cast<const R*>(a.sym_e),
-                         reinterpret_cast<const R*>(a.sym_o), tscale, ltw);
+        line_toeplitz<R, RMAX, LGM, decltype(ltw), kWS>(A, B, lgm, lt, G, tw, twl,
+                                                         reinterpret_cast<const R*>(a.sym_e),
+                                                         reinterpret_cast<const R*>(a.sym_o), tscale, ltw);
+        if constexpr (kWS) __syncthreads();   // element phase 2 reads every line
         const R cT = static_cast<R>(a.cT);
         // operands first (see element phase 1)
         constexpr bool kFirst = (OUTM == OUT_ACC_FIRST);
@@ -455,13 +516,18 @@ static hipError_t launch_pass_t(const PassArgs& a, int blocks, size_t lds, hipSt
 template <typename R, int INM, int OPS, int ZM, int OUTM, int FIN>
 static hipError_t launch_pass_r(int rmax, const PassArgs& a, int blocks, size_t lds, hipStream_t s,
                                 const LaunchEvents* te) {
-    if (a.lgm == 10) {   // m = 1024: compile-time plan
+    // compile-time plans for m = 1024, 512 and 256 (d = 2, n = 1023 and 511;
+    // d = 3, n = 255); those with G = m / rmax <= 64 threads per line
+    // transform each line within one wavefront (no workgroup barriers)
+    if (a.lgm == 10) {
         if (rmax == 4) return launch_pass_t<R, 4, 10, INM, OPS, ZM, OUTM, FIN>(a, blocks, lds, s, te);
         if (rmax == 8) return launch_pass_t<R, 8, 10, INM, OPS, ZM, OUTM, FIN>(a, blocks, lds, s, te);
+        if (rmax == 16) return launch_pass_t<R, 16, 10, INM, OPS, ZM, OUTM, FIN>(a, blocks, lds, s, te);
     }
-    // m = 512 and 256 (d = 2, n = 511; d = 3, n = 255): compile-time radix-4 plans
     if (a.lgm == 9 && rmax == 4) return launch_pass_t<R, 4, 9, INM, OPS, ZM, OUTM, FIN>(a, blocks, lds, s, te);
+    if (a.lgm == 9 && rmax == 8) return launch_pass_t<R, 8, 9, INM, OPS, ZM, OUTM, FIN>(a, blocks, lds, s, te);
     if (a.lgm == 8 && rmax == 4) return launch_pass_t<R, 4, 8, INM, OPS, ZM, OUTM, FIN>(a, blocks, lds, s, te);
+    if (a.lgm == 8 && rmax == 8) return launch_pass_t<R, 8, 8, INM, OPS, ZM, OUTM, FIN>(a, blocks, lds, s, te);
     switch (rmax) {
         case 4: return launch_pass_t<R, 4, 0, INM, OPS, ZM, OUTM, FIN>(a, blocks, lds, s, te);
         case 8: return launch_pass_t<R, 8, 0, INM, OPS, ZM, OUTM, FIN>(a, blocks, lds, s, te);
@@ -492,6 +558,9 @@ hipError_t dispatch_pass(const PassVariant& v, const PassArgs& a, int blocks, si
     // last sine transform of the preconditioner (d >= 2)
     FNLS_PASS_CASE(R, IN_PLAIN, LASTDST, Z_NONE, OUT_LINE, FIN_WRITE)
     FNLS_PASS_CASE(R, IN_PLAIN, LASTDST_T, Z_WRITE, OUT_ACC_FIRST, FIN_WRITE)
+    FNLS_PASS_CASE(R, IN_BASIS, LASTDST_T, Z_WRITE, OUT_ACC_FIRST, FIN_WRITE)
+    // second Gram-Schmidt update fused with the next step's first sine transform
+    FNLS_PASS_CASE(R, IN_CGS, DST, Z_NONE, OUT_LINE, FIN_WRITE)
     // d = 1: the whole preconditioned operator on one line
     FNLS_PASS_CASE(R, IN_PLAIN, FULL1, Z_NONE, OUT_LINE, FIN_WRITE)
     FNLS_PASS_CASE(R, IN_BASIS, FULL1_T, Z_NONE, OUT_ACC_FIRST, FIN_WDOTS)
@@ -508,12 +577,13 @@ hipError_t dispatch_pass(const PassVariant& v, const PassArgs& a, int blocks, si
     return hipErrorInvalidValue;
 }
 
-// ---- batched launches (radix 4, 1024 threads per workgroup; line length
-// 2^LGM for every instance of the launch, or generic with LGM = 0) ----
-template <typename R, int LGM, int INM, int OPS, int ZM, int OUTM, int FIN>
+// ---- batched launches: radix 4 (or 8 for the compile-time line lengths),
+// G * L threads per workgroup; line length 2^LGM for every instance of the
+// launch, or generic with LGM = 0 (radix 4) ----
+template <typename R, int RMAX, int LGM, int INM, int OPS, int ZM, int OUTM, int FIN>
 static hipError_t launch_pass_batch_l(const PassArgs* args, const int* offs, int count, int blocks, size_t lds,
                                       int threads, hipStream_t s) {
-    auto kern = k_pass_batch<R, 4, LGM, INM, OPS, ZM, OUTM, FIN>;
+    auto kern = k_pass_batch<R, RMAX, LGM, INM, OPS, ZM, OUTM, FIN>;
     static size_t granted = 64 * 1024;
     if (lds > granted) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
@@ -522,24 +592,33 @@ static hipError_t launch_pass_batch_l(const PassArgs* args, const int* offs, int
         granted = lds;
     }
     if (!args) return hipSuccess;   // attribute only (before a graph capture)
-    if (threads != PassThreads<4>::v) return hipErrorInvalidConfiguration;
+    if (threads > PassThreads<RMAX>::v || threads % 64 != 0) return hipErrorInvalidConfiguration;
     return launch_k(kern, dim3(blocks), dim3(threads), lds, s, nullptr, args, offs, count);
 }
 
 template <typename R, int INM, int OPS, int ZM, int OUTM, int FIN>
-static hipError_t launch_pass_batch_t(int lgm, const PassArgs* args, const int* offs, int count, int blocks,
-                                      size_t lds, int threads, hipStream_t s) {
+static hipError_t launch_pass_batch_t(int lgm, int rmax, const PassArgs* args, const int* offs, int count,
+                                      int blocks, size_t lds, int threads, hipStream_t s) {
+    if (rmax == 8) {
+        switch (lgm) {
+            case 10: return launch_pass_batch_l<R, 8, 10, INM, OPS, ZM, OUTM, FIN>(args, offs, count, blocks, lds, threads, s);
+            case 9: return launch_pass_batch_l<R, 8, 9, INM, OPS, ZM, OUTM, FIN>(args, offs, count, blocks, lds, threads, s);
+            case 8: return launch_pass_batch_l<R, 8, 8, INM, OPS, ZM, OUTM, FIN>(args, offs, count, blocks, lds, threads, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    if (rmax != 4) return hipErrorInvalidValue;
     switch (lgm) {
-        case 10: return launch_pass_batch_l<R, 10, INM, OPS, ZM, OUTM, FIN>(args, offs, count, blocks, lds, threads, s);
-        case 9: return launch_pass_batch_l<R, 9, INM, OPS, ZM, OUTM, FIN>(args, offs, count, blocks, lds, threads, s);
-        case 8: return launch_pass_batch_l<R, 8, INM, OPS, ZM, OUTM, FIN>(args, offs, count, blocks, lds, threads, s);
-        default: return launch_pass_batch_l<R, 0, INM, OPS, ZM, OUTM, FIN>(args, offs, count, blocks, lds, threads, s);
+        case 10: return launch_pass_batch_l<R, 4, 10, INM, OPS, ZM, OUTM, FIN>(args, offs, count, blocks, lds, threads, s);
+        case 9: return launch_pass_batch_l<R, 4, 9, INM, OPS, ZM, OUTM, FIN>(args, offs, count, blocks, lds, threads, s);
+        case 8: return launch_pass_batch_l<R, 4, 8, INM, OPS, ZM, OUTM, FIN>(args, offs, count, blocks, lds, threads, s);
+        default: return launch_pass_batch_l<R, 4, 0, INM, OPS, ZM, OUTM, FIN>(args, offs, count, blocks, lds, threads, s);
     }
 }
 
 #define FNLS_BATCH_CASE(R, INM, OPS, ZM, OUTM, FIN)                                             \
     if (v.inm == INM && v.ops == (OPS) && v.zm == ZM && v.outm == OUTM && v.fin == FIN)         \
-        return launch_pass_batch_t<R, INM, OPS, ZM, OUTM, FIN>(lgm, args, offs, count, blocks, lds, threads, s);
+        return launch_pass_batch_t<R, INM, OPS, ZM, OUTM, FIN>(lgm, v.rmax, args, offs, count, blocks, lds, threads, s);
 
 template <typename R>
 hipError_t dispatch_pass_batch(const PassVariant& v, int lgm, const PassArgs* args, const int* offs,

@@ -53,7 +53,7 @@ class HostStats(ctypes.Structure):
     _fields_ = [("solves", ctypes.c_longlong), ("cycles", ctypes.c_longlong),
                 ("iterations", ctypes.c_longlong), ("stop_predictions", ctypes.c_longlong),
                 ("ends_ahead", ctypes.c_longlong), ("late_reads", ctypes.c_longlong),
-                ("cycles_ahead", ctypes.c_longlong), ("reserved", ctypes.c_longlong)]
+                ("cycles_ahead", ctypes.c_longlong), ("early_stops", ctypes.c_longlong)]
 
 
 class KernelStat(ctypes.Structure):
@@ -142,6 +142,10 @@ def lib() -> ctypes.CDLL:
     L.fnls_batch_step.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                   ctypes.POINTER(Opts), ctypes.POINTER(Info)]
     L.fnls_batch_step.restype = ci
+    L.fnls_batch_autotune.argtypes = [vp, ctypes.POINTER(vp), ci, ci, ctypes.POINTER(ci)]
+    L.fnls_batch_autotune.restype = ci
+    L.fnls_batch_schedule.argtypes = [vp, ci, ci, ci, ctypes.POINTER(ci), ctypes.POINTER(ci)]
+    L.fnls_batch_schedule.restype = ci
     L.fnls_batch_last_error.argtypes = [vp]
     L.fnls_batch_last_error.restype = ctypes.c_char_p
     L.fnls_batch_graph_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)]
@@ -282,7 +286,7 @@ class Solver:
         """Counters of the host's GMRES sequencing (fnls_get_host_stats)."""
         st = HostStats()
         self._check(lib().fnls_get_host_stats(self._ctx, ctypes.byref(st), 1 if reset else 0))
-        return {name: getattr(st, name) for name, _ in HostStats._fields_ if name != "reserved"}
+        return {name: getattr(st, name) for name, _ in HostStats._fields_}
 
     def rhs(self, u_prev, out=None):
         b = self._out() if out is None else out
@@ -437,6 +441,22 @@ class Batch:
         if len(ts) != n:
             raise ValueError("%s: expected %d tensors" % (name, n))
         return (ctypes.c_void_p * n)(*[s._vec(t, name) for s, t in zip(self.solvers, ts)])
+
+    def autotune(self, bs, precision="fp64", reps: int = 3) -> int:
+        """fnls_batch_autotune: time batched solves of bs over the schedules of
+        each line-length class; returns the number of classes tuned."""
+        p = {"fp64": FP64, "fp32_ir": FP32_IR}[precision] if isinstance(precision, str) else precision
+        n = ctypes.c_int()
+        self._check(lib().fnls_batch_autotune(self._b, self._ptrs(bs, "b"), p, reps, ctypes.byref(n)))
+        return n.value
+
+    def schedule(self, n: int, precision="fp64", strided: bool = True):
+        """(rmax, lines) the batch's autotuner chose for line length n + 1, or
+        (0, 0) for the default shape."""
+        p = {"fp64": FP64, "fp32_ir": FP32_IR}[precision] if isinstance(precision, str) else precision
+        rm, li = ctypes.c_int(), ctypes.c_int()
+        self._check(lib().fnls_batch_schedule(self._b, n, p, 1 if strided else 0, ctypes.byref(rm), ctypes.byref(li)))
+        return rm.value, li.value
 
     def solve(self, bs, outs=None, *, tol=1e-10, restart=30, maxit=2000, precision="fp64", inner_tol=1e-5,
               max_outer=20, lookahead=1, graph=False):

@@ -75,6 +75,9 @@ def test_null_context_is_rejected(L):
     assert L.fnls_batch_solve(None, None, None, None, None) == fnls.ERR_INVALID_ARG
     assert L.fnls_batch_step(None, None, None, None, None, None) == fnls.ERR_INVALID_ARG
     assert L.fnls_batch_last_error(None) == b"null batch"
+    assert L.fnls_batch_autotune(None, None, 0, 1, None) == fnls.ERR_INVALID_ARG
+    rm, li = ctypes.c_int(-1), ctypes.c_int(-1)
+    assert L.fnls_batch_schedule(None, 1023, 0, 1, ctypes.byref(rm), ctypes.byref(li)) == fnls.ERR_INVALID_ARG
     assert L.fnls_batch_workspace_bytes(0) == 0 and L.fnls_batch_workspace_bytes(4097) == 0
     assert L.fnls_batch_workspace_bytes(64) >= 16 << 20
     # the workspace grows with the count (argument tables of the cached graphs)

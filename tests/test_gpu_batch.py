@@ -133,6 +133,21 @@ def test_batched_workload_64_instances(torch_dev):
           flush=True)
     assert all(i.status == 0 and i.relres_true < TOL for i in infos)
     assert all(abs(a.iters - b.iters) <= 1 for a, b in zip(infos, sinfos))
+    # one instance of every size class against the oracle's FP64 solution of
+    # its system (to 1e-13): within cond(A) * (relres + 1e-13)
+    for n in sizes:
+        k = next(i for i, p in enumerate(cases) if p.n == n)
+        p = cases[k]
+        o = oracle.OracleSolver(p.alpha, p.rho, p.d, p.n, p.h, p.tau)
+        o.precond_setup(p.u)
+        b = o.rhs(p.u)
+        xo, io = o.solve(b, tol=1e-13)
+        x = to_np(outs[k])
+        err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+        kap = kappa_bound(p)
+        print("instance %d (n=%d): |x_batch - x_oracle| / |x_oracle| = %.2e (cond bound %.1f, relres %.2e)"
+              % (k, n, err, kap, infos[k].relres_true), flush=True)
+        assert err <= kap * (infos[k].relres_true + 1e-13)
     # the oracle's residual for a sample of instances, and agreement with the single path
     for k in range(0, 64, 9):
         p = cases[k]
@@ -144,6 +159,70 @@ def test_batched_workload_64_instances(torch_dev):
         e1 = np.linalg.norm(x - to_np(single[k])) / np.linalg.norm(to_np(single[k]))
         print("instance %d (n=%d): oracle residual %.2e, |x_batch - x_single| %.1e" % (k, p.n, res, e1), flush=True)
         assert res < TOL and e1 <= 1e-8
+    batch.close()
+
+
+def kappa_bound(p):
+    """cond_2(A) <= sqrt(1 + ||B||^2) for A = B + iI, B = D - T_d real
+    symmetric: ||T_d|| <= d mu 2 c_0 (Gershgorin, sum |c_k| = 2 c_0) and
+    ||D|| <= rho dt max |u|^2."""
+    from oracle import fcd
+    c0 = fcd.coefficients(p.alpha, 2)[0]
+    nB = p.d * fcd.mu(p.alpha, p.h, p.tau) * 2.0 * c0 + p.rho * p.tau * float(np.abs(p.u).max() ** 2)
+    return float(np.sqrt(1.0 + nB * nB))
+
+
+def test_batched_workload_autotuned(torch_dev):
+    """The 64-instance workload with autotuned schedules: fnls_batch_autotune
+    times batched solves over radix x lines for each line-length class with a
+    compile-time plan (m = 256, 512, 1024) and keeps what is faster, and the
+    batch then launches each class with its schedule.  Timed against the
+    default schedule (radix 4, 1024 threads) and not slower (5 % for noise);
+    every instance still converges, and its solution agrees with the
+    default one within cond(A) * (relres + relres)."""
+    from paper_2410_03643_amd.fnls import Batch, Solver
+    torch, dev = torch_dev
+    cases = inputs.batched_cases(64)
+    solvers = [Solver(p.alpha, p.rho, p.d, p.n, p.h, p.tau, device=dev) for p in cases]
+    us = [torch.from_numpy(p.u).to(dev) for p in cases]
+    batch = Batch(solvers)
+
+    def timed(outs):
+        batch.step(us, us, outs, tol=TOL, precision="fp32_ir")
+        torch.cuda.synchronize()
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            _, infos = batch.step(us, us, outs, tol=TOL, precision="fp32_ir")
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps, infos
+
+    x_def = [torch.empty_like(u) for u in us]
+    t_def, i_def = timed(x_def)
+    bs = []
+    for s, u in zip(solvers, us):
+        s.precond_setup(u)
+        bs.append(s.rhs(u))
+    t0 = time.perf_counter()
+    classes = batch.autotune(bs, precision="fp32_ir", reps=2)
+    t_tune = time.perf_counter() - t0
+    chosen = {n: (batch.schedule(n, "fp32_ir", strided=False), batch.schedule(n, "fp32_ir", strided=True))
+              for n in sorted({p.n for p in cases if p.n + 1 in (256, 512, 1024)})}
+    print("schedules (contiguous, strided) as (rmax, lines): %s" % chosen, flush=True)
+    x_tun = [torch.empty_like(u) for u in us]
+    t_tun, i_tun = timed(x_tun)
+    print("64 instances, FP32-IR step of all: default schedules %.2f ms, autotuned %.2f ms (%d classes tuned in "
+          "%.1f s)" % (1e3 * t_def, 1e3 * t_tun, classes, t_tune), flush=True)
+    assert classes == len({p.n for p in cases if p.n + 1 in (256, 512, 1024)})
+    assert t_tun <= 1.05 * t_def
+    worst = 0.0
+    for k, p in enumerate(cases):
+        assert i_tun[k].status == 0 and i_tun[k].relres_true < TOL
+        assert abs(i_tun[k].iters - i_def[k].iters) <= 2
+        e = float(torch.linalg.vector_norm(x_tun[k] - x_def[k]).item() / torch.linalg.vector_norm(x_def[k]).item())
+        worst = max(worst, e / kappa_bound(p))
+        assert e <= kappa_bound(p) * (i_tun[k].relres_true + i_def[k].relres_true)
+    print("largest |x_tuned - x_default| / |x_default| / cond bound: %.2e" % worst, flush=True)
     batch.close()
 
 

