@@ -460,10 +460,11 @@ __device__ __forceinline__ void stockham_stage(cplx<R>* A, cplx<R>* B, bool both
 
 // Compile-time stage plan (m = 2^LGM known at compile time): every index,
 // bound and radix folds to a constant.
-template <typename R, bool INV, int RMAX, int LGM, int LGNS, typename LT, bool WS>
+// Stages LGNS .. LGEND - 1 (default: through the last one).
+template <typename R, bool INV, int RMAX, int LGM, int LGNS, typename LT, bool WS, int LGEND = LGM>
 __device__ __forceinline__ void fft_stages_ct(cplx<R>* A, cplx<R>* B, bool both, int lt, const cplx<R>* twl,
                                               const LT& lw) {
-    if constexpr (LGNS < LGM) {
+    if constexpr (LGNS < LGEND) {
         constexpr int rem = LGM - LGNS;
         constexpr int lr = rem < Lg<RMAX>::v ? rem : Lg<RMAX>::v;
         constexpr int G = (1 << LGM) / RMAX;
@@ -474,7 +475,7 @@ __device__ __forceinline__ void fft_stages_ct(cplx<R>* A, cplx<R>* B, bool both,
             else wr = lw.w2;
         }
         stockham_stage<R, (1 << lr), RMAX, INV, kReg, WS>(A, B, both, LGM, LGNS, lt, G, twl, wr);
-        fft_stages_ct<R, INV, RMAX, LGM, LGNS + lr, LT, WS>(A, B, both, lt, twl, lw);
+        fft_stages_ct<R, INV, RMAX, LGM, LGNS + lr, LT, WS, LGEND>(A, B, both, lt, twl, lw);
     }
 }
 
@@ -509,30 +510,93 @@ __device__ __forceinline__ void line_fft(cplx<R>* A, cplx<R>* B, bool both, int 
     line_sync<WS>();
 }
 
+// Cross-lane moves without LDS: DPP (data-parallel primitives) on 32-bit
+// halves, lanes without a source lane reading 0; readlane broadcasts one
+// lane's value to the wavefront.
+template <int CTRL, typename R>
+__device__ __forceinline__ R dpp_mov(R v) {
+    if constexpr (sizeof(R) == 8) {
+        const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
+        const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, true);
+        const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, true);
+        return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+    } else {
+        return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+    }
+}
+template <typename R>
+__device__ __forceinline__ R read_lane(R v, int lane) {
+    if constexpr (sizeof(R) == 8) {
+        const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
+        const int lo = __builtin_amdgcn_readlane((int)(unsigned)b, lane);
+        const int hi = __builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+        return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+    } else {
+        return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+    }
+}
+// DPP controls: row_shr:d (within rows of 16 lanes), quad_perm [1,0,3,2] and
+// [2,3,0,1], row_half_mirror, row_mirror.
+constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
+constexpr int kDppQuadSwap1 = 0xB1, kDppQuadSwap2 = 0x4E, kDppHalfMirror = 0x141, kDppRowMirror = 0x140;
+
 // Exclusive prefix sum of v over the G threads of a line (threads lt = 0..G-1
-// are consecutive lanes of the workgroup, G a power of two): a tree scan
-// within each wavefront segment, then the totals of the line's earlier
-// wavefronts from LDS.  Must be reached by the whole workgroup.
+// are consecutive lanes of the workgroup, G a power of two).  Segments of 16
+// lanes or more: a tree scan within each row of 16 lanes by DPP row shifts,
+// then the totals of the segment's earlier rows; narrower segments use lane
+// shuffles.  Lines wider than a wavefront add the totals of their earlier
+// wavefronts from LDS.  Must be reached by the whole workgroup (full
+// wavefronts).
 template <typename R>
 __device__ __forceinline__ cplx<R> line_exclusive_scan(cplx<R> v, int G) {
     using C = cplx<R>;
     __shared__ C s_wtot[16];   // one total per wavefront (<= 1024 threads)
     const int lane = threadIdx.x & 63;
     const int sw = G < 64 ? G : 64;     // segment width
-    const int ls = lane & (sw - 1);     // position in the segment
     C inc = v;
-    for (int d = 1; d < sw; d <<= 1) {
-        const R tx = __shfl_up(inc.x, d, sw);
-        const R ty = __shfl_up(inc.y, d, sw);
-        if (ls >= d) {
-            inc.x += tx;
-            inc.y += ty;
-        }
-    }
     C exc;
-    exc.x = __shfl_up(inc.x, 1, sw);
-    exc.y = __shfl_up(inc.y, 1, sw);
-    if (ls == 0) exc = czero<C>();
+    if (sw >= 16) {
+        inc.x += dpp_mov<kDppRowShr1>(inc.x);
+        inc.y += dpp_mov<kDppRowShr1>(inc.y);
+        inc.x += dpp_mov<kDppRowShr2>(inc.x);
+        inc.y += dpp_mov<kDppRowShr2>(inc.y);
+        inc.x += dpp_mov<kDppRowShr4>(inc.x);
+        inc.y += dpp_mov<kDppRowShr4>(inc.y);
+        inc.x += dpp_mov<kDppRowShr8>(inc.x);
+        inc.y += dpp_mov<kDppRowShr8>(inc.y);
+        exc.x = dpp_mov<kDppRowShr1>(inc.x);   // 0 in the first lane of a row
+        exc.y = dpp_mov<kDppRowShr1>(inc.y);
+        // totals of rows 0, 1, 2 of the wavefront
+        const C r0 = cm<R>(read_lane(inc.x, 15), read_lane(inc.y, 15));
+        const C r1 = cm<R>(read_lane(inc.x, 31), read_lane(inc.y, 31));
+        const C r2 = cm<R>(read_lane(inc.x, 47), read_lane(inc.y, 47));
+        const int row = lane >> 4;
+        C add = czero<C>();
+        if (sw == 32) {
+            if (row == 1) add = r0;
+            if (row == 3) add = r2;
+        } else if (sw == 64) {
+            const C r01 = cadd(r0, r1);
+            if (row == 1) add = r0;
+            if (row == 2) add = r01;
+            if (row == 3) add = cadd(r01, r2);
+        }
+        inc = cadd(inc, add);
+        exc = cadd(exc, add);
+    } else {
+        const int ls = lane & (sw - 1);     // position in the segment
+        for (int d = 1; d < sw; d <<= 1) {
+            const R tx = __shfl_up(inc.x, d, sw);
+            const R ty = __shfl_up(inc.y, d, sw);
+            if (ls >= d) {
+                inc.x += tx;
+                inc.y += ty;
+            }
+        }
+        exc.x = __shfl_up(inc.x, 1, sw);
+        exc.y = __shfl_up(inc.y, 1, sw);
+        if (ls == 0) exc = czero<C>();
+    }
     if (G > 64) {
         const int wave = threadIdx.x >> 6;
         if (lane == 63) s_wtot[wave] = inc;
@@ -554,10 +618,16 @@ __device__ __forceinline__ cplx<R> line_exclusive_scan(cplx<R> v, int G) {
 // B_p = C_0 + sum_{q=1..p} (C_q + C_{m-q}), A_p = C_p - B_p.  The sum is a
 // prefix scan over p < m/2 (each thread owns a contiguous range of p).
 // Caller has synchronised after writing A.  tw[s] = W_{2m}^s (global table).
-// B is not used.
-template <typename R, int RMAX, int LGM, typename LT, bool WS = false>
+// B is not used.  post(k, y_k) is applied to every output k >= 1 before it
+// is stored (an elementwise operation fused into the transform's last step).
+struct DstNoPost {
+    template <typename C>
+    __device__ __forceinline__ C operator()(int, C v) const { return v; }
+};
+template <typename R, int RMAX, int LGM, typename LT, bool WS = false, typename POST = DstNoPost>
 __device__ __forceinline__ void line_dst(cplx<R>* A, cplx<R>* B, int lgm, int lt, int G,
-                                         const cplx<R>* __restrict__ tw, const cplx<R>* twl, const LT& lw) {
+                                         const cplx<R>* __restrict__ tw, const cplx<R>* twl, const LT& lw,
+                                         const POST& post = POST{}) {
     using C = cplx<R>;
     constexpr bool kReg = LT::kReg;
     (void)B;
@@ -624,15 +694,16 @@ __device__ __forceinline__ void line_dst(cplx<R>* A, cplx<R>* B, int lgm, int lt
         const C b0 = cadd(off, d0), b1 = cadd(off, d1);
         const C a0 = csub(c0p, b0), a1 = csub(c1p, b1);
         // y = (i sc) v: y_{2p} from A_p, y_{2p+1} from B_p
+        const int o = 2 * p0;
         const R y0r = (p0 == 0) ? R(0) : -sc * a0.y, y0i = (p0 == 0) ? R(0) : sc * a0.x;
-        const C y0 = cm<R>(y0r, y0i);
-        const C y1 = cm<R>(-sc * b0.y, sc * b0.x);
-        const C y2 = cm<R>(-sc * a1.y, sc * a1.x);
-        const C y3 = cm<R>(-sc * b1.y, sc * b1.x);
+        C y0 = cm<R>(y0r, y0i);
+        if (p0 != 0) y0 = post(o, y0);
+        const C y1 = post(o + 1, cm<R>(-sc * b0.y, sc * b0.x));
+        const C y2 = post(o + 2, cm<R>(-sc * a1.y, sc * a1.x));
+        const C y3 = post(o + 3, cm<R>(-sc * b1.y, sc * b1.x));
         const int rot = out_rot<R>();
         C u0, u1, u2, u3;
         rot4(y0, y1, y2, y3, rot, u0, u1, u2, u3);
-        const int o = 2 * p0;
         A[o + (0 ^ rot)] = u0;
         A[o + (1 ^ rot)] = u1;
         A[o + (2 ^ rot)] = u2;
@@ -659,8 +730,8 @@ __device__ __forceinline__ void line_dst(cplx<R>* A, cplx<R>* B, int lgm, int lt
                 const C bp = cadd(off, dinc[e]);
                 const C ap = csub(cp[e], bp);
                 // y = (i sc) v
-                A[2 * p] = (p == 0) ? czero<C>() : cm<R>(-sc * ap.y, sc * ap.x);
-                A[2 * p + 1] = cm<R>(-sc * bp.y, sc * bp.x);
+                A[2 * p] = (p == 0) ? czero<C>() : post(2 * p, cm<R>(-sc * ap.y, sc * ap.x));
+                A[2 * p + 1] = post(2 * p + 1, cm<R>(-sc * bp.y, sc * bp.x));
             }
         }
     }
@@ -676,24 +747,60 @@ __device__ __forceinline__ void line_toeplitz(cplx<R>* A, cplx<R>* B, int lgm, i
                                               R tscale, const LT& lw) {
     const int m = 1 << lgm;
     if constexpr (LT::kReg) {
-        // G = m / RMAX: thread lt owns s = lt + i G, i < RMAX
-        constexpr int Gc = (1 << LGM) / RMAX;
+        // Compile-time radix-4 plan (G = m / 4, one butterfly per thread and
+        // stage).  The first stage of a transform reads slots lt + r G, and
+        // the last stage writes its outputs to the same slots, so the
+        // W_{2m}^j pre-multiplication of B is applied to the first stage's
+        // registers, and the symbol multiplication joins the forward
+        // transform's last stage to the inverse transform's first stage
+        // without a round trip through LDS.  Same operations, same order.
+        using C = cplx<R>;
+        constexpr int Gc = (1 << LGM) / 4;
+        static_assert(RMAX == 4, "register plan");
+        {
+            StageRegs<R, 4, 4> ga, gb;
 #pragma unroll
-        for (int i = 0; i < RMAX; ++i) {
-            const int s = lt + i * Gc;
-            if constexpr (LT::kWl) B[s] = cmul(A[s], cmul(lw.wl, w2r<R, RMAX>(i)));
-            else B[s] = cmul(A[s], tw[s]);
+            for (int r = 0; r < 4; ++r) {
+                const int s = lt + r * Gc;
+                ga.v[0][r] = A[s];
+                if constexpr (LT::kWl) gb.v[0][r] = cmul(ga.v[0][r], cmul(lw.wl, w2r<R, 4>(r)));
+                else gb.v[0][r] = cmul(ga.v[0][r], tw[s]);
+            }
+            dft<4, false>(ga.v[0]);
+            dft<4, false>(gb.v[0]);
+            line_sync<WS>();
+            stage_store<R, 4, 4>(ga, A, LGM, 0, lt, Gc);
+            stage_store<R, 4, 4>(gb, B, LGM, 0, lt, Gc);
+            line_sync<WS>();
         }
-        line_sync<WS>();
-        line_fft<R, false, RMAX, LGM, LT, WS>(A, B, true, lgm, lt, G, twl, lw);
+        fft_stages_ct<R, false, 4, LGM, 2, LT, WS, LGM - 2>(A, B, true, lt, twl, lw);
+        {
+            // forward last stage (no register twiddle: LGM - 2 >= 6)
+            StageRegs<R, 4, 4> ga, gb;
+            R se[4], so[4];
 #pragma unroll
-        for (int i = 0; i < RMAX; ++i) {
-            const int p = lt + i * Gc;
-            A[p] = cscale(A[p], sym_e[p] * tscale);
-            B[p] = cscale(B[p], sym_o[p] * tscale);
+            for (int r = 0; r < 4; ++r) {
+                se[r] = sym_e[lt + r * Gc] * tscale;
+                so[r] = sym_o[lt + r * Gc] * tscale;
+            }
+            stage_load<R, 4, 4, false>(ga, A, LGM, LGM - 2, lt, Gc, twl);
+            stage_load<R, 4, 4, false>(gb, B, LGM, LGM - 2, lt, Gc, twl);
+            // output r belongs to slot lt + r G; inverse stage 0 (twiddle-free)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                ga.v[0][r] = cscale(ga.v[0][r], se[r]);
+                gb.v[0][r] = cscale(gb.v[0][r], so[r]);
+            }
+            dft<4, true>(ga.v[0]);
+            dft<4, true>(gb.v[0]);
+            line_sync<WS>();
+            stage_store<R, 4, 4>(ga, A, LGM, 0, lt, Gc);
+            stage_store<R, 4, 4>(gb, B, LGM, 0, lt, Gc);
+            line_sync<WS>();
         }
-        line_sync<WS>();
-        line_fft<R, true, RMAX, LGM, LT, WS>(A, B, true, lgm, lt, G, twl, lw);
+        fft_stages_ct<R, true, 4, LGM, 2, LT, WS>(A, B, true, lt, twl, lw);
+        (void)m;
+        (void)G;
     } else {
         for (int s = lt; s < m; s += G) B[s] = cmul(A[s], tw[s]);
         line_sync<WS>();
@@ -710,10 +817,14 @@ __device__ __forceinline__ void line_toeplitz(cplx<R>* A, cplx<R>* B, int lgm, i
 // ---------------------------------------------------------------------------
 // wavefront / workgroup reductions (fixed order: deterministic)
 // ---------------------------------------------------------------------------
+// Sum over the 64 lanes of a (full) wavefront, the same value in every lane:
+// pairs, quads, half rows and rows by DPP, then the four row totals.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v += dpp_mov<kDppQuadSwap1>(v);
+    v += dpp_mov<kDppQuadSwap2>(v);
+    v += dpp_mov<kDppHalfMirror>(v);
+    v += dpp_mov<kDppRowMirror>(v);
+    return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
 }
 
 }  // namespace fnls

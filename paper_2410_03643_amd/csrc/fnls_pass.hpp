@@ -20,6 +20,20 @@ template <> struct PassThreads<16> { static constexpr int v = 256; };
 // LGM > 0: the line length m = 2^LGM is a compile-time constant (the host
 // launches this specialisation only when a.lgm == LGM); 0: generic.
 // BJ: the launch may take its iteration index from the GMRES state (a.dev_j).
+// Preconditioner diagonal: v / (omega + i mu_k), mu_k = lo + tscale lambda_k
+// (lo: the other axes' share for this line) = v (omega - i mu_k) / den, with
+// one division per unknown.
+template <typename R>
+struct DivPost {
+    R om, lo, tscale;
+    const R* lam;
+    __device__ __forceinline__ cplx<R> operator()(int k, cplx<R> v) const {
+        const R mu = lo + tscale * lam[k];
+        const R rden = R(1) / (om * om + mu * mu);
+        return cm<R>((v.x * om + v.y * mu) * rden, (v.y * om - v.x * mu) * rden);
+    }
+};
+
 template <typename R, int RMAX, int LGM, int INM, int OPS, int ZM, int OUTM, int FIN, bool BJ = false>
 __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
     using C = cplx<R>;
@@ -173,6 +187,10 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
 
     // ---- load phase
     double wnrm = 0.0;   // IN_CGS: this thread's part of ||w||^2
+    // the accumulator of the other axes' Toeplitz products is loaded with the
+    // line data, so its loads are in flight during the transforms
+    constexpr bool kAccEarly = (OPS & OP_TOEP) != 0 && OUTM == OUT_ACC_NEXT;
+    C accq[kAccEarly ? kMaxEptLine : 1];
     {
         double sig = 1.0;
         if (INM == IN_BASIS) sig = a.st->sigma[basis_j];
@@ -181,6 +199,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
 #pragma unroll
         for (int q = 0; q < kMaxEptLine; ++q) {
             const int e = tid + q * T;
+            if constexpr (kAccEarly) accq[q] = czero<C>();
             if (e < E) {
                 int l, j;
                 emap(e, l, j);
@@ -188,6 +207,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
                 C v = czero<C>();
                 if (base >= 0) {
                     const long long gi = base + (long long)j * stride;
+                    if constexpr (kAccEarly) accq[q] = ld<R>(a.acc_in, gi);
                     if (INM == IN_PLAIN) {
                         v = ld<R>(in_p, gi);
                     } else if constexpr (kCgs) {
@@ -263,18 +283,14 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
 
     // ---- transform stages (line-local: with WS, G <= 64 threads per line,
     // each wavefront transforms its own lines without workgroup barriers)
-    if (OPS & OP_DST1) line_dst<R, RMAX, LGM, decltype(ltw), kWS>(A, B, lgm, lt, G, tw, twl, ltw);
-    if (OPS & OP_DIV) {
-        const R om = static_cast<R>(a.omega);
-        const R lo = s_lamo[line];
-        for (int k = lt + 1; k < m; k += G) {
-            const R mu = lo + tscale * lam[k];
-            const R den = om * om + mu * mu;
-            const C v = A[k];
-            // v / (om + i mu) = v (om - i mu) / den
-            A[k] = cm<R>((v.x * om + v.y * mu) / den, (v.y * om - v.x * mu) / den);
-        }
-        line_sync<kWS>();
+    if constexpr ((OPS & OP_DIV) != 0) {
+        // the division by (omega + i mu_k) is applied to the first transform's
+        // outputs before they are stored
+        static_assert((OPS & OP_DST1) && (OPS & OP_DST2), "division between two sine transforms");
+        const DivPost<R> div{static_cast<R>(a.omega), s_lamo[line], tscale, lam};
+        line_dst<R, RMAX, LGM, decltype(ltw), kWS>(A, B, lgm, lt, G, tw, twl, ltw, div);
+    } else if (OPS & OP_DST1) {
+        line_dst<R, RMAX, LGM, decltype(ltw), kWS>(A, B, lgm, lt, G, tw, twl, ltw);
     }
     if (OPS & OP_DST2) line_dst<R, RMAX, LGM, decltype(ltw), kWS>(A, B, lgm, lt, G, tw, twl, ltw);
     // the element phases read every line of the workgroup
@@ -360,13 +376,11 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
         constexpr bool kFirst = (OUTM == OUT_ACC_FIRST);
         constexpr bool kResid = (FIN == FIN_RESID);
         R dq[kFirst ? kMaxEptLine : 1];
-        C accq[kFirst ? 1 : kMaxEptLine];
         double2 bq[kResid ? kMaxEptLine : 1];
 #pragma unroll
         for (int q = 0; q < kMaxEptLine; ++q) {
             const int e = tid + q * T;
             if (kFirst) dq[q] = R(0);
-            else accq[q] = czero<C>();
             if (kResid) bq[q] = dmk(0.0, 0.0);
             if (e >= E) continue;
             int l, j;
@@ -375,7 +389,6 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
             if (base < 0) continue;
             const long long gi = base + (long long)j * stride;
             if (kFirst) dq[q] = Dv[gi];
-            else accq[q] = ld<R>(a.acc_in, gi);
             if (kResid) bq[q] = a.b64[gi];
         }
 #pragma unroll
@@ -398,7 +411,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
                 const C z = zreg[kKeepZ ? q : 0];
                 o = cm<R>(cD * z.x - ci * z.y + cT * tz.x, cD * z.y + ci * z.x + cT * tz.y);
             } else {
-                const C acc = accq[kFirst ? 0 : q];
+                const C acc = accq[kAccEarly ? q : 0];
                 o = cm<R>(acc.x + cT * tz.x, acc.y + cT * tz.y);
             }
             if (FIN == FIN_WRITE) {
