@@ -652,21 +652,68 @@ __device__ __forceinline__ void line_dst(cplx<R>* A, cplx<R>* B, int lgm, int lt
         }
     };
     if constexpr (kReg) {
-        // j = lt + i G with G = m / RMAX: W_{2m}^j = wl W_{2 RMAX}^i
-        constexpr int Gc = (1 << LGM) / RMAX;
+        // Compile-time radix-4 plan: the first FFT stage of thread lt reads
+        // slots s_r = lt + r G (G = m / 4).  The thread forms those four
+        // pre-processed values itself from x_s and x_{m-s} (the mirror slots
+        // m - s_r are the first-stage slots of thread G - lt), so the
+        // pre-processing needs no LDS round trip.  Slots s_0, s_1 < m/2 take
+        // a_j + s_j W^j (j = s_r, thread lt's own pairs, W_{2m}^j = wl W_8^r);
+        // s_2, s_3 > m/2 take -a_j - s_j conj(W^j) with j = m - s_r, the
+        // pairs of thread G - lt (W_{2m}^j = wl' W_8^{3-r}, wl' = W_{2m}^{G-lt}),
+        // computed with the same operations as that thread would.  Thread 0:
+        // s_0 = 0 is the Dirichlet zero, s_2 = m/2 is the middle value, and
+        // s_3 = m - G pairs with its own s_1.
+        constexpr int Gc = (1 << LGM) / 4;
+        static_assert(RMAX == 4, "register plan");
+        const int mt = (Gc - lt) & (Gc - 1);   // mirror thread (thread 0: itself)
+        C xs[4], xm[4];
 #pragma unroll
-        for (int i = 0; i <= RMAX / 2; ++i) {
-            const int j = lt + i * Gc;
-            if (j <= half) {
-                if constexpr (LT::kWl) pre(j, cmul(lw.wl, w2r<R, RMAX>(i)));
-                else pre(j, tw[j < half ? j : 0]);
-            }
+        for (int r = 0; r < 4; ++r) {
+            xs[r] = A[lt + r * Gc];
+            xm[r] = A[(m - lt - r * Gc) & (m - 1)];   // slot m - s_r (thread 0, r = 0: unused)
         }
+        C w[4];
+        if constexpr (LT::kWl) {
+            const C wm = tw[mt];
+            w[0] = cmul(lw.wl, w2r<R, 4>(0));
+            w[1] = cmul(lw.wl, w2r<R, 4>(1));
+            w[2] = cmul(wm, w2r<R, 4>(1));
+            w[3] = cmul(wm, w2r<R, 4>(0));
+        } else {
+            w[0] = tw[lt];
+            w[1] = tw[lt + Gc];
+            w[2] = tw[mt + Gc];
+            w[3] = tw[mt];
+        }
+        if (lt == 0) w[3] = w[1];
+        StageRegs<R, 4, 4> g;
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const C a = csub(xs[r], xm[r]);
+            const C sw = cadd(xs[r], xm[r]);
+            g.v[0][r] = cadd(a, cmul(sw, w[r]));
+        }
+#pragma unroll
+        for (int r = 2; r < 4; ++r) {
+            // x_j = xm[r], x_{m-j} = xs[r]
+            const C a = csub(xm[r], xs[r]);
+            const C sw = cadd(xm[r], xs[r]);
+            g.v[0][r] = csub(cneg(a), cmulc(sw, w[r]));
+        }
+        if (lt == 0) {
+            g.v[0][0] = czero<C>();
+            g.v[0][2] = cm<R>(R(2) * xs[2].y, R(-2) * xs[2].x);   // a = 0, b = -2 i x
+        }
+        dft<4, false>(g.v[0]);
+        line_sync<WS>();
+        stage_store<R, 4, 4>(g, A, LGM, 0, lt, Gc);
+        line_sync<WS>();
+        fft_stages_ct<R, false, 4, LGM, 2, LT, WS>(A, A, false, lt, twl, lw);
     } else {
         for (int j = lt; j <= half; j += G) pre(j, j < half ? tw[j] : czero<C>());
+        line_sync<WS>();
+        line_fft<R, false, RMAX, LGM, LT, WS>(A, A, false, lgm, lt, G, twl, lw);
     }
-    line_sync<WS>();
-    line_fft<R, false, RMAX, LGM, LT, WS>(A, A, false, lgm, lt, G, twl, lw);
     // p range of this thread: [lt E, lt E + E), E = half / G (G <= half unless m < 2 RMAX... E >= 1)
     constexpr int PER = RMAX / 2;
     const int E = half >= G ? half / G : 1;
