@@ -120,22 +120,24 @@ void tuned_put(int m, bool fp64, bool strided, int rmax, int lines) {
 // strided axes the lanes of a wavefront spread over L interleaved lines; the
 // element writes of one LDS write cycle (8 lanes of 16-byte values, 16 of
 // 8-byte ones, on a 128-byte bank row) stay apart when
-// ls * size = 128 / L modulo 256 / L bytes.  pa is the smallest length >= m
-// that gives that stride (m itself for a single line or when none does).
+// ls * size = 128 / L modulo 256 / L bytes.  ls is the smallest stride >= k m
+// (k buffers) that gives it (k m itself for a single line or when none
+// does); with two buffers B starts pa = m + (ls - 2 m) / 2 slots after A, so
+// an odd stride (16-byte values, 8 lines) leaves its spare slot after B.
 void line_layout(int m, int L, bool fp64, bool two, int* pa, int* ls) {
     const int elem = fp64 ? 16 : 8;
     const int k = two ? 2 : 1;
-    int best = m;
+    int extra = 0;
     if (L >= 2 && 128 / L >= elem) {
         const int target = 128 / L / elem, mod = 256 / L / elem;   // in slots
         for (int d = 0; d < mod; ++d)
-            if ((k * (m + d)) % mod == target) {
-                best = m + d;
+            if ((k * m + d) % mod == target) {
+                extra = d;
                 break;
             }
     }
-    *pa = best;
-    *ls = k * best;
+    *ls = k * m + extra;
+    *pa = two ? m + extra / 2 : *ls;
 }
 
 Geo pass_geo(int d, int n, int axis, bool fp64, size_t max_dyn_lds, const PassConfig& cfg) {

@@ -214,6 +214,45 @@ __device__ __forceinline__ int scan_rot() {
     return sizeof(R) == 8 ? ((lane >> 3) & 1) : ((lane >> 4) & 1);
 }
 
+// Radix-4 stages with Ns < 16 store output r of a butterfly at position
+// (r + s) mod 4 of its four slots, s = out_rot() (a cyclic lane rotation:
+// over each write cycle it covers the same slot positions as r ^ s, so the
+// strided stores stay free of bank conflicts).  Output register i holds
+// y_{(i + s) mod 4} when input q of the butterfly is multiplied by
+// W_4^{q s} (inverse: W_4^{-q s}) beforehand: y_{r+s} = sum_q W_4^{r q}
+// (W_4^{q s} x_q).  Those factors are powers of i, applied exactly by
+// swapping and negating parts (rot_inputs), or folded into the stage's
+// twiddle W^k -> W^k W_4^s, whose powers W^{q k} W_4^{q s} carry them; no
+// register permutation (selects on every value) is needed.
+template <typename R> __device__ __forceinline__ R xor_sign(R x, unsigned m);
+template <> __device__ __forceinline__ double xor_sign<double>(double x, unsigned m) {
+    const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(x)) ^
+                                 (static_cast<unsigned long long>(m) << 32);
+    return __longlong_as_double(static_cast<long long>(b));
+}
+template <> __device__ __forceinline__ float xor_sign<float>(float x, unsigned m) {
+    return __int_as_float(__float_as_int(x) ^ static_cast<int>(m));
+}
+// v i^e (e mod 4): (x, y), (-y, x), (-x, -y), (y, -x)
+template <typename R>
+__device__ __forceinline__ cplx<R> mul_ipow(cplx<R> v, int e) {
+    const bool odd = (e & 1) != 0;
+    const unsigned mre = ((e + 1) & 2) ? 0x80000000u : 0u;
+    const unsigned mim = (e & 2) ? 0x80000000u : 0u;
+    const R a = odd ? v.y : v.x;
+    const R b = odd ? v.x : v.y;
+    return cm<R>(xor_sign<R>(a, mre), xor_sign<R>(b, mim));
+}
+// inputs of a twiddle-free radix-4 butterfly times W_4^{q s} (forward,
+// W_4 = -i) or W_4^{-q s} (inverse)
+template <bool INV, typename C>
+__device__ __forceinline__ void rot_inputs(C* v, int s) {
+    using R = decltype(v[0].x);
+    v[1] = mul_ipow<R>(v[1], INV ? s : -s);
+    v[2] = mul_ipow<R>(v[2], 2 * s);
+    v[3] = mul_ipow<R>(v[3], INV ? -s : s);
+}
+
 // One Stockham (self-sorting, decimation in time) stage of radix RAD on one
 // line buffer X, computed in registers.  The caller places a barrier between
 // stage_load and stage_store (in-place update).  Ns = 2^lgNs is the product of
@@ -269,12 +308,12 @@ struct LineTw {
             if constexpr (kWl) wl = tw[lt];
         }
     }
-    // W_16^{lt mod 4}
+    // W_16^{lt mod 4} W_4^s (s = out_rot(): the stage's outputs rotate)
     __device__ __forceinline__ static cplx<R> stage1(int lt) {
         const int k = lt & 3;
         const R c = k == 0 ? R(1) : (k == 1 ? static_cast<R>(kc16(1)) : (k == 2 ? static_cast<R>(kc16(2)) : static_cast<R>(kc16(3))));
         const R sn = k == 0 ? R(0) : (k == 1 ? static_cast<R>(ks16(1)) : (k == 2 ? static_cast<R>(ks16(2)) : static_cast<R>(ks16(3))));
-        return cm<R>(c, -sn);
+        return mul_ipow<R>(cm<R>(c, -sn), -out_rot<R>());
     }
 };
 
@@ -294,6 +333,10 @@ __device__ __forceinline__ void stage_load(StageRegs<R, RAD, RMAX>& g, const cpl
     constexpr int PER = RMAX / RAD;
     const int nb = (1 << lgm) >> Lg<RAD>::v;
     const int tsh = lgm - lgNs - Lg<RAD>::v;   // W_{Ns RAD}^q = W_m^{q << tsh}
+    // radix-4 stages with Ns < 16 rotate their outputs (rot_inputs): a
+    // register twiddle comes rotated (LineTw::stage1), a table twiddle is
+    // rotated here, a twiddle-free stage rotates its inputs
+    const int srot = (RAD == 4 && lgNs < 4) ? out_rot<R>() : 0;
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
         const int b = lt + q * G;
@@ -301,14 +344,17 @@ __device__ __forceinline__ void stage_load(StageRegs<R, RAD, RMAX>& g, const cpl
 #pragma unroll
             for (int r = 0; r < RAD; ++r) g.v[q][r] = X[b + r * nb];
             const int k = b & ((1 << lgNs) - 1);
-            // with a register twiddle every lane multiplies (W^0 = 1 exactly)
-            if (WR ? lgNs > 0 : k != 0) {
+            // every lane of a stage with twiddles multiplies (W^0 = 1 is exact
+            // in the table and in the register twiddles), so no lane diverges
+            if (lgNs > 0) {
                 // one table read per butterfly; W^{r k} as products of W^k
                 // (depth <= 4 multiplications, a few ulps)
                 C w[RAD];
                 if constexpr (WR) w[1] = wr;
                 else w[1] = tw_quarter<R>(twl, k << tsh, lgm);
                 if (INV) w[1].y = -w[1].y;
+                if constexpr (RAD == 4 && !WR)
+                    if (lgNs < 4) w[1] = mul_ipow<R>(w[1], INV ? srot : -srot);
                 if constexpr (RAD >= 4) {
                     w[2] = cmul(w[1], w[1]);
                     w[3] = cmul(w[2], w[1]);
@@ -326,6 +372,8 @@ __device__ __forceinline__ void stage_load(StageRegs<R, RAD, RMAX>& g, const cpl
                 }
 #pragma unroll
                 for (int r = 1; r < RAD; ++r) g.v[q][r] = cmul(g.v[q][r], w[r]);
+            } else if constexpr (RAD == 4) {
+                rot_inputs<INV>(g.v[q], srot);
             }
             dft<RAD, INV>(g.v[q]);
         }
@@ -350,8 +398,10 @@ __device__ __forceinline__ void rot4(C a0, C a1, C a2, C a3, int rot, C& u0, C& 
     csel2(v1, v3, (rot & 2) != 0, u1, u3);
 }
 
-// Radix 2 and 4: store i of a thread writes output r = i ^ out_rot() (the
-// rotation is applied with selects, so the register indices stay static).
+// Radix 4: output register i (which holds y_{(i + s) mod 4}, see
+// rot_inputs) goes to slot position (i + s) mod 4.  Radix 2 and 8: store i of
+// a thread writes output r = i ^ rot (the rotation is applied with selects,
+// so the register indices stay static).
 template <typename R, int RAD, int RMAX>
 __device__ __forceinline__ void stage_store(const StageRegs<R, RAD, RMAX>& g, cplx<R>* X, int lgm, int lgNs, int lt,
                                             int G) {
@@ -370,12 +420,8 @@ __device__ __forceinline__ void stage_store(const StageRegs<R, RAD, RMAX>& g, cp
             const int k = b & (Ns - 1);
             const int base = ((b - k) << Lg<RAD>::v) + k;
             if constexpr (RAD == 4) {
-                C u0, u1, u2, u3;
-                rot4(g.v[q][0], g.v[q][1], g.v[q][2], g.v[q][3], rot, u0, u1, u2, u3);
-                X[base + (0 ^ rot) * Ns] = u0;
-                X[base + (1 ^ rot) * Ns] = u1;
-                X[base + (2 ^ rot) * Ns] = u2;
-                X[base + (3 ^ rot) * Ns] = u3;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) X[base + ((i + rot) & 3) * Ns] = g.v[q][i];
             } else if constexpr (RAD == 8) {
                 // u_i = v_{i ^ rot} by three rounds of conditional pair swaps
                 C u[8];
@@ -704,6 +750,7 @@ __device__ __forceinline__ void line_dst(cplx<R>* A, cplx<R>* B, int lgm, int lt
             g.v[0][0] = czero<C>();
             g.v[0][2] = cm<R>(R(2) * xs[2].y, R(-2) * xs[2].x);   // a = 0, b = -2 i x
         }
+        rot_inputs<false>(g.v[0], out_rot<R>());   // the stage's outputs rotate
         dft<4, false>(g.v[0]);
         line_sync<WS>();
         stage_store<R, 4, 4>(g, A, LGM, 0, lt, Gc);
@@ -807,11 +854,13 @@ __device__ __forceinline__ void line_toeplitz(cplx<R>* A, cplx<R>* B, int lgm, i
         {
             StageRegs<R, 4, 4> ga, gb;
 #pragma unroll
+            for (int r = 0; r < 4; ++r) ga.v[0][r] = A[lt + r * Gc];
+            // both buffers' first-stage outputs rotate (rot_inputs)
+            rot_inputs<false>(ga.v[0], out_rot<R>());
+#pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int s = lt + r * Gc;
-                ga.v[0][r] = A[s];
                 if constexpr (LT::kWl) gb.v[0][r] = cmul(ga.v[0][r], cmul(lw.wl, w2r<R, 4>(r)));
-                else gb.v[0][r] = cmul(ga.v[0][r], tw[s]);
+                else gb.v[0][r] = cmul(ga.v[0][r], tw[lt + r * Gc]);
             }
             dft<4, false>(ga.v[0]);
             dft<4, false>(gb.v[0]);
@@ -838,6 +887,8 @@ __device__ __forceinline__ void line_toeplitz(cplx<R>* A, cplx<R>* B, int lgm, i
                 ga.v[0][r] = cscale(ga.v[0][r], se[r]);
                 gb.v[0][r] = cscale(gb.v[0][r], so[r]);
             }
+            rot_inputs<true>(ga.v[0], out_rot<R>());
+            rot_inputs<true>(gb.v[0], out_rot<R>());
             dft<4, true>(ga.v[0]);
             dft<4, true>(gb.v[0]);
             line_sync<WS>();

@@ -32,17 +32,20 @@ PASS_CONFIGS = [DEFAULT_CFG,
 
 def line_layout(m, L, fp64, two):
     """Line buffer slots pa >= m and line stride ls (host rule): with L >= 2
-    interleaved lines, ls * size = 128 / L mod 256 / L bytes when reachable."""
+    interleaved lines, ls * size = 128 / L mod 256 / L bytes when reachable;
+    ls is the smallest such stride >= k m (k buffers), and with two buffers B
+    starts pa = m + (ls - 2 m) // 2 slots after A."""
     elem = 16 if fp64 else 8
     k = 2 if two else 1
-    best = m
+    extra = 0
     if L >= 2 and 128 // L >= elem:
         target, mod = 128 // L // elem, 256 // L // elem
         for dd in range(mod):
-            if (k * (m + dd)) % mod == target:
-                best = m + dd
+            if (k * m + dd) % mod == target:
+                extra = dd
                 break
-    return best, k * best
+    ls = k * m + extra
+    return (m + extra // 2 if two else ls), ls
 
 
 def par(x):
@@ -155,7 +158,7 @@ def test_pass_addresses(d, n, max_dyn, cfg):
             table = (m // 4 if m >= 4 else 1) * elem
             layouts = [line_layout(m, L, fp64, two) for two in (True, False)]
             for pa, ls in layouts:
-                assert pa >= m and ls in (pa, 2 * pa)
+                assert pa >= m and ls >= pa + (m if ls != pa else 0)
                 # what the launch allocates (reduction sums included) fits
                 lds = max(L * ls * elem + table + L * (8 + elem // 2), 66 * (T // 64) * 16, 4096)
                 assert L * ls * elem + table + L * (8 + elem // 2) <= g["lds"]
@@ -185,7 +188,7 @@ def test_pass_addresses(d, n, max_dyn, cfg):
                 for pa, LSb in layouts:
                     assert slots.max() < pa
                     assert (ls * LSb + slots).max() < L * LSb
-                    assert (ls * LSb + LSb - pa + slots).max() < L * LSb   # buffer B
+                    assert (ls * LSb + pa + slots).max() < L * LSb or pa == LSb   # buffer B
                 lg = blk * L + ls
                 valid = lg < g["nlines"]
                 o = lg // stride
@@ -354,7 +357,7 @@ def test_stream_kernels_and_partials(d, n):
 def test_lds_layout_is_conflict_free_at_m1024(fp64):
     """Under the gfx950 bank model, the LDS accesses of a radix-4 line of
     m = 1024 (G = 256 threads) are free of bank conflicts: stage loads,
-    lane-rotated stage stores, the last two stages' twiddle reads, the
+    lane-rotated stage stores (cyclic rotation (i + s) mod 4), the last two stages' twiddle reads, the
     sine-transform pre-pass pairs, rotated scan reads and output writes, the
     element phases of rows at any offset, and the element writes of 2 and 4
     interleaved strided lines at the host's line stride (whose reads cost at
@@ -371,7 +374,7 @@ def test_lds_layout_is_conflict_free_at_m1024(fp64):
                 st = []
                 for l, b in zip(range(64), lt):
                     k = b & (Ns - 1)
-                    st.append(((b - k) << 2) + k + (i ^ (out_rot(l, fp64) if Ns < 16 else 0)) * Ns)
+                    st.append(((b - k) << 2) + k + ((i + (out_rot(l, fp64) if Ns < 16 else 0)) & 3) * Ns)
                 bad.append(lds_extra_cycles(st, elem, "w"))
         for tsh in (0, 2):   # stages 4 and 3: q = k << tsh, table slot q ^ ((q >> 4 or 5) & 3)
             q = [(t & (255 >> tsh)) << tsh for t in lt]
@@ -401,3 +404,23 @@ def test_lds_layout_is_conflict_free_at_m1024(fp64):
         for kind in "rw":
             bad.append(lds_extra_cycles([start + l + 1 for l in range(64)], elem, kind))
     assert max(bad) == 0
+
+
+@pytest.mark.parametrize("fp64", [True, False])
+def test_interleaved_element_writes_are_conflict_free_at_m256(fp64):
+    """The element writes of 8 and 16 interleaved strided lines of m = 256
+    (the d = 3, n = 255 strided passes) are free of bank conflicts at the
+    host's line stride, for one and for two buffers per line (the two-buffer
+    stride may be odd, with the spare slot after buffer B)."""
+    elem = 16 if fp64 else 8
+    m = 256
+    for L in (8, 16):
+        if 128 // L < elem:
+            continue
+        lgL = L.bit_length() - 1
+        for two in (True, False):
+            pa, ls = line_layout(m, L, fp64, two)
+            assert pa >= m and (not two or ls >= pa + m)
+            for start in range(0, 64):
+                sl = [((start * 64 + l) & (L - 1)) * ls + ((start * 64 + l) >> lgL) + 1 for l in range(64)]
+                assert lds_extra_cycles(sl, elem, "w") == 0, (L, two, start)
