@@ -118,17 +118,6 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
     LineTw<R, RMAX, LGM, !((OPS & OP_TOEP) && OUTM == OUT_ACC_FIRST)> ltw;
     ltw.init(tw, lt);
 
-    // coalescing element map: e -> (line l, unknown j); rows are contiguous on
-    // the last axis, lines are interleaved on strided axes
-    auto emap = [&](int e, int& l, int& j) {
-        if (contiguous) {
-            l = (n == 1) ? e : (int)__umulhi((unsigned)e, a.magic_n);
-            j = e - l * n;
-        } else {
-            j = e >> lgL;
-            l = e & (L - 1);
-        }
-    };
 
     // IN_CGS: totals of the second-round dot products d_i (every workgroup,
     // in the same fixed order), h_i = sigma_i d_i and the update coefficients
@@ -185,81 +174,214 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
     for (int q = tid; q < nq; q += T) twl[tw_slot<R>(q)] = tw[2 * q];
     __syncthreads();
 
+    // Coalescing element map: element q < kMaxEptLine of this thread is
+    // e = tid + q T of the workgroup's L n unknowns.  Rows of the contiguous
+    // axis lie back to back (e = l n + j, global index blk L n + e); lines of
+    // strided axes are interleaved (e = j L + l), and since T is a multiple
+    // of L the thread keeps one line l = tid mod L while j advances by
+    // T / L = G per element.  Both give the global index and the LDS slot
+    // without a 64-bit multiply or an LDS read per element.  Each phase forms
+    // its context (the line's base offset, read from LDS) anew, so that no
+    // 64-bit index stays live in registers across the transforms.
+    struct Elem {
+        long long gi;   // global index (meaningful when valid)
+        int j;          // unknown along the line
+        int slot;       // LDS slot l LS + j + 1
+        bool in;        // e < L n
+        bool valid;     // in, and the line exists
+    };
+    struct ElemCtx {
+        int t;          // the thread index, opaque to the compiler (below)
+        long long gi0;  // strided: global index of element 0; contiguous: blk L n
+        bool ok;        // strided: the thread's line exists
+    };
+    auto elem_ctx = [&]() {
+        ElemCtx c;
+        // an opaque copy of the thread index per phase: the indices of one
+        // phase are not merged with the same expressions of an earlier phase,
+        // which would keep them live in registers across the transforms
+        c.t = tid;
+        asm volatile("" : "+v"(c.t));
+        if (contiguous) {
+            c.gi0 = (long long)blk * L * n;
+            c.ok = true;
+        } else {
+            const long long b = s_base[c.t & (L - 1)];
+            c.gi0 = b + (long long)(c.t >> lgL) * stride;
+            c.ok = b >= 0;
+        }
+        return c;
+    };
+    auto elem = [&](const ElemCtx& c, int q) {
+        Elem r;
+        const int e = c.t + q * T;
+        r.in = e < E;
+        if (contiguous) {
+            const int l = (n == 1) ? e : (int)__umulhi((unsigned)e, a.magic_n);
+            r.j = e - l * n;
+            r.slot = l * LS + r.j + 1;
+            r.gi = c.gi0 + e;
+            r.valid = r.in && r.gi < (long long)a.nlines * n;
+        } else {
+            r.j = (c.t >> lgL) + q * G;
+            r.slot = (c.t & (L - 1)) * LS + r.j + 1;
+            r.gi = c.gi0 + q * ((long long)G * stride);
+            r.valid = r.in && c.ok;
+        }
+        return r;
+    };
+
     // ---- load phase
     double wnrm = 0.0;   // IN_CGS: this thread's part of ||w||^2
     // the accumulator of the other axes' Toeplitz products is loaded with the
     // line data, so its loads are in flight during the transforms
     constexpr bool kAccEarly = (OPS & OP_TOEP) != 0 && OUTM == OUT_ACC_NEXT;
+    static_assert(!(kCgs && kAccEarly), "the fused Gram-Schmidt load phase reads no accumulator");
     C accq[kAccEarly ? kMaxEptLine : 1];
     {
         double sig = 1.0;
         if (INM == IN_BASIS) sig = a.st->sigma[basis_j];
         int nvc = 0;
         if (INM == IN_COMBO) nvc = a.st->k;
+        const ElemCtx ec = elem_ctx();
+        if constexpr (INM == IN_PLAIN || INM == IN_BASIS) {
+            // every global load of the phase is in flight before the first
+            // LDS write (a write waits for its value, and would otherwise hold
+            // back the next element's loads: one memory round trip each)
+            C vin[kMaxEptLine];
 #pragma unroll
-        for (int q = 0; q < kMaxEptLine; ++q) {
-            const int e = tid + q * T;
-            if constexpr (kAccEarly) accq[q] = czero<C>();
-            if (e < E) {
-                int l, j;
-                emap(e, l, j);
-                const long long base = s_base[l];
-                C v = czero<C>();
-                if (base >= 0) {
-                    const long long gi = base + (long long)j * stride;
-                    if constexpr (kAccEarly) accq[q] = ld<R>(a.acc_in, gi);
-                    if (INM == IN_PLAIN) {
-                        v = ld<R>(in_p, gi);
-                    } else if constexpr (kCgs) {
-                        // w -= sum_i c_i v_i as explicit fused multiply-adds in
-                        // the order of the streaming update (same rounding)
-                        const C wv = ld<R>(in_p, gi);
-                        double wx = wv.x, wy = wv.y;
-                        const double2* s_coef = s_cgs + (kMaxRestart + 2);
-                        for (int i = 0; i <= basis_j; ++i) {
-                            const C t = (i == 0) ? ld<R>(a.v0, gi) : ld<R>(a.vbase, (long long)(i - 1) * a.N + gi);
-                            cmsub(wx, wy, s_coef[i], t.x, t.y);
-                        }
-                        v = cm<R>(static_cast<R>(wx), static_cast<R>(wy));
-                        stc<R>(const_cast<void*>(in_p), gi, v);
+            for (int q = 0; q < kMaxEptLine; ++q) {
+                const Elem el = elem(ec, q);
+                vin[q] = czero<C>();
+                if constexpr (kAccEarly) accq[q] = czero<C>();
+                if (el.valid) {
+                    if constexpr (kAccEarly) accq[q] = ld<R>(a.acc_in, el.gi);
+                    vin[q] = ld<R>(in_p, el.gi);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < kMaxEptLine; ++q) {
+                const Elem el = elem(ec, q);
+                if (el.in) {
+                    C v = vin[q];
+                    if (INM == IN_BASIS && el.valid) v = cm<R>(static_cast<R>(v.x * sig), static_cast<R>(v.y * sig));
+                    lds[el.slot] = v;
+                }
+            }
+        } else if constexpr (kCgs && sizeof(R) == 8) {
+            // w -= sum_i c_i v_i as explicit fused multiply-adds in the order
+            // of the streaming update (same rounding).  The basis vectors are
+            // the outer loop, so each of them is read for all of the thread's
+            // elements at once, and the next one is in flight while the
+            // current one is applied (measured faster for FP64 only; complex64
+            // bases take the per-element loop below).
+            const double2* s_coef = s_cgs + (kMaxRestart + 2);
+            long long gq[kMaxEptLine];
+            double wx[kMaxEptLine], wy[kMaxEptLine];
+#pragma unroll
+            for (int q = 0; q < kMaxEptLine; ++q) {
+                const Elem el = elem(ec, q);
+                gq[q] = el.valid ? el.gi : -1;
+                wx[q] = 0.0;
+                wy[q] = 0.0;
+                if (el.valid) {
+                    const C wv = ld<R>(in_p, el.gi);
+                    wx[q] = wv.x;
+                    wy[q] = wv.y;
+                }
+            }
+            auto load_vec = [&](int i, C* t) {
+                const C* src = (i == 0) ? reinterpret_cast<const C*>(a.v0)
+                                        : reinterpret_cast<const C*>(a.vbase) + (long long)(i - 1) * a.N;
+#pragma unroll
+                for (int q = 0; q < kMaxEptLine; ++q) t[q] = gq[q] >= 0 ? src[gq[q]] : czero<C>();
+            };
+            auto apply_vec = [&](int i, const C* t) {
+                const double2 c = s_coef[i];
+#pragma unroll
+                for (int q = 0; q < kMaxEptLine; ++q) cmsub(wx[q], wy[q], c, t[q].x, t[q].y);
+            };
+            C ta[kMaxEptLine], tb[kMaxEptLine];
+            load_vec(0, ta);
+            for (int i = 0; i <= basis_j; i += 2) {
+                if (i + 1 <= basis_j) load_vec(i + 1, tb);
+                apply_vec(i, ta);
+                if (i + 1 <= basis_j) {
+                    if (i + 2 <= basis_j) load_vec(i + 2, ta);
+                    apply_vec(i + 1, tb);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < kMaxEptLine; ++q) {
+                const Elem el = elem(ec, q);
+                if (el.in) {
+                    C v = czero<C>();
+                    if (el.valid) {
+                        v = cm<R>(static_cast<R>(wx[q]), static_cast<R>(wy[q]));
+                        stc<R>(const_cast<void*>(in_p), el.gi, v);
                         wnrm = fma((double)v.x, (double)v.x, wnrm);
                         wnrm = fma((double)v.y, (double)v.y, wnrm);
-                    } else if (INM == IN_BASIS) {
-                        const C t = ld<R>(in_p, gi);
-                        v = cm<R>(static_cast<R>(t.x * sig), static_cast<R>(t.y * sig));
-                    } else if (a.zsum) {
-                        // sum_k y_k z_k over the stored preconditioned basis
-                        // (complex64 when z32), accumulated in FP64
-                        double sx = 0.0, sy = 0.0;
-                        for (int i = 0; i < nvc; ++i) {
-                            const long long zi = (long long)i * a.N + gi;
-                            double tx, ty;
-                            if (a.z32) {
-                                const float2 t = reinterpret_cast<const float2*>(a.vbase)[zi];
-                                tx = t.x;
-                                ty = t.y;
-                            } else {
-                                const double2 t = reinterpret_cast<const double2*>(a.vbase)[zi];
-                                tx = t.x;
-                                ty = t.y;
-                            }
-                            const double2 c = a.st->y[i];
-                            sx += c.x * tx - c.y * ty;
-                            sy += c.x * ty + c.y * tx;
-                        }
-                        v = cm<R>(static_cast<R>(sx), static_cast<R>(sy));
-                    } else {
-                        double sx = 0.0, sy = 0.0;
-                        for (int i = 0; i < nvc; ++i) {
-                            const C t = (i == 0) ? ld<R>(a.v0, gi) : ld<R>(a.vbase, (long long)(i - 1) * a.N + gi);
-                            const double2 c = a.st->coef[i];
-                            sx += c.x * t.x - c.y * t.y;
-                            sy += c.x * t.y + c.y * t.x;
-                        }
-                        v = cm<R>(static_cast<R>(sx), static_cast<R>(sy));
                     }
+                    lds[el.slot] = v;
                 }
-                lds[(size_t)l * LS + j + 1] = v;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < kMaxEptLine; ++q) {
+                const Elem el = elem(ec, q);
+                if constexpr (kAccEarly) accq[q] = czero<C>();
+                if (el.in) {
+                    C v = czero<C>();
+                    if (el.valid) {
+                        const long long gi = el.gi;
+                        if constexpr (kAccEarly) accq[q] = ld<R>(a.acc_in, gi);
+                        if constexpr (kCgs) {
+                            // the same update and rounding, one element at a time
+                            const C wv = ld<R>(in_p, gi);
+                            double wx = wv.x, wy = wv.y;
+                            const double2* s_coef = s_cgs + (kMaxRestart + 2);
+                            for (int i = 0; i <= basis_j; ++i) {
+                                const C t = (i == 0) ? ld<R>(a.v0, gi) : ld<R>(a.vbase, (long long)(i - 1) * a.N + gi);
+                                cmsub(wx, wy, s_coef[i], t.x, t.y);
+                            }
+                            v = cm<R>(static_cast<R>(wx), static_cast<R>(wy));
+                            stc<R>(const_cast<void*>(in_p), gi, v);
+                            wnrm = fma((double)v.x, (double)v.x, wnrm);
+                            wnrm = fma((double)v.y, (double)v.y, wnrm);
+                        } else if (a.zsum) {
+                            // sum_k y_k z_k over the stored preconditioned basis
+                            // (complex64 when z32), accumulated in FP64
+                            double sx = 0.0, sy = 0.0;
+                            for (int i = 0; i < nvc; ++i) {
+                                const long long zi = (long long)i * a.N + gi;
+                                double tx, ty;
+                                if (a.z32) {
+                                    const float2 t = reinterpret_cast<const float2*>(a.vbase)[zi];
+                                    tx = t.x;
+                                    ty = t.y;
+                                } else {
+                                    const double2 t = reinterpret_cast<const double2*>(a.vbase)[zi];
+                                    tx = t.x;
+                                    ty = t.y;
+                                }
+                                const double2 c = a.st->y[i];
+                                sx += c.x * tx - c.y * ty;
+                                sy += c.x * ty + c.y * tx;
+                            }
+                            v = cm<R>(static_cast<R>(sx), static_cast<R>(sy));
+                        } else {
+                            double sx = 0.0, sy = 0.0;
+                            for (int i = 0; i < nvc; ++i) {
+                                const C t = (i == 0) ? ld<R>(a.v0, gi) : ld<R>(a.vbase, (long long)(i - 1) * a.N + gi);
+                                const double2 c = a.st->coef[i];
+                                sx += c.x * t.x - c.y * t.y;
+                                sy += c.x * t.y + c.y * t.x;
+                            }
+                            v = cm<R>(static_cast<R>(sx), static_cast<R>(sy));
+                        }
+                    }
+                    lds[el.slot] = v;
+                }
             }
         }
     }
@@ -306,6 +428,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
     // ---- element phase 1: preconditioner scale, z / x outputs, Toeplitz operand
     if (kPhase1) {
         const double om = a.omega;
+        const ElemCtx ec = elem_ctx();
         // every global operand of this phase is loaded before the first
         // global store (a store could alias a later load, which would
         // serialise one memory round trip per element)
@@ -315,28 +438,20 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
         double2 xpre[kNeedX ? kMaxEptLine : 1];
 #pragma unroll
         for (int q = 0; q < kMaxEptLine; ++q) {
-            const int e = tid + q * T;
+            const Elem el = elem(ec, q);
             if (kNeedD) dpre[q] = R(0);
             if (kNeedX) xpre[q] = dmk(0.0, 0.0);
-            if (e >= E) continue;
-            int l, j;
-            emap(e, l, j);
-            const long long base = s_base[l];
-            if (base < 0) continue;
-            const long long gi = base + (long long)j * stride;
-            if (kNeedD) dpre[q] = Dv[gi];
-            if (kNeedX && !a.first_cycle) xpre[q] = a.x64[gi];
+            if (!el.valid) continue;
+            if (kNeedD) dpre[q] = Dv[el.gi];
+            if (kNeedX && !a.first_cycle) xpre[q] = a.x64[el.gi];
         }
 #pragma unroll
         for (int q = 0; q < kMaxEptLine; ++q) {
-            const int e = tid + q * T;
-            if (e >= E) continue;
-            int l, j;
-            emap(e, l, j);
-            const long long base = s_base[l];
-            C z = lds[(size_t)l * LS + j + 1];
-            if (base >= 0) {
-                const long long gi = base + (long long)j * stride;
+            const Elem el = elem(ec, q);
+            if (!el.in) continue;
+            C z = lds[el.slot];
+            if (el.valid) {
+                const long long gi = el.gi;
                 if (OPS & OP_SCALE) {
                     const R Dj = dpre[kNeedD ? q : 0];
                     // -2 i om / ((om+1) - i D) = (2 om D - 2 i om (om+1)) / ((om+1)^2 + D^2)
@@ -360,7 +475,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
                 if (!kToep && FIN == FIN_WRITE && out_p) stc<R>(out_p, gi, z);
             }
             if (kKeepZ) zreg[q] = z;
-            if (kToep) lds[(size_t)l * LS + j + 1] = z;
+            if (kToep) lds[el.slot] = z;
         }
         if (kToep) __syncthreads();
     }
@@ -372,6 +487,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
                                                          reinterpret_cast<const R*>(a.sym_o), tscale, ltw);
         if constexpr (kWS) __syncthreads();   // element phase 2 reads every line
         const R cT = static_cast<R>(a.cT);
+        const ElemCtx ec = elem_ctx();
         // operands first (see element phase 1)
         constexpr bool kFirst = (OUTM == OUT_ACC_FIRST);
         constexpr bool kResid = (FIN == FIN_RESID);
@@ -379,31 +495,21 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
         double2 bq[kResid ? kMaxEptLine : 1];
 #pragma unroll
         for (int q = 0; q < kMaxEptLine; ++q) {
-            const int e = tid + q * T;
+            const Elem el = elem(ec, q);
             if (kFirst) dq[q] = R(0);
             if (kResid) bq[q] = dmk(0.0, 0.0);
-            if (e >= E) continue;
-            int l, j;
-            emap(e, l, j);
-            const long long base = s_base[l];
-            if (base < 0) continue;
-            const long long gi = base + (long long)j * stride;
-            if (kFirst) dq[q] = Dv[gi];
-            if (kResid) bq[q] = a.b64[gi];
+            if (!el.valid) continue;
+            if (kFirst) dq[q] = Dv[el.gi];
+            if (kResid) bq[q] = a.b64[el.gi];
         }
 #pragma unroll
         for (int q = 0; q < kMaxEptLine; ++q) {
-            const int e = tid + q * T;
+            const Elem el = elem(ec, q);
             if (FIN == FIN_WDOTS) oreg[q] = czero<C>();
-            if (e >= E) continue;
-            int l, j;
-            emap(e, l, j);
-            const long long base = s_base[l];
-            if (base < 0) continue;
-            const long long gi = base + (long long)j * stride;
-            const int s = j + 1;
-            const C* Al = lds + (size_t)l * LS;
-            const C tz = cadd(Al[s], cmulc(Al[PA + s], tw[s]));
+            if (!el.valid) continue;
+            const long long gi = el.gi;
+            const int s = el.j + 1;
+            const C tz = cadd(lds[el.slot], cmulc(lds[el.slot + PA], tw[s]));
             C o;
             if (OUTM == OUT_ACC_FIRST) {
                 const R Dj = dq[kFirst ? q : 0];
@@ -445,15 +551,11 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
         // global index of each element (-1: none) and double-buffered basis
         // loads: vector i + 1 is in flight while vector i is reduced
         long long gq[kMaxEptLine];
+        const ElemCtx ec = elem_ctx();
 #pragma unroll
         for (int q = 0; q < kMaxEptLine; ++q) {
-            const int e = tid + q * T;
-            gq[q] = -1;
-            if (e >= E) continue;
-            int l, j;
-            emap(e, l, j);
-            const long long base = s_base[l];
-            if (base >= 0) gq[q] = base + (long long)j * stride;
+            const Elem el = elem(ec, q);
+            gq[q] = el.valid ? el.gi : -1;
         }
         auto load_vec = [&](int i, C* v) {
             const C* src = (i == 0) ? reinterpret_cast<const C*>(a.v0)
