@@ -7,6 +7,10 @@ plus 1e-3 complex noise (seed 0); right-preconditioned GMRES(30) with the
 sine-transform TBAN preconditioner (omega = 1), tolerance 1e-10.
 --workload d3: the d = 3, n = 255 system on [-8, 8]^3 (16,581,375 unknowns),
 alpha = 1.6, rho = 1, dt = 0.01 (profiling of the HBM-resident case).
+--workload batch64: 64 independent d = 2 instances (n drawn from 127, 255,
+511, 1023; alpha, rho, soliton centre and phase drawn with seed 0), one
+FP32-IR time step of all of them per step through the batched solver, with
+direct launches and with hipGraph replays (profiling of the batched path).
 
 One step = one time-step solve of the whole hot path through the C ABI:
 preconditioner setup D = rho dt |u|^2, right-hand side b = (iI + T - D) u, and
@@ -245,13 +249,74 @@ def cpu_baseline(p, seconds, x64, x32):
     return base, errs
 
 
+def batch_bench(args, torch, dev):
+    """64 batched d = 2 instances, one FP32-IR time step of all per step:
+    direct launches and hipGraph replays timed alike.  The whole-step
+    roofline charges each instance the minimal-traffic bytes of its own
+    step (the single-instance timing records of the same step, whose
+    iteration counts the batch matches within one)."""
+    from paper_2410_03643_amd import inputs
+    from paper_2410_03643_amd.fnls import Batch, Solver
+    cases = inputs.batched_cases(64)
+    sizes = sorted(set(p.n for p in cases))
+    counts = {n: sum(p.n == n for p in cases) for n in sizes}
+    log("batch64: n counts %s, %d unknowns" % (counts, sum(p.N for p in cases)))
+    solvers = [Solver(p.alpha, p.rho, p.d, p.n, p.h, p.tau, device=dev) for p in cases]
+    us = [torch.from_numpy(p.u).to(dev) for p in cases]
+    outs = [torch.empty_like(u) for u in us]
+    batch = Batch(solvers)
+    times, infos = {}, None
+    for mode in ("direct", "graph"):
+        g = mode == "graph"
+        for _ in range(args.warmup):
+            batch.step(us, us, outs, tol=TOL, precision="fp32_ir", graph=g)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            _, infos = batch.step(us, us, outs, tol=TOL, precision="fp32_ir", graph=g)
+        torch.cuda.synchronize()
+        times[mode] = (time.perf_counter() - t0) / args.steps
+        assert all(i.status == 0 and i.relres_true < TOL for i in infos), "a batched solve missed the tolerance"
+        log("batch64 %s: %.3f ms per step of all 64" % (mode, 1e3 * times[mode]))
+    # minimal-traffic bytes of each instance's step, from its own timed step
+    alg, single_its = 0.0, []
+    for s, u, o in zip(solvers, us, outs):
+        s.timing(True)
+        _, si = s.step(u, u, out=o, tol=TOL, precision="fp32_ir")
+        rep = s.timing_report()
+        s.timing(False)
+        alg += sum(r["bytes_min"] for r in rep)
+        single_its.append(si.iters)
+    batch.close()
+    its = [i.iters for i in infos]
+    assert all(abs(a - b) <= 1 for a, b in zip(its, single_its))
+    t = times["direct"]
+    gbs = alg / t / 1e9
+    out = {
+        "metric": "batched PGMRES instance-steps/s: 64 d=2 instances, n in {127,255,511,1023}, FP32-IR @1e-10",
+        "value": round(64 / t, 1), "unit": "instance-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * t, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "batch64: 64 independent d=2 instances on [-10,10]^2, dt=0.01, n counts %s, "
+                               "alpha ~ U[1.1,1.9], rho ~ U[0.5,3], soliton with random centre and phase "
+                               "(seed 0); one FP32-IR time step of all per step" % counts,
+                   "instances": 64, "unknowns": sum(p.N for p in cases), "tol": TOL},
+        "iters_min": min(its), "iters_max": max(its),
+        "graph": {"value": round(64 / times["graph"], 1), "ms_per_step": round(1e3 * times["graph"], 4)},
+        "step_roofline": {"alg_bytes": int(alg), "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
+                          "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4)},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", choices=["metric", "d3"], default="metric",
-                    help="metric: d=2 n=1023 (the headline); d3: d=3 n=255 (profiling)")
+    ap.add_argument("--workload", choices=["metric", "d3", "batch64"], default="metric",
+                    help="metric: d=2 n=1023 (the headline); d3: d=3 n=255; batch64: 64 batched d=2 "
+                         "instances (both for profiling)")
     ap.add_argument("--precision", choices=["fp64", "fp32_ir"], default="fp64",
                     help="precision of the headline value (both are measured)")
     ap.add_argument("--profile-steps", type=int, default=20)
@@ -280,6 +345,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda", 0)
+    if args.workload == "batch64":
+        batch_bench(args, torch, dev)
+        return
     if args.copy_calibration:
         src = torch.ones(COPY_BYTES, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)

@@ -268,13 +268,9 @@ template <typename R>
 __device__ __forceinline__ cplx<R> tw_quarter(const cplx<R>* twl, int q, int lgm) {
     const int t = q >> (lgm - 2);
     const cplx<R> w = twl[tw_slot<R>(q & ((1 << (lgm - 2)) - 1))];
-    // (-i)^t w without divergent branches: odd t swaps (x, y) -> (y, -x),
-    // t >= 2 negates
-    const bool odd = t & 1;
-    const R sg = (t & 2) ? R(-1) : R(1);
-    const R x = odd ? w.y : w.x;
-    const R y = odd ? -w.x : w.y;
-    return cm<R>(sg * x, sg * y);
+    // (-i)^t w = i^{-t} w without divergent branches (part swap and sign
+    // flips)
+    return mul_ipow<R>(w, -t);
 }
 
 template <int RAD> struct Lg;
@@ -324,18 +320,66 @@ __device__ __forceinline__ cplx<R> w2r(int i) {
     return cm<R>(static_cast<R>(kc16(j)), static_cast<R>(-ks16(j)));
 }
 
-// WR: wr is this thread's twiddle W_{Ns RAD}^k of the stage (LineTw);
-// otherwise it is read from the LDS quarter table.
+// Twiddles W^{r k} of this thread's butterflies in one stage; they are the
+// same for every buffer of a line, so a stage over buffers A and B forms them
+// once.  WR: wr is this thread's twiddle W_{Ns RAD}^k of the stage (LineTw);
+// otherwise it is read from the LDS quarter table.  Radix-4 stages with
+// Ns < 16 rotate their outputs (rot_inputs): a register twiddle comes
+// rotated (LineTw::stage1), a table twiddle is rotated here, and a
+// twiddle-free stage rotates its inputs in stage_load_tw.
+template <typename R, int RAD, int RMAX>
+struct StageTw {
+    cplx<R> w[RMAX / RAD][RAD];
+};
 template <typename R, int RAD, int RMAX, bool INV, bool WR = false>
-__device__ __forceinline__ void stage_load(StageRegs<R, RAD, RMAX>& g, const cplx<R>* X, int lgm, int lgNs, int lt,
-                                           int G, const cplx<R>* twl, cplx<R> wr = cplx<R>{}) {
+__device__ __forceinline__ void stage_tw(StageTw<R, RAD, RMAX>& t, int lgm, int lgNs, int lt, int G,
+                                         const cplx<R>* twl, cplx<R> wr = cplx<R>{}) {
     using C = cplx<R>;
     constexpr int PER = RMAX / RAD;
     const int nb = (1 << lgm) >> Lg<RAD>::v;
     const int tsh = lgm - lgNs - Lg<RAD>::v;   // W_{Ns RAD}^q = W_m^{q << tsh}
-    // radix-4 stages with Ns < 16 rotate their outputs (rot_inputs): a
-    // register twiddle comes rotated (LineTw::stage1), a table twiddle is
-    // rotated here, a twiddle-free stage rotates its inputs
+    const int srot = (RAD == 4 && lgNs < 4) ? out_rot<R>() : 0;
+    // every lane of a stage with twiddles multiplies (W^0 = 1 is exact in
+    // the table and in the register twiddles), so no lane diverges
+    if (lgNs == 0) return;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int b = lt + q * G;
+        if (b < nb) {
+            const int k = b & ((1 << lgNs) - 1);
+            // one table read per butterfly; W^{r k} as products of W^k
+            // (depth <= 4 multiplications, a few ulps)
+            C* w = t.w[q];
+            if constexpr (WR) w[1] = wr;
+            else w[1] = tw_quarter<R>(twl, k << tsh, lgm);
+            if (INV) w[1].y = -w[1].y;
+            if constexpr (RAD == 4 && !WR)
+                if (lgNs < 4) w[1] = mul_ipow<R>(w[1], INV ? srot : -srot);
+            if constexpr (RAD >= 4) {
+                w[2] = cmul(w[1], w[1]);
+                w[3] = cmul(w[2], w[1]);
+            }
+            if constexpr (RAD >= 8) {
+                w[4] = cmul(w[2], w[2]);
+                w[5] = cmul(w[4], w[1]);
+                w[6] = cmul(w[4], w[2]);
+                w[7] = cmul(w[4], w[3]);
+            }
+            if constexpr (RAD >= 16) {
+                w[8] = cmul(w[4], w[4]);
+#pragma unroll
+                for (int r = 9; r < 16; ++r) w[r] = cmul(w[8], w[r - 8]);
+            }
+        }
+    }
+}
+// One Stockham stage's loads of buffer X, twiddles t (stage_tw) and
+// butterflies, in registers.
+template <typename R, int RAD, int RMAX, bool INV>
+__device__ __forceinline__ void stage_load_tw(StageRegs<R, RAD, RMAX>& g, const cplx<R>* X, int lgm, int lgNs,
+                                              int lt, int G, const StageTw<R, RAD, RMAX>& t) {
+    constexpr int PER = RMAX / RAD;
+    const int nb = (1 << lgm) >> Lg<RAD>::v;
     const int srot = (RAD == 4 && lgNs < 4) ? out_rot<R>() : 0;
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
@@ -343,41 +387,22 @@ __device__ __forceinline__ void stage_load(StageRegs<R, RAD, RMAX>& g, const cpl
         if (b < nb) {
 #pragma unroll
             for (int r = 0; r < RAD; ++r) g.v[q][r] = X[b + r * nb];
-            const int k = b & ((1 << lgNs) - 1);
-            // every lane of a stage with twiddles multiplies (W^0 = 1 is exact
-            // in the table and in the register twiddles), so no lane diverges
             if (lgNs > 0) {
-                // one table read per butterfly; W^{r k} as products of W^k
-                // (depth <= 4 multiplications, a few ulps)
-                C w[RAD];
-                if constexpr (WR) w[1] = wr;
-                else w[1] = tw_quarter<R>(twl, k << tsh, lgm);
-                if (INV) w[1].y = -w[1].y;
-                if constexpr (RAD == 4 && !WR)
-                    if (lgNs < 4) w[1] = mul_ipow<R>(w[1], INV ? srot : -srot);
-                if constexpr (RAD >= 4) {
-                    w[2] = cmul(w[1], w[1]);
-                    w[3] = cmul(w[2], w[1]);
-                }
-                if constexpr (RAD >= 8) {
-                    w[4] = cmul(w[2], w[2]);
-                    w[5] = cmul(w[4], w[1]);
-                    w[6] = cmul(w[4], w[2]);
-                    w[7] = cmul(w[4], w[3]);
-                }
-                if constexpr (RAD >= 16) {
-                    w[8] = cmul(w[4], w[4]);
 #pragma unroll
-                    for (int r = 9; r < 16; ++r) w[r] = cmul(w[8], w[r - 8]);
-                }
-#pragma unroll
-                for (int r = 1; r < RAD; ++r) g.v[q][r] = cmul(g.v[q][r], w[r]);
+                for (int r = 1; r < RAD; ++r) g.v[q][r] = cmul(g.v[q][r], t.w[q][r]);
             } else if constexpr (RAD == 4) {
                 rot_inputs<INV>(g.v[q], srot);
             }
             dft<RAD, INV>(g.v[q]);
         }
     }
+}
+template <typename R, int RAD, int RMAX, bool INV, bool WR = false>
+__device__ __forceinline__ void stage_load(StageRegs<R, RAD, RMAX>& g, const cplx<R>* X, int lgm, int lgNs, int lt,
+                                           int G, const cplx<R>* twl, cplx<R> wr = cplx<R>{}) {
+    StageTw<R, RAD, RMAX> t;
+    stage_tw<R, RAD, RMAX, INV, WR>(t, lgm, lgNs, lt, G, twl, wr);
+    stage_load_tw<R, RAD, RMAX, INV>(g, X, lgm, lgNs, lt, G, t);
 }
 
 // (u0, u1) = sw ? (a1, a0) : (a0, a1), component-wise selects on values
@@ -483,8 +508,10 @@ __device__ __forceinline__ void stockham_stage(cplx<R>* A, cplx<R>* B, bool both
                                                int G, const cplx<R>* twl, cplx<R> wr = cplx<R>{}) {
     if constexpr (RMAX <= 8) {
         StageRegs<R, RAD, RMAX> ga, gb;
-        stage_load<R, RAD, RMAX, INV, WR>(ga, A, lgm, lgNs, lt, G, twl, wr);
-        if (both) stage_load<R, RAD, RMAX, INV, WR>(gb, B, lgm, lgNs, lt, G, twl, wr);
+        StageTw<R, RAD, RMAX> t;   // one set of twiddles for both buffers
+        stage_tw<R, RAD, RMAX, INV, WR>(t, lgm, lgNs, lt, G, twl, wr);
+        stage_load_tw<R, RAD, RMAX, INV>(ga, A, lgm, lgNs, lt, G, t);
+        if (both) stage_load_tw<R, RAD, RMAX, INV>(gb, B, lgm, lgNs, lt, G, t);
         line_sync<WS>();
         stage_store<R, RAD, RMAX>(ga, A, lgm, lgNs, lt, G);
         if (both) stage_store<R, RAD, RMAX>(gb, B, lgm, lgNs, lt, G);
@@ -879,8 +906,10 @@ __device__ __forceinline__ void line_toeplitz(cplx<R>* A, cplx<R>* B, int lgm, i
                 se[r] = sym_e[lt + r * Gc] * tscale;
                 so[r] = sym_o[lt + r * Gc] * tscale;
             }
-            stage_load<R, 4, 4, false>(ga, A, LGM, LGM - 2, lt, Gc, twl);
-            stage_load<R, 4, 4, false>(gb, B, LGM, LGM - 2, lt, Gc, twl);
+            StageTw<R, 4, 4> t;
+            stage_tw<R, 4, 4, false>(t, LGM, LGM - 2, lt, Gc, twl);
+            stage_load_tw<R, 4, 4, false>(ga, A, LGM, LGM - 2, lt, Gc, t);
+            stage_load_tw<R, 4, 4, false>(gb, B, LGM, LGM - 2, lt, Gc, t);
             // output r belongs to slot lt + r G; inverse stage 0 (twiddle-free)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
