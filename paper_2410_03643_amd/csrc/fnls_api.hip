@@ -2021,12 +2021,21 @@ Geo batch_geo(int d, int n, int axis, bool fp64, const fnls_batch* B = nullptr) 
     int rmax = 4, lines = 0;
     bool tuned = false;
     if (B && batch_lgm_class(lgm) != 0) {
+        // a class with a compile-time plan has one line length, so its launch
+        // takes that length's own schedule: the one fnls_batch_autotune chose,
+        // else the single-instance default (smaller workgroups than the
+        // shared 1024-thread shape, so that several share a CU and overlap
+        // their load, transform and store phases)
         auto it = B->sched.find((long long)m * 4 + (fp64 ? 2 : 0) + (axis != d - 1 ? 1 : 0));
         if (it != B->sched.end()) {
             rmax = it->second.first;
             lines = it->second.second;
-            tuned = (rmax == 4 || rmax == 8);
+        } else {
+            const PassConfig cfg = default_pass_config(m);
+            rmax = cfg.rmax[fp64 ? 1 : 0][axis != d - 1 ? 1 : 0];
+            lines = cfg.lines[fp64 ? 1 : 0][axis != d - 1 ? 1 : 0];
         }
+        tuned = (rmax == 4 || rmax == 8);
     }
     if (tuned) {
         g.rmax = rmax;
