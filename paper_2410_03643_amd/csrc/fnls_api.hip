@@ -1971,6 +1971,13 @@ struct fnls_batch {
     GraphSlot gs[kGraphSlots];
     unsigned long long tick = 0;
     long long captures = 0, replays = 0;
+    // side streams of an Arnoldi iteration: the pass launches of the line-length
+    // classes other than the first run on them, forked from and joined back to
+    // the batch stream (default priority, non-blocking)
+    static constexpr int kSide = 3;
+    hipStream_t side[kSide] = {};
+    hipEvent_t ev_fork = nullptr;
+    hipEvent_t ev_join[kSide] = {};
     // transform schedules chosen by fnls_batch_autotune per line length,
     // precision and axis kind: key m * 4 + fp64 * 2 + strided -> (rmax, lines)
     std::map<long long, std::pair<int, int>> sched;
@@ -2178,7 +2185,29 @@ void build_blob(Step& st, Blob& blob) {
 // Enqueue the launches of `st` on stream `s`, argument arrays at device
 // address `base` (laid out by build_blob).  attr_only: only raise the dynamic
 // LDS limits of the pass kernels (no launch), as a graph capture needs.
-int launch_step(fnls_batch* B, const Step& st, char* base, hipStream_t s_, bool attr_only = false) {
+// fork: a run of pass launches gives each line-length class its own stream
+// (the first class stays on s_, the others on the batch's side streams,
+// forked from s_ by an event); the classes touch disjoint instances, so their
+// chains of passes are independent and run side by side.  Every side stream
+// is joined back into s_ before the next streaming launch (which covers all
+// instances) and at the end, so s_ orders everything that follows.
+int launch_step(fnls_batch* B, const Step& st, char* base, hipStream_t s_, bool attr_only = false,
+                bool fork = false) {
+    fork = fork && !attr_only;
+    int cls[fnls_batch::kSide + 1];   // class of s_ and of each side stream in use
+    int ncls = 0;
+    unsigned used = 0;                // side streams forked since the last join
+    bool seg = false;                 // the fork event marks the start of the current run
+    auto join = [&]() -> hipError_t {
+        for (int k = 0; k < fnls_batch::kSide; ++k) {
+            if (!(used & (1u << k))) continue;
+            hipError_t e = hipEventRecord(B->ev_join[k], B->side[k]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s_, B->ev_join[k], 0);
+            if (e != hipSuccess) return e;
+        }
+        used = 0;
+        return hipSuccess;
+    };
     for (int o : st.order) {
         hipError_t e = hipSuccess;
         if (o >= 0) {
@@ -2186,10 +2215,39 @@ int launch_step(fnls_batch* B, const Step& st, char* base, hipStream_t s_, bool 
             const int count = (int)p.args.size();
             if (count == 0) continue;
             if (p.lds > B->ctx[0]->max_dyn_lds) return berr(B, FNLS_ERR_INVALID_ARG, "batch pass needs %zu B of LDS", p.lds);
+            hipStream_t ps = s_;
+            if (fork) {
+                // the run's fork point precedes its first launch, so a side
+                // stream waits only for what came before the run
+                if (!seg) {
+                    e = hipEventRecord(B->ev_fork, s_);
+                    if (e != hipSuccess)
+                        return berr(B, FNLS_ERR_HIP, "batched stream fork failed: %s", hipGetErrorString(e));
+                    seg = true;
+                }
+                int k = 0;
+                while (k < ncls && cls[k] != p.lgm) ++k;
+                if (k == ncls && ncls <= fnls_batch::kSide) cls[ncls++] = p.lgm;
+                if (k >= 1 && k <= fnls_batch::kSide) {
+                    const int sk = k - 1;
+                    if (!(used & (1u << sk))) {
+                        e = hipStreamWaitEvent(B->side[sk], B->ev_fork, 0);
+                        if (e != hipSuccess)
+                            return berr(B, FNLS_ERR_HIP, "batched stream fork failed: %s", hipGetErrorString(e));
+                        used |= 1u << sk;
+                    }
+                    ps = B->side[sk];
+                }
+            }
             e = launch_pass_batch(p.fp64, p.v, p.lgm, attr_only ? nullptr : reinterpret_cast<const PassArgs*>(base + p.a_off),
                                   reinterpret_cast<const int*>(base + p.o_off), count, p.offs.back(), p.lds,
-                                  p.threads, s_);
+                                  p.threads, ps);
         } else if (!attr_only) {
+            seg = false;
+            if (used) {
+                e = join();
+                if (e != hipSuccess) return berr(B, FNLS_ERR_HIP, "batched stream join failed: %s", hipGetErrorString(e));
+            }
             const StreamLaunch& s = st.streams[-o - 1];
             const int count = (int)s.args.size();
             if (count == 0) continue;
@@ -2204,6 +2262,10 @@ int launch_step(fnls_batch* B, const Step& st, char* base, hipStream_t s_, bool 
             }
         }
         if (e != hipSuccess) return berr(B, FNLS_ERR_HIP, "batched launch failed: %s", hipGetErrorString(e));
+    }
+    if (used) {
+        const hipError_t e = join();
+        if (e != hipSuccess) return berr(B, FNLS_ERR_HIP, "batched stream join failed: %s", hipGetErrorString(e));
     }
     return FNLS_OK;
 }
@@ -2288,7 +2350,7 @@ int prepare_iteration(fnls_batch* B, IterLaunch& it, bool graph) {
     BHIPCHK(B, hipMemcpyAsync(dslot, staged, blob.data.size(), hipMemcpyDeviceToDevice, B->stream));
     if ((rc = launch_step(B, it.st, dslot, B->cap, true)) != FNLS_OK) return rc;
     BHIPCHK(B, hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
-    rc = launch_step(B, it.st, dslot, B->cap);
+    rc = launch_step(B, it.st, dslot, B->cap, false, true);
     hipGraph_t graph_ = nullptr;
     const hipError_t e = hipStreamEndCapture(B->cap, &graph_);
     if (rc != FNLS_OK || e != hipSuccess) {
@@ -2316,7 +2378,7 @@ int launch_iteration(fnls_batch* B, IterLaunch& it) {
         ++B->replays;
         return FNLS_OK;
     }
-    return launch_step(B, it.st, it.base, B->stream);
+    return launch_step(B, it.st, it.base, B->stream, false, true);
 }
 
 StreamArgs stream_base(fnls_ctx* c) {
@@ -2728,6 +2790,14 @@ int fnls_batch_create(fnls_batch** out, fnls_ctx* const* ctxs, int count, void* 
             return FNLS_ERR_HIP;
         }
     }
+    bool ok = hipEventCreateWithFlags(&B->ev_fork, hipEventDisableTiming) == hipSuccess;
+    for (int k = 0; ok && k < fnls_batch::kSide; ++k)
+        ok = hipStreamCreateWithFlags(&B->side[k], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&B->ev_join[k], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        fnls_batch_destroy(B);
+        return FNLS_ERR_HIP;
+    }
     *out = B;
     return FNLS_OK;
 }
@@ -2738,6 +2808,11 @@ void fnls_batch_destroy(fnls_batch* B) {
     (void)hipStreamSynchronize(B->stream);
     for (int i = 0; i < kEvents; ++i)
         if (B->ev[i]) (void)hipEventDestroy(B->ev[i]);
+    for (int k = 0; k < fnls_batch::kSide; ++k) {
+        if (B->side[k]) (void)hipStreamDestroy(B->side[k]);
+        if (B->ev_join[k]) (void)hipEventDestroy(B->ev_join[k]);
+    }
+    if (B->ev_fork) (void)hipEventDestroy(B->ev_fork);
     for (int i = 0; i < kGraphSlots; ++i) drop_graph(B->gs[i]);
     if (B->cap) (void)hipStreamDestroy(B->cap);
     if (B->hring) (void)hipHostFree(B->hring);

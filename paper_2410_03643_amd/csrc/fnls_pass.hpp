@@ -454,11 +454,12 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
                 const long long gi = el.gi;
                 if (OPS & OP_SCALE) {
                     const R Dj = dpre[kNeedD ? q : 0];
-                    // -2 i om / ((om+1) - i D) = (2 om D - 2 i om (om+1)) / ((om+1)^2 + D^2)
+                    // -2 i om / ((om+1) - i D) = (2 om D - 2 i om (om+1)) / ((om+1)^2 + D^2),
+                    // one reciprocal per unknown
                     const R op1 = static_cast<R>(om + 1.0);
-                    const R den = op1 * op1 + Dj * Dj;
-                    const R fr = static_cast<R>(2.0 * om) * Dj / den;
-                    const R fi = -static_cast<R>(2.0 * om) * op1 / den;
+                    const R rden = R(1) / (op1 * op1 + Dj * Dj);
+                    const R fr = static_cast<R>(2.0 * om) * Dj * rden;
+                    const R fi = -static_cast<R>(2.0 * om) * op1 * rden;
                     z = cm<R>(z.x * fr - z.y * fi, z.x * fi + z.y * fr);
                 }
                 if (ZM == Z_WRITE) stc<R>(zout_p, gi, z);
