@@ -325,6 +325,67 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
                     lds[el.slot] = v;
                 }
             }
+        } else if constexpr (INM == IN_COMBO && !kAccEarly) {
+            // sum_k c_k t_k over the k stored vectors (the preconditioned
+            // basis z_k, complex64 when z32, with the coefficients y; else the
+            // basis v_k with coef), accumulated in FP64.  The vectors are the
+            // outer loop, so each is read for all of the thread's elements at
+            // once, and the next one is in flight while the current one is
+            // added.
+            long long gq[kMaxEptLine];
+            double sx[kMaxEptLine], sy[kMaxEptLine];
+#pragma unroll
+            for (int q = 0; q < kMaxEptLine; ++q) {
+                const Elem el = elem(ec, q);
+                gq[q] = el.valid ? el.gi : -1;
+                sx[q] = 0.0;
+                sy[q] = 0.0;
+            }
+            const bool zs = a.zsum != 0, z32 = a.z32 != 0;
+            auto load_vec = [&](int i, double2* t) {
+#pragma unroll
+                for (int q = 0; q < kMaxEptLine; ++q) {
+                    double2 v = dmk(0.0, 0.0);
+                    if (gq[q] >= 0) {
+                        if (zs) {
+                            const long long zi = (long long)i * a.N + gq[q];
+                            if (z32) {
+                                const float2 f = reinterpret_cast<const float2*>(a.vbase)[zi];
+                                v = dmk(f.x, f.y);
+                            } else {
+                                v = reinterpret_cast<const double2*>(a.vbase)[zi];
+                            }
+                        } else {
+                            const C u = (i == 0) ? ld<R>(a.v0, gq[q]) : ld<R>(a.vbase, (long long)(i - 1) * a.N + gq[q]);
+                            v = dmk(u.x, u.y);
+                        }
+                    }
+                    t[q] = v;
+                }
+            };
+            auto add_vec = [&](int i, const double2* t) {
+                const double2 c = zs ? a.st->y[i] : a.st->coef[i];
+#pragma unroll
+                for (int q = 0; q < kMaxEptLine; ++q) {
+                    sx[q] += c.x * t[q].x - c.y * t[q].y;
+                    sy[q] += c.x * t[q].y + c.y * t[q].x;
+                }
+            };
+            double2 ta[kMaxEptLine], tb[kMaxEptLine];
+            if (nvc > 0) load_vec(0, ta);
+            for (int i = 0; i < nvc; i += 2) {
+                if (i + 1 < nvc) load_vec(i + 1, tb);
+                add_vec(i, ta);
+                if (i + 1 < nvc) {
+                    if (i + 2 < nvc) load_vec(i + 2, ta);
+                    add_vec(i + 1, tb);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < kMaxEptLine; ++q) {
+                const Elem el = elem(ec, q);
+                if (el.in) lds[el.slot] = el.valid ? cm<R>(static_cast<R>(sx[q]), static_cast<R>(sy[q])) : czero<C>();
+            }
         } else {
 #pragma unroll
             for (int q = 0; q < kMaxEptLine; ++q) {
