@@ -424,3 +424,52 @@ def test_interleaved_element_writes_are_conflict_free_at_m256(fp64):
             for start in range(0, 64):
                 sl = [((start * 64 + l) & (L - 1)) * ls + ((start * 64 + l) >> lgL) + 1 for l in range(64)]
                 assert lds_extra_cycles(sl, elem, "w") == 0, (L, two, start)
+
+
+def mul_ipow(v, e):
+    """v i^e for e mod 4, as the kernels form it: a swap of the parts for odd
+    e, and sign flips."""
+    odd = e & 1
+    a, b = (v.imag, v.real) if odd else (v.real, v.imag)
+    return complex(-a if (e + 1) & 2 else a, -b if e & 2 else b)
+
+
+@pytest.mark.parametrize("m", [16, 64, 256, 1024])
+@pytest.mark.parametrize("inv", [False, True])
+@pytest.mark.parametrize("fp64", [True, False])
+def test_rotated_radix4_stockham_is_the_dft(m, inv, fp64):
+    """Replay of the compile-time radix-4 Stockham plan with the cyclic output
+    rotation: stages with Ns < 16 store output register i at slot position
+    (i + s) mod 4 (s = out_rot of the lane), the twiddle-free first stage
+    multiplies input q by W_4^{+-q s} (part swaps and sign flips), the next
+    stage folds W_4^{+-s} into its twiddle W^k (whose powers then carry
+    W_4^{+-q s}).  The result in natural order must be the DFT (inverse:
+    unnormalised inverse DFT) of the line."""
+    rng = np.random.default_rng(m)
+    x = rng.standard_normal(m) + 1j * rng.standard_normal(m)
+    sgn = 1.0 if inv else -1.0
+    G = m // 4
+    X = x.copy()
+    Ns = 1
+    while Ns < m:
+        Y = np.zeros(m, dtype=complex)
+        for b in range(G):
+            s = out_rot(b & 63, fp64) if Ns < 16 else 0
+            k = b % Ns
+            v = [X[b + r * G] for r in range(4)]
+            if Ns == 1:
+                e1 = s if inv else -s
+                v = [v[0], mul_ipow(v[1], e1), mul_ipow(v[2], 2 * s), mul_ipow(v[3], -e1)]
+            else:
+                w = np.exp(sgn * 2j * np.pi * k / (4 * Ns))
+                if Ns < 16:
+                    w = mul_ipow(w, s if inv else -s)
+                v = [v[r] * w ** r for r in range(4)]
+            y = [sum(v[q] * np.exp(sgn * 2j * np.pi * r * q / 4) for q in range(4)) for r in range(4)]
+            base = (b - k) * 4 + k
+            for i in range(4):
+                Y[base + ((i + s) & 3) * Ns] = y[i]
+        X = Y
+        Ns *= 4
+    ref = np.fft.ifft(x) * m if inv else np.fft.fft(x)
+    assert np.abs(X - ref).max() <= 1e-12 * np.abs(ref).max()
