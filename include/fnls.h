@@ -416,6 +416,19 @@ int fnls_get_host_stats(fnls_ctx *ctx, fnls_host_stats *out, int reset);
 int fnls_status_report_accepted(unsigned seq_base, unsigned seq_before, unsigned seq_after, int total,
                                 int done, int target);
 
+/* The host's launch geometry of a transform pass, for tests of the index
+ * arithmetic without a device (host arithmetic only, no HIP call).  For the
+ * pass along `axis` of the d-dimensional grid with n points per axis, in
+ * `precision`, with largest radix `rmax` (4, 8 or 16) and the lines setting
+ * `lines` (per workgroup at m = 1024, scaled up for shorter lines), within
+ * `max_dyn_lds` bytes of dynamic LDS, writes out[0..9]: threads per line G,
+ * lines per workgroup L, workgroups, dynamic LDS bytes, the axis stride, the
+ * number of lines, then the line layouts with two buffers (offset of buffer B
+ * and line stride, in slots) and with one (the same pair).  Returns
+ * FNLS_ERR_INVALID_ARG for sizes or settings the library does not support. */
+int fnls_pass_geometry(int d, int n, int axis, int precision, int rmax, int lines, size_t max_dyn_lds,
+                       long long out[10]);
+
 /* Last error message of this context ("" if none); valid until the next call. */
 const char *fnls_last_error(const fnls_ctx *ctx);
 

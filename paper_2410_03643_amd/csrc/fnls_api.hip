@@ -1594,6 +1594,27 @@ int fnls_status_report_accepted(unsigned seq_base, unsigned seq_before, unsigned
     return report_accepted(seq_base, seq_before, seq_after, total, done, target) ? 1 : 0;
 }
 
+int fnls_pass_geometry(int d, int n, int axis, int precision, int rmax, int lines, size_t max_dyn_lds,
+                       long long out[10]) {
+    if (!out || d < 1 || d > 3 || axis < 0 || axis >= d || !valid_n(n) ||
+        (precision != FNLS_FP64 && precision != FNLS_FP32_IR) || (rmax != 4 && rmax != 8 && rmax != 16) ||
+        lines < 1 || lines > 64 || max_dyn_lds == 0)
+        return FNLS_ERR_INVALID_ARG;
+    const bool fp64 = precision == FNLS_FP64;
+    PassConfig cfg = default_pass_config(n + 1);
+    for (int st = 0; st < 2; ++st) {
+        cfg.rmax[fp64 ? 1 : 0][st] = rmax;
+        cfg.lines[fp64 ? 1 : 0][st] = lines;
+    }
+    const Geo g = pass_geo(d, n, axis, fp64, max_dyn_lds, cfg);
+    int pa2 = 0, ls2 = 0, pa1 = 0, ls1 = 0;
+    line_layout(n + 1, g.L, fp64, true, &pa2, &ls2);
+    line_layout(n + 1, g.L, fp64, false, &pa1, &ls1);
+    const long long v[10] = {g.G, g.L, g.blocks, (long long)g.lds, g.stride, g.nlines, pa2, ls2, pa1, ls1};
+    for (int i = 0; i < 10; ++i) out[i] = v[i];
+    return FNLS_OK;
+}
+
 static int resolve_opts(fnls_ctx* c, const fnls_opts* in, fnls_opts* o, int restart_cap = -1) {
     if (in) *o = *in;
     else fnls_default_opts(o);

@@ -154,9 +154,11 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs a) {
 // are complex<R>; arithmetic in FP64.  Each thread owns kEpt elements
 // (stride = workgroup size: every load instruction of a wavefront is
 // contiguous) and issues all kEpt loads of a vector at once.
-// NVR > 0 (MODE 0, nv = NVR known at launch): the basis values of the
-// thread's elements are read once into registers and serve both the update
-// and the second-round dot products (a single read of V instead of two).
+// NVR > 0 (MODE 0, nv >= NVR): the values of the first NVR basis vectors at
+// the thread's elements are read once into registers and serve both the
+// update and the second-round dot products (a single read of those vectors
+// instead of two); vectors NVR .. nv-1 are streamed, once for the update and
+// once for the dot products.
 template <typename R, int MODE, bool BJ = false, int NVR = 0>
 __device__ __forceinline__ void cgs_body(const StreamArgs& a, int blk) {
     using C = cplx<R>;
@@ -201,6 +203,10 @@ __device__ __forceinline__ void cgs_body(const StreamArgs& a, int blk) {
         wy[q] = w.y;
     }
     constexpr bool kRegV = (MODE == 0 && NVR > 0);
+    // streamed vectors: all of them without registers; beyond the register
+    // set only for the widest one (nv > 5 is launched with NVR = 5), so that
+    // the narrower ones keep their register counts
+    constexpr bool kStream = !kRegV || NVR >= 5;
     C vr[kRegV ? NVR : 1][kRegV ? kEpt : 1];
     if constexpr (kRegV) {
 #pragma unroll
@@ -221,20 +227,42 @@ __device__ __forceinline__ void cgs_body(const StreamArgs& a, int blk) {
                 cmsub(wx[q], wy[q], c, vr[vi][q].x, vr[vi][q].y);
             }
         }
-    } else {
-        for (int vi = 0; vi < nv; ++vi) {
-            const void* vp = (vi == 0) ? a.v0
-                                       : (const void*)(reinterpret_cast<const C*>(a.vbase) + (long long)(vi - 1) * N);
+    }
+    // streamed basis vectors, double-buffered without the register set
+    // (vector vi + 1 is in flight while vector vi is applied or reduced);
+    // beside the register set, one at a time (the registers are full)
+    auto load_v = [&](int vi, C* v) {
+        const void* vp = (vi == 0) ? a.v0
+                                   : (const void*)(reinterpret_cast<const C*>(a.vbase) + (long long)(vi - 1) * N);
+#pragma unroll
+        for (int q = 0; q < kEpt; ++q) {
+            const long long i = base + (long long)q * kStreamThreads;
+            v[q] = i < N ? ld<R>(vp, i) : czero<C>();
+        }
+    };
+    const int vs0 = kRegV ? NVR : 0;
+    if constexpr (kStream) {
+        auto apply_v = [&](int vi, const C* v) {
             const double2 c = s_coef[vi];
-            C v[kEpt];
 #pragma unroll
-            for (int q = 0; q < kEpt; ++q) {
-                const long long i = base + (long long)q * kStreamThreads;
-                v[q] = i < N ? ld<R>(vp, i) : czero<C>();
+            for (int q = 0; q < kEpt; ++q) cmsub(wx[q], wy[q], c, v[q].x, v[q].y);
+        };
+        if constexpr (kRegV) {
+            for (int vi = vs0; vi < nv; ++vi) {
+                C v[kEpt];
+                load_v(vi, v);
+                apply_v(vi, v);
             }
-#pragma unroll
-            for (int q = 0; q < kEpt; ++q) {
-                cmsub(wx[q], wy[q], c, v[q].x, v[q].y);
+        } else {
+            C va[kEpt], vb[kEpt];
+            if (vs0 < nv) load_v(vs0, va);
+            for (int vi = vs0; vi < nv; vi += 2) {
+                if (vi + 1 < nv) load_v(vi + 1, vb);
+                apply_v(vi, va);
+                if (vi + 1 < nv) {
+                    if (vi + 2 < nv) load_v(vi + 2, va);
+                    apply_v(vi + 1, vb);
+                }
             }
         }
     }
@@ -263,25 +291,35 @@ __device__ __forceinline__ void cgs_body(const StreamArgs& a, int blk) {
             sy = wave_sum(sy);
             if (lane == 0) s_red[vi * kMaxWaves + wave] = dmk(sx, sy);
         }
-        nout = NVR;
-    } else if (MODE == 0) {
-        for (int vi = 0; vi < nv; ++vi) {
-            const void* vp = (vi == 0) ? a.v0
-                                       : (const void*)(reinterpret_cast<const C*>(a.vbase) + (long long)(vi - 1) * N);
-            C v[kEpt];
+    }
+    if (MODE == 0) {
+        if constexpr (kStream) {
+            auto dot_v = [&](int vi, const C* v) {
+                double sx = 0.0, sy = 0.0;
 #pragma unroll
-            for (int q = 0; q < kEpt; ++q) {
-                const long long i = base + (long long)q * kStreamThreads;
-                v[q] = i < N ? ld<R>(vp, i) : czero<C>();
+                for (int q = 0; q < kEpt; ++q) cdot_acc(sx, sy, v[q].x, v[q].y, wr[q].x, wr[q].y);
+                sx = wave_sum(sx);
+                sy = wave_sum(sy);
+                if (lane == 0) s_red[vi * kMaxWaves + wave] = dmk(sx, sy);
+            };
+            if constexpr (kRegV) {
+                for (int vi = vs0; vi < nv; ++vi) {
+                    C v[kEpt];
+                    load_v(vi, v);
+                    dot_v(vi, v);
+                }
+            } else {
+                C va[kEpt], vb[kEpt];
+                if (vs0 < nv) load_v(vs0, va);
+                for (int vi = vs0; vi < nv; vi += 2) {
+                    if (vi + 1 < nv) load_v(vi + 1, vb);
+                    dot_v(vi, va);
+                    if (vi + 1 < nv) {
+                        if (vi + 2 < nv) load_v(vi + 2, va);
+                        dot_v(vi + 1, vb);
+                    }
+                }
             }
-            double sx = 0.0, sy = 0.0;
-#pragma unroll
-            for (int q = 0; q < kEpt; ++q) {
-                cdot_acc(sx, sy, v[q].x, v[q].y, wr[q].x, wr[q].y);
-            }
-            sx = wave_sum(sx);
-            sy = wave_sum(sy);
-            if (lane == 0) s_red[vi * kMaxWaves + wave] = dmk(sx, sy);   // blockDim 256: kMaxWaves waves
         }
         nout = nv;
     } else {
@@ -490,7 +528,8 @@ hipError_t launch_reduce_chunks(const StreamArgs& a, int chunks, hipStream_t s, 
     return launch_k(k_reduce_chunks, dim3(chunks), dim3(kStreamThreads), 0, s, te, a, chunks);
 }
 
-// First update with nv basis vectors held in registers (nv <= kCgsRegMax)
+// First update with min(nv, kCgsRegMax) basis vectors held in registers
+// and the rest streamed
 template <typename R>
 static hipError_t launch_cgs_reg(const StreamArgs& a, dim3 g, dim3 b, hipStream_t s, const LaunchEvents* te) {
     switch (a.nv) {
@@ -501,13 +540,13 @@ static hipError_t launch_cgs_reg(const StreamArgs& a, dim3 g, dim3 b, hipStream_
         default: return launch_k(k_cgs<R, 0, 5>, g, b, 0, s, te, a);
     }
 }
-// (six vectors would spill: one workgroup per CU leaves 256 VGPRs, which
-// the basis values, w and the sums exceed)
+// (six vectors in registers would spill: one workgroup per CU leaves 256
+// VGPRs, which the basis values, w and the sums exceed)
 constexpr int kCgsRegMax = 5;
 
 hipError_t launch_cgs(int fp64, int mode, const StreamArgs& a, int blocks, hipStream_t s, const LaunchEvents* te) {
     const dim3 g(blocks), b(kStreamThreads);
-    if (mode == 0 && a.nv >= 1 && a.nv <= kCgsRegMax)
+    if (mode == 0 && a.nv >= 1)
         return fp64 ? launch_cgs_reg<double>(a, g, b, s, te) : launch_cgs_reg<float>(a, g, b, s, te);
     if (fp64)
         return mode == 0 ? launch_k(k_cgs<double, 0>, g, b, 0, s, te, a) : launch_k(k_cgs<double, 1>, g, b, 0, s, te, a);

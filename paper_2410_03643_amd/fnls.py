@@ -101,6 +101,8 @@ def lib() -> ctypes.CDLL:
     L.fnls_get_host_stats.restype = ci
     L.fnls_status_report_accepted.argtypes = [ctypes.c_uint, ctypes.c_uint, ctypes.c_uint, ci, ci, ci]
     L.fnls_status_report_accepted.restype = ci
+    L.fnls_pass_geometry.argtypes = [ci, ci, ci, ci, ci, ci, sz, ctypes.POINTER(ctypes.c_longlong)]
+    L.fnls_pass_geometry.restype = ci
     for name in ("fnls_apply_A", "fnls_apply_precond", "fnls_rhs", "fnls_apply_A_c64", "fnls_apply_precond_c64"):
         getattr(L, name).argtypes = [vp, vp, vp]
         getattr(L, name).restype = ci

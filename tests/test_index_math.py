@@ -473,3 +473,37 @@ def test_rotated_radix4_stockham_is_the_dft(m, inv, fp64):
         Ns *= 4
     ref = np.fft.ifft(x) * m if inv else np.fft.fft(x)
     assert np.abs(X - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("cfg", range(len(PASS_CONFIGS)))
+def test_mirror_matches_the_library_geometry(cfg):
+    """The host geometry rules replayed above (pass_geo, line_layout) are the
+    library's own: fnls_pass_geometry (host arithmetic of libfnls, no device)
+    gives the same G, L, workgroups, LDS bytes, stride, line count and line
+    layouts for every supported size, axis, precision and schedule."""
+    import ctypes
+    from paper_2410_03643_amd import fnls
+    L = fnls.lib()
+    out = (ctypes.c_longlong * 10)()
+    max_dyn = MAX_LDS_BLOCK - STATIC_LDS
+    checked = 0
+    for d, n in SIZES:
+        for axis in range(d):
+            for fp64 in (True, False):
+                c = PASS_CONFIGS[cfg]
+                col = 0 if axis == d - 1 else 1
+                prec = fnls.FP64 if fp64 else fnls.FP32_IR
+                rc = L.fnls_pass_geometry(d, n, axis, prec, c["rmax"][col], c["lines"][col], max_dyn, out)
+                assert rc == 0
+                g = pass_geo(d, n, axis, fp64, max_dyn, c)
+                m = n + 1
+                pa2, ls2 = line_layout(m, g["L"], fp64, True)
+                pa1, ls1 = line_layout(m, g["L"], fp64, False)
+                want = [g["G"], g["L"], g["blocks"], g["lds"], g["stride"], g["nlines"], pa2, ls2, pa1, ls1]
+                assert list(out) == want, (d, n, axis, fp64, list(out), want)
+                checked += 1
+    assert checked > 100
+    # unsupported settings are rejected
+    assert L.fnls_pass_geometry(2, 1000, 0, fnls.FP64, 4, 1, max_dyn, out) != 0
+    assert L.fnls_pass_geometry(2, 1023, 2, fnls.FP64, 4, 1, max_dyn, out) != 0
+    assert L.fnls_pass_geometry(2, 1023, 0, fnls.FP64, 5, 1, max_dyn, out) != 0
