@@ -118,7 +118,6 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
     LineTw<R, RMAX, LGM, !((OPS & OP_TOEP) && OUTM == OUT_ACC_FIRST)> ltw;
     ltw.init(tw, lt);
 
-
     // IN_CGS: totals of the second-round dot products d_i (every workgroup,
     // in the same fixed order), h_i = sigma_i d_i and the update coefficients
     // h_i sigma_i (basis vector i is stored as v_i / sigma_i); workgroup 0
@@ -233,8 +232,8 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
 
     // ---- load phase
     double wnrm = 0.0;   // IN_CGS: this thread's part of ||w||^2
-    // the accumulator of the other axes' Toeplitz products is loaded with the
-    // line data, so its loads are in flight during the transforms
+    // the accumulator of the other axes' Toeplitz products is loaded in the
+    // load phase, so its loads are in flight during the transforms
     constexpr bool kAccEarly = (OPS & OP_TOEP) != 0 && OUTM == OUT_ACC_NEXT;
     static_assert(!(kCgs && kAccEarly), "the fused Gram-Schmidt load phase reads no accumulator");
     C accq[kAccEarly ? kMaxEptLine : 1];
@@ -248,14 +247,18 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
             // every global load of the phase is in flight before the first
             // LDS write (a write waits for its value, and would otherwise hold
             // back the next element's loads: one memory round trip each)
+            // (FP64: the accumulator's loads are issued behind the line data's,
+            // below, and complete during the transforms; complex64 measured
+            // faster with both issued together)
+            constexpr bool kAccLate = sizeof(R) == 8;
             C vin[kMaxEptLine];
 #pragma unroll
             for (int q = 0; q < kMaxEptLine; ++q) {
                 const Elem el = elem(ec, q);
                 vin[q] = czero<C>();
-                if constexpr (kAccEarly) accq[q] = czero<C>();
+                if constexpr (kAccEarly && !kAccLate) accq[q] = czero<C>();
                 if (el.valid) {
-                    if constexpr (kAccEarly) accq[q] = ld<R>(a.acc_in, el.gi);
+                    if constexpr (kAccEarly && !kAccLate) accq[q] = ld<R>(a.acc_in, el.gi);
                     vin[q] = ld<R>(in_p, el.gi);
                 }
             }
@@ -266,6 +269,13 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
                     C v = vin[q];
                     if (INM == IN_BASIS && el.valid) v = cm<R>(static_cast<R>(v.x * sig), static_cast<R>(v.y * sig));
                     lds[el.slot] = v;
+                }
+            }
+            if constexpr (kAccEarly && kAccLate) {
+#pragma unroll
+                for (int q = 0; q < kMaxEptLine; ++q) {
+                    const Elem el = elem(ec, q);
+                    accq[q] = el.valid ? ld<R>(a.acc_in, el.gi) : czero<C>();
                 }
             }
         } else if constexpr (kCgs && sizeof(R) == 8) {
