@@ -159,6 +159,9 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs a) {
 // update and the second-round dot products (a single read of those vectors
 // instead of two); vectors NVR .. nv-1 are streamed, once for the update and
 // once for the dot products.
+// Widest register set: six vectors would spill (one workgroup per CU leaves
+// 256 VGPRs, which the basis values, w and the sums exceed).
+constexpr int kCgsRegMax = 5;
 template <typename R, int MODE, bool BJ = false, int NVR = 0>
 __device__ __forceinline__ void cgs_body(const StreamArgs& a, int blk) {
     using C = cplx<R>;
@@ -204,9 +207,10 @@ __device__ __forceinline__ void cgs_body(const StreamArgs& a, int blk) {
     }
     constexpr bool kRegV = (MODE == 0 && NVR > 0);
     // streamed vectors: all of them without registers; beyond the register
-    // set only for the widest one (nv > 5 is launched with NVR = 5), so that
-    // the narrower ones keep their register counts
-    constexpr bool kStream = !kRegV || NVR >= 5;
+    // set only for the widest one (nv > kCgsRegMax is launched with
+    // NVR = kCgsRegMax, smaller nv with NVR = nv), so that the narrower ones
+    // keep their register counts
+    constexpr bool kStream = !kRegV || NVR >= kCgsRegMax;
     C vr[kRegV ? NVR : 1][kRegV ? kEpt : 1];
     if constexpr (kRegV) {
 #pragma unroll
@@ -529,20 +533,19 @@ hipError_t launch_reduce_chunks(const StreamArgs& a, int chunks, hipStream_t s, 
 }
 
 // First update with min(nv, kCgsRegMax) basis vectors held in registers
-// and the rest streamed
+// and the rest streamed: NVR = nv up to four vectors (those variants stream
+// nothing), NVR = kCgsRegMax from five on
 template <typename R>
 static hipError_t launch_cgs_reg(const StreamArgs& a, dim3 g, dim3 b, hipStream_t s, const LaunchEvents* te) {
+    static_assert(kCgsRegMax == 5, "one specialisation per register-set width");
     switch (a.nv) {
         case 1: return launch_k(k_cgs<R, 0, 1>, g, b, 0, s, te, a);
         case 2: return launch_k(k_cgs<R, 0, 2>, g, b, 0, s, te, a);
         case 3: return launch_k(k_cgs<R, 0, 3>, g, b, 0, s, te, a);
         case 4: return launch_k(k_cgs<R, 0, 4>, g, b, 0, s, te, a);
-        default: return launch_k(k_cgs<R, 0, 5>, g, b, 0, s, te, a);
+        default: return launch_k(k_cgs<R, 0, kCgsRegMax>, g, b, 0, s, te, a);
     }
 }
-// (six vectors in registers would spill: one workgroup per CU leaves 256
-// VGPRs, which the basis values, w and the sums exceed)
-constexpr int kCgsRegMax = 5;
 
 hipError_t launch_cgs(int fp64, int mode, const StreamArgs& a, int blocks, hipStream_t s, const LaunchEvents* te) {
     const dim3 g(blocks), b(kStreamThreads);
