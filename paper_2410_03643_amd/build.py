@@ -15,6 +15,10 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfnls.so")
 SOURCES = ["fnls_pass64.hip", "fnls_pass32.hip", "fnls_kernels.hip", "fnls_api.hip"]
 ARCH = os.environ.get("FNLS_OFFLOAD_ARCH", "gfx950")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+# the host trace ranges (roctx) resolve against the ROCm profiler SDK's library
+LINK_LIBS = ["-L" + os.path.join(ROCM, "lib"), "-Wl,-rpath," + os.path.join(ROCM, "lib"),
+             "-lrocprofiler-sdk-roctx"]
 
 
 def hipcc() -> str:
@@ -42,7 +46,7 @@ def build(verbose: bool = False, extra_flags=()) -> str:
     if failed:
         raise subprocess.CalledProcessError(1, failed[0])
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, *objs, *LINK_LIBS]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

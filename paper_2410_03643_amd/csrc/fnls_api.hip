@@ -2,6 +2,7 @@
 // host assembly of the tables, and the GMRES / GMRES-IR drivers that
 // sequence the kernels of fnls_kernels.hip on the context's stream.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <cmath>
@@ -35,6 +36,17 @@ constexpr int kRedundantMax = 1024;
 constexpr int kReduceChunks = 64;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Host-side trace range (roctx): one per solve-level API call and one per
+// restart cycle, so that a profiler recording markers (rocprofv3
+// --marker-trace) shows where the host spends its time between the kernels.
+// Without such a profiler a push or pop is a call that returns at once.
+struct TraceRange {
+    explicit TraceRange(const char* name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange&) = delete;
+    TraceRange& operator=(const TraceRange&) = delete;
+};
 
 bool valid_n(int n) {
     if (n < 1 || n > 1023) return false;
@@ -1178,6 +1190,7 @@ void fill_info(fnls_ctx* c, fnls_info* info, int status) {
 
 int solve_impl(fnls_ctx* c, const fnls_c128* b, fnls_c128* x, const fnls_opts* o, fnls_info* info) {
     const bool fp64 = (o->precision == FNLS_FP64);
+    const TraceRange trace(fp64 ? "fnls.solve.fp64" : "fnls.solve.fp32_ir");
     const int restart = o->restart;
     c->seq_base += kSeqStride;
     c->poll_delay_us = o->poll_delay_us;
@@ -1220,6 +1233,7 @@ int solve_impl(fnls_ctx* c, const fnls_c128* b, fnls_c128* x, const fnls_opts* o
     double relres_prev = 1.0;
     int cycle = 0;        // cycles of this solve whose end is enqueued
     while (true) {
+        const TraceRange trace_cycle("fnls.cycle");
         Bufs bf = bufs(c, fp64, first ? (const void*)b : (const void*)c->sc<double2>(c->lay.r64));
         int done = 0, final_issued = 0;
         const FinalArgs fin{b, x, first};
@@ -1683,6 +1697,7 @@ int fnls_solve_noalloc(fnls_ctx* c, const fnls_c128* b, fnls_c128* x, const fnls
 
 int fnls_step(fnls_ctx* c, const fnls_c128* u_prev, const fnls_c128* u_cur, fnls_c128* u_next,
               const fnls_opts* opts, fnls_info* info) {
+    const TraceRange trace("fnls.step");
     int rc = check_ready(c);
     if (rc != FNLS_OK) return rc;
     if (!u_prev || !u_cur || !u_next) return set_err(c, FNLS_ERR_INVALID_ARG, "NULL vector");
@@ -1699,6 +1714,7 @@ int fnls_step(fnls_ctx* c, const fnls_c128* u_prev, const fnls_c128* u_cur, fnls
 }
 
 int fnls_first_step(fnls_ctx* c, const fnls_c128* u0, fnls_c128* u1, const fnls_opts* opts, fnls_info* info) {
+    const TraceRange trace("fnls.first_step");
     int rc = check_ready(c);
     if (rc != FNLS_OK) return rc;
     if (!u0 || !u1) return set_err(c, FNLS_ERR_INVALID_ARG, "NULL vector");
@@ -1792,6 +1808,7 @@ extern "C" {
 int fnls_step_backward(fnls_ctx* c, const fnls_c128* u_prev, const fnls_c128* u_cur, const fnls_c128* u_next,
                        const fnls_c128* g_next, fnls_c128* g_prev, fnls_c128* g_cur, double* g_V,
                        const fnls_opts* opts, fnls_info* info) {
+    const TraceRange trace("fnls.step_backward");
     int rc = check_ready(c);
     if (rc != FNLS_OK) return rc;
     if (!u_prev || !u_cur || !u_next || !g_next || !g_prev || !g_cur)
@@ -1805,6 +1822,7 @@ int fnls_step_backward(fnls_ctx* c, const fnls_c128* u_prev, const fnls_c128* u_
 
 int fnls_first_step_backward(fnls_ctx* c, const fnls_c128* u0, const fnls_c128* u1, const fnls_c128* g1,
                              fnls_c128* g0, double* g_V, const fnls_opts* opts, fnls_info* info) {
+    const TraceRange trace("fnls.first_step_backward");
     int rc = check_ready(c);
     if (rc != FNLS_OK) return rc;
     if (!u0 || !u1 || !g1 || !g0) return set_err(c, FNLS_ERR_INVALID_ARG, "NULL vector");
@@ -1846,6 +1864,7 @@ int fnls_timing_report(fnls_ctx* c, fnls_kernel_stat* out, int max_entries) {
 }
 
 int fnls_autotune(fnls_ctx* c, const fnls_c128* b, int precision, int reps, int best[4], double* best_ms) {
+    const TraceRange trace("fnls.autotune");
     int rc = check_solve_ready(c);
     if (rc != FNLS_OK) return rc;
     if (!b) return set_err(c, FNLS_ERR_INVALID_ARG, "NULL vector");
@@ -2849,6 +2868,7 @@ int fnls_batch_graph_stats(const fnls_batch* B, long long* captures, long long* 
 
 int fnls_batch_solve(fnls_batch* B, const fnls_c128* const* bs, fnls_c128* const* xs, const fnls_opts* opts,
                      fnls_info* infos) {
+    const TraceRange trace("fnls.batch_solve");
     if (!B) return FNLS_ERR_INVALID_ARG;
     if (!bs || !xs) return berr(B, FNLS_ERR_INVALID_ARG, "NULL pointer array");
     fnls_opts o;
@@ -2867,6 +2887,7 @@ int fnls_batch_solve(fnls_batch* B, const fnls_c128* const* bs, fnls_c128* const
 
 int fnls_batch_step(fnls_batch* B, const fnls_c128* const* u_prev, const fnls_c128* const* u_cur,
                     fnls_c128* const* u_next, const fnls_opts* opts, fnls_info* infos) {
+    const TraceRange trace("fnls.batch_step");
     if (!B) return FNLS_ERR_INVALID_ARG;
     if (!u_prev || !u_cur || !u_next) return berr(B, FNLS_ERR_INVALID_ARG, "NULL pointer array");
     fnls_opts o;
@@ -2910,6 +2931,7 @@ int fnls_batch_step(fnls_batch* B, const fnls_c128* const* u_prev, const fnls_c1
 }
 
 int fnls_batch_autotune(fnls_batch* B, const fnls_c128* const* b, int precision, int reps, int* classes) {
+    const TraceRange trace("fnls.batch_autotune");
     if (!B) return FNLS_ERR_INVALID_ARG;
     if (classes) *classes = 0;
     if (!b) return berr(B, FNLS_ERR_INVALID_ARG, "NULL pointer array");

@@ -20,6 +20,21 @@ def test_exports_every_declared_symbol(L):
         assert hasattr(L, name), name
 
 
+def test_library_carries_the_host_trace_ranges(L):
+    """The solve-level calls open roctx ranges: the library needs the ROCm
+    profiler SDK's roctx library and imports its push and pop."""
+    import shutil
+    import subprocess
+    if not shutil.which("readelf"):
+        pytest.skip("readelf not available")
+    dyn = subprocess.run(["readelf", "-d", fnls.LIB_PATH], capture_output=True, text=True, check=True).stdout
+    assert "librocprofiler-sdk-roctx.so" in dyn
+    syms = subprocess.run(["readelf", "--dyn-syms", "-W", fnls.LIB_PATH], capture_output=True, text=True,
+                          check=True).stdout
+    undef = {ln.split()[-1].split("@")[0] for ln in syms.splitlines() if " UND " in ln}
+    assert {"roctxRangePushA", "roctxRangePop"} <= undef
+
+
 def test_default_opts(L):
     o = fnls.default_opts()
     assert o.tol == 1e-10 and o.restart == 30 and o.maxit == 2000

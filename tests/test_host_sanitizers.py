@@ -17,6 +17,8 @@ import subprocess
 
 import pytest
 
+from paper_2410_03643_amd import build
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
@@ -40,7 +42,8 @@ def test_host_code_is_clean_under_sanitizers(tmp_path):
                    check=True, capture_output=True)
     subprocess.run([cc, *common, *san, "-c", os.path.join(ROOT, "tests", "host", "abi_host_check.cpp"),
                     "-o", chk_o], check=True, capture_output=True)
-    subprocess.run([cc, "--offload-arch=gfx950", *san, chk_o, api_o, "-o", exe], check=True, capture_output=True)
+    subprocess.run([cc, "--offload-arch=gfx950", *san, chk_o, api_o, "-o", exe, *build.LINK_LIBS],
+                   check=True, capture_output=True)
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:halt_on_error=1",
                UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
     r = subprocess.run([exe], capture_output=True, text=True, timeout=300, env=env)
