@@ -178,6 +178,45 @@ __device__ __forceinline__ void cgs_body(const StreamArgs& a, int blk) {
         wp = reinterpret_cast<C*>(wp) + (long long)j * a.jw;
     }
     GmresState* st = a.st;
+    // w and the register-held basis values (or the first streamed vector)
+    // are read before the dot-product totals are reduced: a barrier does not
+    // wait for global loads, so they are in flight during the reduction
+    const long long base = (long long)blk * (kStreamThreads * kEpt) + threadIdx.x;
+    double wx[kEpt], wy[kEpt];
+#pragma unroll
+    for (int q = 0; q < kEpt; ++q) {
+        const long long i = base + (long long)q * kStreamThreads;
+        const C w = i < N ? ld<R>(wp, i) : czero<C>();
+        wx[q] = w.x;
+        wy[q] = w.y;
+    }
+    constexpr bool kRegV = (MODE == 0 && NVR > 0);
+    // streamed vectors: all of them without registers; beyond the register
+    // set only for the widest one (nv > kCgsRegMax is launched with
+    // NVR = kCgsRegMax, smaller nv with NVR = nv), so that the narrower ones
+    // keep their register counts
+    constexpr bool kStream = !kRegV || NVR >= kCgsRegMax;
+    auto load_v = [&](int vi, C* v) {
+        const void* vp = (vi == 0) ? a.v0
+                                   : (const void*)(reinterpret_cast<const C*>(a.vbase) + (long long)(vi - 1) * N);
+#pragma unroll
+        for (int q = 0; q < kEpt; ++q) {
+            const long long i = base + (long long)q * kStreamThreads;
+            v[q] = i < N ? ld<R>(vp, i) : czero<C>();
+        }
+    };
+    C vr[kRegV ? NVR : 1][kRegV ? kEpt : 1];
+    if constexpr (kRegV) {
+#pragma unroll
+        for (int vi = 0; vi < NVR; ++vi) load_v(vi, vr[vi]);
+    }
+    const int vs0 = kRegV ? NVR : 0;
+    // without the register set, the double-buffered stream's first vector
+    C va[kRegV ? 1 : kEpt], vb[kRegV ? 1 : kEpt];
+    if constexpr (!kRegV) {
+        if (vs0 < nv) load_v(vs0, va);
+    }
+
     reduce_partials(a.pin, a.pin_stride, a.pin_nb, MODE == 0 ? nv + 1 : nv, s_tot, s_red);
     if (threadIdx.x < nv) {
         const int i = threadIdx.x;
@@ -196,33 +235,7 @@ __device__ __forceinline__ void cgs_body(const StreamArgs& a, int blk) {
     if (MODE == 0 && blk == 0 && threadIdx.x == 0) st->wnorm0 = sqrt(s_tot[nv].x);
     __syncthreads();
 
-    const long long base = (long long)blk * (kStreamThreads * kEpt) + threadIdx.x;
-    double wx[kEpt], wy[kEpt];
-#pragma unroll
-    for (int q = 0; q < kEpt; ++q) {
-        const long long i = base + (long long)q * kStreamThreads;
-        const C w = i < N ? ld<R>(wp, i) : czero<C>();
-        wx[q] = w.x;
-        wy[q] = w.y;
-    }
-    constexpr bool kRegV = (MODE == 0 && NVR > 0);
-    // streamed vectors: all of them without registers; beyond the register
-    // set only for the widest one (nv > kCgsRegMax is launched with
-    // NVR = kCgsRegMax, smaller nv with NVR = nv), so that the narrower ones
-    // keep their register counts
-    constexpr bool kStream = !kRegV || NVR >= kCgsRegMax;
-    C vr[kRegV ? NVR : 1][kRegV ? kEpt : 1];
     if constexpr (kRegV) {
-#pragma unroll
-        for (int vi = 0; vi < NVR; ++vi) {
-            const void* vp = (vi == 0) ? a.v0
-                                       : (const void*)(reinterpret_cast<const C*>(a.vbase) + (long long)(vi - 1) * N);
-#pragma unroll
-            for (int q = 0; q < kEpt; ++q) {
-                const long long i = base + (long long)q * kStreamThreads;
-                vr[vi][q] = i < N ? ld<R>(vp, i) : czero<C>();
-            }
-        }
 #pragma unroll
         for (int vi = 0; vi < NVR; ++vi) {
             const double2 c = s_coef[vi];
@@ -235,16 +248,6 @@ __device__ __forceinline__ void cgs_body(const StreamArgs& a, int blk) {
     // streamed basis vectors, double-buffered without the register set
     // (vector vi + 1 is in flight while vector vi is applied or reduced);
     // beside the register set, one at a time (the registers are full)
-    auto load_v = [&](int vi, C* v) {
-        const void* vp = (vi == 0) ? a.v0
-                                   : (const void*)(reinterpret_cast<const C*>(a.vbase) + (long long)(vi - 1) * N);
-#pragma unroll
-        for (int q = 0; q < kEpt; ++q) {
-            const long long i = base + (long long)q * kStreamThreads;
-            v[q] = i < N ? ld<R>(vp, i) : czero<C>();
-        }
-    };
-    const int vs0 = kRegV ? NVR : 0;
     if constexpr (kStream) {
         auto apply_v = [&](int vi, const C* v) {
             const double2 c = s_coef[vi];
@@ -258,8 +261,6 @@ __device__ __forceinline__ void cgs_body(const StreamArgs& a, int blk) {
                 apply_v(vi, v);
             }
         } else {
-            C va[kEpt], vb[kEpt];
-            if (vs0 < nv) load_v(vs0, va);
             for (int vi = vs0; vi < nv; vi += 2) {
                 if (vi + 1 < nv) load_v(vi + 1, vb);
                 apply_v(vi, va);
@@ -313,7 +314,6 @@ __device__ __forceinline__ void cgs_body(const StreamArgs& a, int blk) {
                     dot_v(vi, v);
                 }
             } else {
-                C va[kEpt], vb[kEpt];
                 if (vs0 < nv) load_v(vs0, va);
                 for (int vi = vs0; vi < nv; vi += 2) {
                     if (vi + 1 < nv) load_v(vi + 1, vb);

@@ -118,61 +118,6 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
     LineTw<R, RMAX, LGM, !((OPS & OP_TOEP) && OUTM == OUT_ACC_FIRST)> ltw;
     ltw.init(tw, lt);
 
-    // IN_CGS: totals of the second-round dot products d_i (every workgroup,
-    // in the same fixed order), h_i = sigma_i d_i and the update coefficients
-    // h_i sigma_i (basis vector i is stored as v_i / sigma_i); workgroup 0
-    // completes the Hessenberg column.  The line buffers serve as reduction
-    // scratch before the per-line set-up below overwrites them.
-    constexpr bool kCgs = (INM == IN_CGS);
-    __shared__ double2 s_cgs[kCgs ? 2 * (kMaxRestart + 2) : 1];
-    __shared__ double s_wn[kCgs ? 16 : 1];
-    if constexpr (kCgs) {
-        const int nv = basis_j + 1;
-        double2* s_tot = s_cgs;
-        double2* s_coef = s_cgs + (kMaxRestart + 2);
-        reduce_partials(a.cgs_pin, a.cgs_stride, a.cgs_nb, nv, s_tot, reinterpret_cast<double2*>(smem_raw));
-        if (tid < nv) {
-            const double sg = a.st->sigma[tid];
-            const double2 h = dmk(s_tot[tid].x * sg, s_tot[tid].y * sg);
-            s_coef[tid] = dmk(h.x * sg, h.y * sg);
-            if (blk == 0) {
-                a.st->hcol[tid].x += h.x;
-                a.st->hcol[tid].y += h.y;
-            }
-        }
-        __syncthreads();
-    }
-
-    // per-line base offset and Lambda of the other axes
-    for (int l = tid; l < L; l += T) {
-        const long long lg = (long long)blk * L + l;
-        long long base = -1;
-        R lamo = 0;
-        if (lg < a.nlines) {
-            const long long o = lg / stride;
-            const long long i = lg - o * stride;
-            base = o * (long long)n * stride + i;
-            if (OPS & OP_DIV) {
-                long long t = o;
-                for (int ax = 0; ax < a.axis; ++ax) {
-                    lamo += lam[(int)(t % n) + 1];
-                    t /= n;
-                }
-                t = i;
-                for (int ax = a.axis + 1; ax < a.d; ++ax) {
-                    lamo += lam[(int)(t % n) + 1];
-                    t /= n;
-                }
-                lamo *= tscale;
-            }
-        }
-        s_base[l] = base;
-        s_lamo[l] = lamo;
-        lds[(size_t)l * LS] = czero<C>();   // slot 0: the Dirichlet zero
-    }
-    for (int q = tid; q < nq; q += T) twl[tw_slot<R>(q)] = tw[2 * q];
-    __syncthreads();
-
     // Coalescing element map: element q < kMaxEptLine of this thread is
     // e = tid + q T of the workgroup's L n unknowns.  Rows of the contiguous
     // axis lie back to back (e = l n + j, global index blk L n + e); lines of
@@ -230,6 +175,96 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
         return r;
     };
 
+    // IN_CGS: totals of the second-round dot products d_i (every workgroup,
+    // in the same fixed order), h_i = sigma_i d_i and the update coefficients
+    // h_i sigma_i (basis vector i is stored as v_i / sigma_i); workgroup 0
+    // completes the Hessenberg column.  The line buffers serve as reduction
+    // scratch before the per-line set-up below overwrites them.
+    constexpr bool kCgs = (INM == IN_CGS);
+    __shared__ double2 s_cgs[kCgs ? 2 * (kMaxRestart + 2) : 1];
+    __shared__ double s_wn[kCgs ? 16 : 1];
+    // FP64 IN_CGS: w and the first basis vector are read before the totals
+    // are reduced (a barrier does not wait for global loads, so they are in
+    // flight during the reduction).  On the contiguous axis, where the pass
+    // runs, the element map needs no per-line set-up; on a strided axis the
+    // load phase reads them after the set-up.
+    constexpr bool kCgs64 = kCgs && sizeof(R) == 8;
+    constexpr int kCq = kCgs64 ? kMaxEptLine : 1;
+    long long cg_gq[kCq];
+    double cg_wx[kCq], cg_wy[kCq];
+    C cg_ta[kCq], cg_tb[kCq];
+    auto cg_load_vec = [&](int i, C* t) {
+        const C* src = (i == 0) ? reinterpret_cast<const C*>(a.v0)
+                                : reinterpret_cast<const C*>(a.vbase) + (long long)(i - 1) * a.N;
+#pragma unroll
+        for (int q = 0; q < kCq; ++q) t[q] = cg_gq[q] >= 0 ? src[cg_gq[q]] : czero<C>();
+    };
+    auto cg_first_loads = [&]() {
+        const ElemCtx ec = elem_ctx();
+#pragma unroll
+        for (int q = 0; q < kCq; ++q) {
+            const Elem el = elem(ec, q);
+            cg_gq[q] = el.valid ? el.gi : -1;
+            cg_wx[q] = 0.0;
+            cg_wy[q] = 0.0;
+            if (el.valid) {
+                const C wv = ld<R>(in_p, el.gi);
+                cg_wx[q] = wv.x;
+                cg_wy[q] = wv.y;
+            }
+        }
+        cg_load_vec(0, cg_ta);
+    };
+    if constexpr (kCgs64) {
+        if (contiguous) cg_first_loads();
+    }
+    if constexpr (kCgs) {
+        const int nv = basis_j + 1;
+        double2* s_tot = s_cgs;
+        double2* s_coef = s_cgs + (kMaxRestart + 2);
+        reduce_partials(a.cgs_pin, a.cgs_stride, a.cgs_nb, nv, s_tot, reinterpret_cast<double2*>(smem_raw));
+        if (tid < nv) {
+            const double sg = a.st->sigma[tid];
+            const double2 h = dmk(s_tot[tid].x * sg, s_tot[tid].y * sg);
+            s_coef[tid] = dmk(h.x * sg, h.y * sg);
+            if (blk == 0) {
+                a.st->hcol[tid].x += h.x;
+                a.st->hcol[tid].y += h.y;
+            }
+        }
+        __syncthreads();
+    }
+
+    // per-line base offset and Lambda of the other axes
+    for (int l = tid; l < L; l += T) {
+        const long long lg = (long long)blk * L + l;
+        long long base = -1;
+        R lamo = 0;
+        if (lg < a.nlines) {
+            const long long o = lg / stride;
+            const long long i = lg - o * stride;
+            base = o * (long long)n * stride + i;
+            if (OPS & OP_DIV) {
+                long long t = o;
+                for (int ax = 0; ax < a.axis; ++ax) {
+                    lamo += lam[(int)(t % n) + 1];
+                    t /= n;
+                }
+                t = i;
+                for (int ax = a.axis + 1; ax < a.d; ++ax) {
+                    lamo += lam[(int)(t % n) + 1];
+                    t /= n;
+                }
+                lamo *= tscale;
+            }
+        }
+        s_base[l] = base;
+        s_lamo[l] = lamo;
+        lds[(size_t)l * LS] = czero<C>();   // slot 0: the Dirichlet zero
+    }
+    for (int q = tid; q < nq; q += T) twl[tw_slot<R>(q)] = tw[2 * q];
+    __syncthreads();
+
     // ---- load phase
     double wnrm = 0.0;   // IN_CGS: this thread's part of ||w||^2
     // the accumulator of the other axes' Toeplitz products is loaded in the
@@ -286,39 +321,18 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
             // current one is applied (measured faster for FP64 only; complex64
             // bases take the per-element loop below).
             const double2* s_coef = s_cgs + (kMaxRestart + 2);
-            long long gq[kMaxEptLine];
-            double wx[kMaxEptLine], wy[kMaxEptLine];
-#pragma unroll
-            for (int q = 0; q < kMaxEptLine; ++q) {
-                const Elem el = elem(ec, q);
-                gq[q] = el.valid ? el.gi : -1;
-                wx[q] = 0.0;
-                wy[q] = 0.0;
-                if (el.valid) {
-                    const C wv = ld<R>(in_p, el.gi);
-                    wx[q] = wv.x;
-                    wy[q] = wv.y;
-                }
-            }
-            auto load_vec = [&](int i, C* t) {
-                const C* src = (i == 0) ? reinterpret_cast<const C*>(a.v0)
-                                        : reinterpret_cast<const C*>(a.vbase) + (long long)(i - 1) * a.N;
-#pragma unroll
-                for (int q = 0; q < kMaxEptLine; ++q) t[q] = gq[q] >= 0 ? src[gq[q]] : czero<C>();
-            };
+            if (!contiguous) cg_first_loads();
             auto apply_vec = [&](int i, const C* t) {
                 const double2 c = s_coef[i];
 #pragma unroll
-                for (int q = 0; q < kMaxEptLine; ++q) cmsub(wx[q], wy[q], c, t[q].x, t[q].y);
+                for (int q = 0; q < kMaxEptLine; ++q) cmsub(cg_wx[q], cg_wy[q], c, t[q].x, t[q].y);
             };
-            C ta[kMaxEptLine], tb[kMaxEptLine];
-            load_vec(0, ta);
             for (int i = 0; i <= basis_j; i += 2) {
-                if (i + 1 <= basis_j) load_vec(i + 1, tb);
-                apply_vec(i, ta);
+                if (i + 1 <= basis_j) cg_load_vec(i + 1, cg_tb);
+                apply_vec(i, cg_ta);
                 if (i + 1 <= basis_j) {
-                    if (i + 2 <= basis_j) load_vec(i + 2, ta);
-                    apply_vec(i + 1, tb);
+                    if (i + 2 <= basis_j) cg_load_vec(i + 2, cg_ta);
+                    apply_vec(i + 1, cg_tb);
                 }
             }
 #pragma unroll
@@ -327,7 +341,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
                 if (el.in) {
                     C v = czero<C>();
                     if (el.valid) {
-                        v = cm<R>(static_cast<R>(wx[q]), static_cast<R>(wy[q]));
+                        v = cm<R>(static_cast<R>(cg_wx[q]), static_cast<R>(cg_wy[q]));
                         stc<R>(const_cast<void*>(in_p), el.gi, v);
                         wnrm = fma((double)v.x, (double)v.x, wnrm);
                         wnrm = fma((double)v.y, (double)v.y, wnrm);
