@@ -156,6 +156,25 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
         }
         return c;
     };
+    // the same context before the per-line set-up: the thread forms its
+    // line's base offset itself (32-bit: lines and strides stay below 2^32)
+    auto elem_ctx_direct = [&]() {
+        ElemCtx c;
+        c.t = tid;
+        asm volatile("" : "+v"(c.t));
+        if (contiguous) {
+            c.gi0 = (long long)blk * L * n;
+            c.ok = true;
+        } else {
+            const unsigned lg = (unsigned)blk * (unsigned)L + (unsigned)(c.t & (L - 1));
+            const unsigned st = (unsigned)stride;
+            const unsigned o = lg / st;
+            const unsigned i = lg - o * st;
+            c.ok = (long long)lg < a.nlines;
+            c.gi0 = (long long)o * n * stride + i + (long long)(c.t >> lgL) * stride;
+        }
+        return c;
+    };
     auto elem = [&](const ElemCtx& c, int q) {
         Elem r;
         const int e = c.t + q * T;
@@ -235,6 +254,32 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
         __syncthreads();
     }
 
+    // IN_PLAIN / IN_BASIS: the line data's loads are issued before the
+    // per-line set-up (whose global reads and barrier they then overlap);
+    // complex64 also issues the accumulator's loads here
+    constexpr bool kAccEarly = (OPS & OP_TOEP) != 0 && OUTM == OUT_ACC_NEXT;
+    static_assert(!(kCgs && kAccEarly), "the fused Gram-Schmidt load phase reads no accumulator");
+    constexpr bool kInEarly = (INM == IN_PLAIN || INM == IN_BASIS);
+    // (FP64: the accumulator's loads are issued behind the line data's LDS
+    // writes, and complete during the transforms; complex64 measured faster
+    // with both issued together)
+    constexpr bool kAccLate = sizeof(R) == 8;
+    C vin[kInEarly ? kMaxEptLine : 1];
+    C accq[kAccEarly ? kMaxEptLine : 1];
+    if constexpr (kInEarly) {
+        const ElemCtx ec = elem_ctx_direct();
+#pragma unroll
+        for (int q = 0; q < kMaxEptLine; ++q) {
+            const Elem el = elem(ec, q);
+            vin[q] = czero<C>();
+            if constexpr (kAccEarly && !kAccLate) accq[q] = czero<C>();
+            if (el.valid) {
+                if constexpr (kAccEarly && !kAccLate) accq[q] = ld<R>(a.acc_in, el.gi);
+                vin[q] = ld<R>(in_p, el.gi);
+            }
+        }
+    }
+
     // per-line base offset and Lambda of the other axes
     for (int l = tid; l < L; l += T) {
         const long long lg = (long long)blk * L + l;
@@ -269,9 +314,6 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
     double wnrm = 0.0;   // IN_CGS: this thread's part of ||w||^2
     // the accumulator of the other axes' Toeplitz products is loaded in the
     // load phase, so its loads are in flight during the transforms
-    constexpr bool kAccEarly = (OPS & OP_TOEP) != 0 && OUTM == OUT_ACC_NEXT;
-    static_assert(!(kCgs && kAccEarly), "the fused Gram-Schmidt load phase reads no accumulator");
-    C accq[kAccEarly ? kMaxEptLine : 1];
     {
         double sig = 1.0;
         if (INM == IN_BASIS) sig = a.st->sigma[basis_j];
@@ -279,24 +321,9 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
         if (INM == IN_COMBO) nvc = a.st->k;
         const ElemCtx ec = elem_ctx();
         if constexpr (INM == IN_PLAIN || INM == IN_BASIS) {
-            // every global load of the phase is in flight before the first
+            // every global load of the phase was issued before the first
             // LDS write (a write waits for its value, and would otherwise hold
             // back the next element's loads: one memory round trip each)
-            // (FP64: the accumulator's loads are issued behind the line data's,
-            // below, and complete during the transforms; complex64 measured
-            // faster with both issued together)
-            constexpr bool kAccLate = sizeof(R) == 8;
-            C vin[kMaxEptLine];
-#pragma unroll
-            for (int q = 0; q < kMaxEptLine; ++q) {
-                const Elem el = elem(ec, q);
-                vin[q] = czero<C>();
-                if constexpr (kAccEarly && !kAccLate) accq[q] = czero<C>();
-                if (el.valid) {
-                    if constexpr (kAccEarly && !kAccLate) accq[q] = ld<R>(a.acc_in, el.gi);
-                    vin[q] = ld<R>(in_p, el.gi);
-                }
-            }
 #pragma unroll
             for (int q = 0; q < kMaxEptLine; ++q) {
                 const Elem el = elem(ec, q);

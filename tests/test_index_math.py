@@ -204,6 +204,19 @@ def test_pass_addresses(d, n, max_dyn, cfg):
                 assert np.all(seen == 1), (axis, fp64)
 
 
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_direct_line_base_fits_32_bits(d):
+    """Before the per-line set-up, a pass thread forms its line's base offset
+    from 32-bit unsigned line indices and strides (lg = blk L + l, o = lg /
+    stride); at every size the library accepts they stay below 2^32."""
+    for n in (1, 3, 7, 15, 31, 63, 127, 255, 511, 1023):
+        for axis in range(d):
+            for fp64 in (True, False):
+                g = pass_geo(d, n, axis, fp64, MAX_LDS_BLOCK - STATIC_LDS)
+                assert g["blocks"] * g["L"] < 2 ** 32
+                assert g["stride"] < 2 ** 32 and g["nlines"] <= g["blocks"] * g["L"]
+
+
 def xcd_block(i, nb, xcd=8):
     x, q = i % xcd, i // xcd
     base, rem = nb // xcd, nb % xcd
