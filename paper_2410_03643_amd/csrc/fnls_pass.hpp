@@ -204,9 +204,8 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
     __shared__ double s_wn[kCgs ? 16 : 1];
     // FP64 IN_CGS: w and the first basis vector are read before the totals
     // are reduced (a barrier does not wait for global loads, so they are in
-    // flight during the reduction).  On the contiguous axis, where the pass
-    // runs, the element map needs no per-line set-up; on a strided axis the
-    // load phase reads them after the set-up.
+    // flight during the reduction), with the element map formed before the
+    // per-line set-up.
     constexpr bool kCgs64 = kCgs && sizeof(R) == 8;
     constexpr int kCq = kCgs64 ? kMaxEptLine : 1;
     long long cg_gq[kCq];
@@ -218,8 +217,8 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
 #pragma unroll
         for (int q = 0; q < kCq; ++q) t[q] = cg_gq[q] >= 0 ? src[cg_gq[q]] : czero<C>();
     };
-    auto cg_first_loads = [&]() {
-        const ElemCtx ec = elem_ctx();
+    if constexpr (kCgs64) {
+        const ElemCtx ec = elem_ctx_direct();
 #pragma unroll
         for (int q = 0; q < kCq; ++q) {
             const Elem el = elem(ec, q);
@@ -233,9 +232,6 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
             }
         }
         cg_load_vec(0, cg_ta);
-    };
-    if constexpr (kCgs64) {
-        if (contiguous) cg_first_loads();
     }
     if constexpr (kCgs) {
         const int nv = basis_j + 1;
@@ -348,7 +344,6 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk_in) {
             // current one is applied (measured faster for FP64 only; complex64
             // bases take the per-element loop below).
             const double2* s_coef = s_cgs + (kMaxRestart + 2);
-            if (!contiguous) cg_first_loads();
             auto apply_vec = [&](int i, const C* t) {
                 const double2 c = s_coef[i];
 #pragma unroll
