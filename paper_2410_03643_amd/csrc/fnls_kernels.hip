@@ -367,14 +367,21 @@ __device__ __forceinline__ void finish_body(const StreamArgs& a) {
         __shared__ double2 s_col[kMaxRestart + 1];
         __shared__ double2 s_sn[kMaxRestart];
         __shared__ double s_cs[kMaxRestart];
+        // earlier columns of R (packed), g, sigma and y for the finish
+        __shared__ double2 s_Rt[kMaxRestart * (kMaxRestart + 1) / 2];
+        __shared__ double2 s_g[kMaxRestart + 1];
+        __shared__ double s_sig[kMaxRestart + 1];
+        __shared__ double2 s_y[kMaxRestart];
         const int j = st->j;
         for (int i = threadIdx.x; i <= j; i += blockDim.x) s_col[i] = st->hcol[i];
         for (int i = threadIdx.x; i < j; i += blockDim.x) {
             s_cs[i] = st->cs[i];
             s_sn[i] = st->sn[i];
         }
+        const FinishStage fs{s_Rt, s_g, s_sig, s_y};
+        stage_finish(st, j, fs, s_sig);
         __syncthreads();
-        if (threadIdx.x == 0) arnoldi_finish(st, a.hs, s_tot[0].x, j, s_col, s_cs, s_sn);
+        if (threadIdx.x == 0) arnoldi_finish(st, a.hs, s_tot[0].x, j, s_col, s_cs, s_sn, fs);
         return;
     }
     if (threadIdx.x != 0) return;

@@ -67,15 +67,47 @@ __device__ __forceinline__ double2 ddiv(double2 a, double2 b) {
 }
 __device__ __forceinline__ double dabs(double2 a) { return hypot(a.x, a.y); }
 
+// Where the Arnoldi finish reads the earlier columns of R, the right-hand
+// side g and the basis scales sigma, and keeps y while it back-substitutes:
+// the GMRES state itself (all null), or copies the whole workgroup staged in
+// LDS beforehand (then the one thread that finishes has no global round trip
+// in its serial chain).  Rt packs column l, rows 0..l at l (l + 1) / 2.
+struct FinishStage {
+    double2* Rt;
+    double2* g;
+    const double* sigma;
+    double2* y;
+};
+
+// Stage columns 0..j-1 of R, g_0..g_j and sigma_0..sigma_j in LDS with every
+// thread of the workgroup (a barrier follows before the finish reads them).
+static __device__ void stage_finish(const GmresState* st, int j, FinishStage f, double* sigma) {
+    for (int t = threadIdx.x; t < j * kMaxRestart; t += blockDim.x) {
+        const int l = t / kMaxRestart, i = t - l * kMaxRestart;
+        if (i <= l) f.Rt[l * (l + 1) / 2 + i] = st->R[l][i];
+    }
+    for (int i = threadIdx.x; i <= j; i += blockDim.x) {
+        f.g[i] = st->g[i];
+        sigma[i] = st->sigma[i];
+    }
+}
+
 // Arnoldi step finish (after the second Gram-Schmidt round): new Hessenberg
 // column, Givens rotation, residual estimate, stopping decision, and -- when
 // the cycle stops -- the least-squares solution y and combination
 // coefficients y_i sigma_i.  Rotation convention: c = |a|/r,
 // s = (a/|a|) conj(b)/r, (x, y) -> (c x + s y, -conj(s) x + c y).
 // s_col holds the new Hessenberg column (rows 0..j), s_cs / s_sn the earlier
-// rotations, all staged in LDS by the whole workgroup; one thread runs this.
+// rotations, all staged in LDS by the whole workgroup; fs the rest (or
+// nothing: then they are read from the state); one thread runs this.  The
+// arithmetic and its order are the same either way.
 static __device__ void arnoldi_finish(GmresState* st, HostStatus* hs, double hn2, int j, double2* s_col,
-                               const double* s_cs, const double2* s_sn) {
+                               const double* s_cs, const double2* s_sn, FinishStage fs = FinishStage{}) {
+    const bool staged = fs.Rt != nullptr;
+    auto R_at = [&](int l, int i) -> double2 { return staged ? fs.Rt[l * (l + 1) / 2 + i] : st->R[l][i]; };
+    double2* gv = staged ? fs.g : st->g;
+    const double* sgv = staged ? fs.sigma : st->sigma;
+    double2* yv = staged ? fs.y : st->y;
     const double hn = sqrt(hn2);
     double2* col = s_col;
     for (int i = 0; i < j; ++i) {
@@ -105,11 +137,15 @@ static __device__ void arnoldi_finish(GmresState* st, HostStatus* hs, double hn2
     st->sn[j] = s;
     col[j] = dmk(c * a.x + s.x * hn, c * a.y + s.y * hn);
     for (int i = 0; i <= j; ++i) st->R[j][i] = col[i];
-    const double2 gj = st->g[j];
-    st->g[j + 1] = dmk(-(s.x * gj.x + s.y * gj.y), -(s.x * gj.y - s.y * gj.x));
-    st->g[j] = dmk(c * gj.x, c * gj.y);
+    const double2 gj = gv[j];
+    const double2 gj1 = dmk(-(s.x * gj.x + s.y * gj.y), -(s.x * gj.y - s.y * gj.x));
+    const double2 gjn = dmk(c * gj.x, c * gj.y);
+    st->g[j + 1] = gj1;
+    st->g[j] = gjn;
+    gv[j + 1] = gj1;
+    gv[j] = gjn;
     st->total += 1;
-    const double est = dabs(st->g[j + 1]) / st->refnorm;
+    const double est = dabs(gj1) / st->refnorm;
     st->est = est;
     if (st->total <= 64) st->hist[st->total - 1] = est;
     const int brk = (hn <= 1e-14 * st->wnorm0) ? 1 : 0;
@@ -125,17 +161,22 @@ static __device__ void arnoldi_finish(GmresState* st, HostStatus* hs, double hn2
     if (stop) {
         const int k = j + 1;
         st->k = k;
+        // column j of R is the new one (col); earlier ones come from R
+        auto Rc = [&](int l, int i) -> double2 { return l == j ? col[i] : R_at(l, i); };
         for (int i = k - 1; i >= 0; --i) {
-            double2 acc = st->g[i];
+            double2 acc = gv[i];
             for (int l = i + 1; l < k; ++l) {
-                const double2 rl = st->R[l][i];
-                const double2 yl = st->y[l];
+                const double2 rl = Rc(l, i);
+                const double2 yl = yv[l];
                 acc.x -= rl.x * yl.x - rl.y * yl.y;
                 acc.y -= rl.x * yl.y + rl.y * yl.x;
             }
-            st->y[i] = ddiv(acc, st->R[i][i]);
+            yv[i] = ddiv(acc, Rc(i, i));
         }
-        for (int i = 0; i < k; ++i) st->coef[i] = dmk(st->y[i].x * st->sigma[i], st->y[i].y * st->sigma[i]);
+        for (int i = 0; i < k; ++i) {
+            if (staged) st->y[i] = yv[i];
+            st->coef[i] = dmk(yv[i].x * sgv[i], yv[i].y * sgv[i]);
+        }
         st->active = 0;
     } else {
         st->sigma[j + 1] = 1.0 / hn;
