@@ -230,6 +230,39 @@ def test_restart_and_maxit(torch_dev):
     assert info.status == 1 and info.iters == 3
 
 
+@pytest.mark.parametrize("restart", [64, 30])
+def test_long_cycles_match_oracle(torch_dev, restart):
+    """A weak preconditioner (omega = 0.02, 1-D, n = 1023) takes GMRES over 50
+    iterations: in one cycle of the largest basis (restart 64, where the
+    stopping workgroup back-substitutes a triangle of that size) and across
+    restart boundaries (30).  The iteration count is the oracle's within one,
+    and the solution equals the oracle's after the same number of iterations
+    and restart length."""
+    from paper_2410_03643_amd.fnls import Solver
+    torch, dev = torch_dev
+    n, lo, hi, alpha, rho, dt, om = 1023, -20.0, 20.0, 1.5, 2.0, 0.01, 0.02
+    h = (hi - lo) / (n + 1)
+    u = inputs.soliton(1, n, lo, hi, kx=2.0)
+    s = Solver(alpha, rho, 1, n, h, dt, device=dev, restart=restart)
+    s.precond_setup(torch.from_numpy(u).to(dev), omega=om)
+    o = oracle.OracleSolver(alpha, rho, 1, n, h, dt)
+    o.precond_setup(u, omega=om)
+    b = o.rhs(u)
+    x_t, info = s.solve(torch.from_numpy(b).to(dev), tol=1e-10, restart=restart)
+    x = to_np(x_t)
+    _, io = o.solve(b, tol=1e-10, restart=restart)
+    xf, _ = o.solve(b, restart=restart, fixed_iters=info.iters)
+    res = np.linalg.norm(b - o.apply_A(x)) / np.linalg.norm(b)
+    err = np.linalg.norm(x - xf) / np.linalg.norm(xf)
+    print("restart %d: IT gpu %d (%d cycles) oracle %d | relres %.3e | |x-x_fixed| %.3e"
+          % (restart, info.iters, info.outer_iters, io.iters, res, err), flush=True)
+    assert info.status == 0 and info.iters > 50
+    assert (info.outer_iters == 1) == (restart == 64)
+    assert abs(info.iters - io.iters) <= 1
+    assert res < 1e-10
+    assert err < X_TOL
+
+
 @pytest.mark.parametrize("k", [1, 2, 4])
 def test_fixed_iters_matches_oracle(torch_dev, k):
     torch, dev = torch_dev
