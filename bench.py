@@ -167,18 +167,25 @@ def summarize(dirs, timing_name, kernel_regex):
                 for r in csv.DictReader(fh):
                     per.setdefault((r["Counter_Name"], r["Kernel_Name"]), []).append(float(r["Counter_Value"]))
     if per:
-        lines.append("Counters, KiB per dispatch (mean over dispatches):")
+        lines.append("Counters, KiB per dispatch (mean over the dispatches that did work: a launch")
+        lines.append("enqueued ahead of the solver's stop decision that the device then skipped moves")
+        lines.append("almost nothing and is left out, as counted in the last column):")
         lines.append("")
-        lines.append("| counter | kernel | dispatches | mean KiB |")
-        lines.append("|---|---|---|---|")
+        lines.append("| counter | kernel | dispatches | mean KiB | skipped |")
+        lines.append("|---|---|---|---|---|")
         factors = {}
         for (cn, kn), vals in sorted(per.items()):
+            skipped = 0
             if kn == COPY_KERNEL:
                 # the calibration copies are the large dispatches of the copy kernel
                 vals = [v for v in vals if v >= 0.5 * max(vals)]
-                per[(cn, kn)] = vals
                 factors[cn] = (COPY_BYTES / 1024.0) / (sum(vals) / len(vals))
-            lines.append("| %s | `%s` | %d | %.1f |" % (cn, kn, len(vals), sum(vals) / len(vals)))
+            elif max(vals) > 0:
+                work = [v for v in vals if v >= 0.01 * max(vals)]
+                skipped = len(vals) - len(work)
+                vals = work
+            per[(cn, kn)] = vals
+            lines.append("| %s | `%s` | %d | %.1f | %d |" % (cn, kn, len(vals), sum(vals) / len(vals), skipped))
         lines.append("")
         for cn, fct in sorted(factors.items()):
             lines.append("- %s_copy_factor: %.4f" % (cn.lower(), fct))
